@@ -1,0 +1,132 @@
+/*
+ * kbisim.h — C ABI of the MI355X (gfx950) k-bisimulation refinement library.
+ *
+ * The library computes the partitions P_1..P_k of k-bisimulation on a
+ * multi-relational labeled graph G = (V, E, l_V, l_E)
+ * (Def. multi-relational-labeled-property-graph):
+ *
+ *   P_0:      u ~0 v  iff  l_V(u) = l_V(v)   (vertex label SETS; base case of
+ *             Def. vertex-labeled-bw-bisimulation).  No vertex labels at all
+ *             means P_0 = {V} (initialisation of Alg. schaetzle-alg).
+ *   P_{i+1}:  u ~(i+1) v  iff  u ~i v  and the sets
+ *             { (l_E(e), block_i(w)) : e = (u, w) in E }  are equal
+ *             (step of Def. edge-labeled-fw-bisimulation; the pair set is the
+ *             signature of Def. signature).
+ *
+ * Output block ids are dense and numbered by first vertex: the block holding
+ * vertex 0 is 0, the next block met in vertex order is 1, and so on.  This
+ * replaces the paper's hash-valued ids (Def. id) by a collision-free naming,
+ * so results compare bit-exactly with any other correct implementation.
+ *
+ * Edge semantics: one label per CSR entry (the RDF triple view); parallel
+ * entries and self-loops are allowed; duplicates never matter (set
+ * semantics).  The graph is read as out-edges (forward bisimulation); pass
+ * the transposed CSR for backward bisimulation (Def. inverse-schema-element).
+ *
+ * Conventions
+ *  - Graph arrays, outputs and the workspace are DEVICE pointers on the
+ *    current HIP device.  Counts returned to the caller are HOST memory.
+ *  - The library allocates no device memory: every buffer it uses is carved
+ *    from the caller's workspace (size from kbisim_workspace_bytes).
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *    work is enqueued on it.  A context is bound to one stream and is not
+ *    thread-safe; separate contexts are independent.
+ *  - The caller owns the graph arrays (read-only, they must outlive the
+ *    context), the outputs and the workspace.
+ *  - Return value: 0 on success or a negative KBISIM_E* code.  No C++
+ *    exception crosses this interface.  On error, output contents are
+ *    unspecified.
+ */
+#ifndef KBISIM_H
+#define KBISIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KBISIM_OK 0
+#define KBISIM_EINVAL (-1)    /* null pointer, bad size, k < 0 or k > kmax        */
+#define KBISIM_EGRAPH (-2)    /* graph validation failed (see kbisim_graph)      */
+#define KBISIM_ENOSPACE (-3)  /* workspace smaller than kbisim_workspace_bytes   */
+#define KBISIM_EHIP (-4)      /* HIP runtime error; kbisim_strerror has details */
+#define KBISIM_ERANGE (-5)    /* n >= 2^31 or m >= 2^62                          */
+#define KBISIM_EINTERNAL (-6) /* a device-side consistency check failed          */
+
+/* A labeled graph in CSR form.  All pointers are device pointers.
+ *   n, m        vertices and CSR entries (edges); 0 <= n < 2^31.
+ *   nlabels     number of entries of vlabel when vlabel_ptr is given
+ *               (= vlabel_ptr[n]); ignored otherwise.  Used for workspace
+ *               sizing and validation.
+ *   row_ptr     int64 [n+1]: row_ptr[0] = 0, non-decreasing, row_ptr[n] = m.
+ *   col         int32 [m]: 0 <= col[e] < n, the target of entry e.
+ *   elabel      int32 [m] edge labels >= 0, or NULL: every edge has label 0.
+ *   vlabel_ptr  int64 [n+1] label-set CSR (same rules as row_ptr, ending at
+ *               the number of labels), or NULL: one label per vertex.
+ *   vlabel      int32 labels >= 0: [vlabel_ptr[n]] entries, or [n] when
+ *               vlabel_ptr is NULL.  NULL together with vlabel_ptr == NULL
+ *               means no vertex labels (P_0 = {V}).
+ * Label values need not be dense.  Repeated labels inside one vertex's set
+ * are allowed and count once.                                               */
+typedef struct {
+  int64_t n;
+  int64_t m;
+  int64_t nlabels;
+  const int64_t *row_ptr;
+  const int32_t *col;
+  const int32_t *elabel;
+  const int64_t *vlabel_ptr;
+  const int32_t *vlabel;
+} kbisim_graph;
+
+typedef struct kbisim_ctx kbisim_ctx;
+
+/* Workspace bytes needed by kbisim_create for a graph of g->n vertices,
+ * g->m edges (and g->nlabels set labels) and up to kmax iterations per call.
+ * Reads only these sizes; no HIP call.  Errors: EINVAL (null), ERANGE.      */
+int kbisim_workspace_bytes(const kbisim_graph *g, int kmax, size_t *bytes);
+
+/* Validate the graph, compute P_0 and the static degree schedule, and bind a
+ * context to `stream`.  Synchronises `stream` once (to report validation).
+ * kmax >= 0 bounds k in later calls.  On success *out receives the context.
+ * Errors: EINVAL, ERANGE, ENOSPACE, EGRAPH, EHIP.                           */
+int kbisim_create(const kbisim_graph *g, int kmax, void *workspace, size_t ws_bytes, void *stream,
+                  kbisim_ctx **out);
+
+/* Copy P_0 into out_ids (device int32 [n]) and its block count into
+ * *out_count (host).  Synchronises the stream.                              */
+int kbisim_initial(kbisim_ctx *c, int32_t *out_ids, int64_t *out_count);
+
+/* Compute P_1..P_k starting from P_0.  out_block_ids is a HOST array of k
+ * device pointers, each to int32 [n]; out_block_ids[i] receives P_{i+1}.
+ * out_counts (host, int64 [k]) receives the block counts.  Every iteration
+ * is computed in full, also past the fixpoint (later arrays then repeat).
+ * Enqueues on the context's stream and synchronises once at the end.  k = 0
+ * is a no-op.  Calls are independent: each restarts from P_0.
+ * Errors: EINVAL (k < 0, k > kmax, null output), EINTERNAL, EHIP.           */
+int kbisim_refine(kbisim_ctx *c, int k, int32_t *const *out_block_ids, int64_t *out_counts);
+
+/* As kbisim_refine, but start from a given labelling pid_i (device int32
+ * [n], values >= 0; vertices with equal values form the blocks) instead of
+ * P_0.  Resuming from the P_i of an earlier call reproduces P_{i+1}.. of an
+ * uninterrupted run, since each step depends only on the previous partition
+ * and G.  Errors as kbisim_refine, plus EINVAL for negative pid values.     */
+int kbisim_refine_from(kbisim_ctx *c, const int32_t *pid_i, int k, int32_t *const *out_block_ids,
+                       int64_t *out_counts);
+
+/* Release the context (host memory only; the workspace stays the caller's). */
+int kbisim_destroy(kbisim_ctx *c);
+
+/* Static description of an error code (or of the last HIP error seen). */
+const char *kbisim_strerror(int code);
+
+/* Library version string. */
+const char *kbisim_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KBISIM_H */

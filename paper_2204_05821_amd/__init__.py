@@ -1,0 +1,194 @@
+"""Python binding of libkbisim (k-bisimulation partition refinement on MI355X).
+
+Argument marshalling only: every step of the refinement runs in the HIP
+kernels of ``libkbisim.so`` behind the C ABI of ``include/kbisim.h``.  PyTorch
+provides device memory and the stream.  There is no CPU fallback: importing
+the package without the built library raises.
+
+Quick use::
+
+    import paper_2204_05821_amd as kb
+    ids, counts = kb.refine(row_ptr, col, elabel=elabel, vlabel=vlabel, k=10)
+
+All tensors are device tensors: row_ptr int64 [n+1], col int32 [m], elabel
+int32 [m] or None, vlabel int32 [n] (one label per vertex) or the label-set
+form vlabel_ptr int64 [n+1] + vlabel int32 [nlabels], or None for P0 = {V}.
+The graph is read as out-edges; transpose it first for backward bisimulation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence, Tuple
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkbisim.so")
+
+OK, EINVAL, EGRAPH, ENOSPACE, EHIP, ERANGE, EINTERNAL = 0, -1, -2, -3, -4, -5, -6
+
+
+class KbisimError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        super().__init__(f"{what}: {_lib().kbisim_strerror(code).decode()} ({code})")
+
+
+class _Graph(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int64), ("nlabels", ctypes.c_int64),
+                ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("elabel", ctypes.c_void_p),
+                ("vlabel_ptr", ctypes.c_void_p), ("vlabel", ctypes.c_void_p)]
+
+
+_LIB = None
+
+
+def _lib():
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run paper_2204_05821_amd/build.py (hipcc, gfx950)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_size_t
+    lib.kbisim_workspace_bytes.argtypes = [ctypes.POINTER(_Graph), i32, ctypes.POINTER(sz)]
+    lib.kbisim_create.argtypes = [ctypes.POINTER(_Graph), i32, vp, sz, vp, ctypes.POINTER(vp)]
+    lib.kbisim_initial.argtypes = [vp, vp, ctypes.POINTER(i64)]
+    lib.kbisim_refine.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(i64)]
+    lib.kbisim_refine_from.argtypes = [vp, vp, i32, ctypes.POINTER(vp), ctypes.POINTER(i64)]
+    lib.kbisim_destroy.argtypes = [vp]
+    lib.kbisim_strerror.argtypes = [i32]
+    lib.kbisim_strerror.restype = ctypes.c_char_p
+    lib.kbisim_version.restype = ctypes.c_char_p
+    for f in ("kbisim_workspace_bytes", "kbisim_create", "kbisim_initial", "kbisim_refine", "kbisim_refine_from",
+              "kbisim_destroy"):
+        getattr(lib, f).restype = i32
+    _LIB = lib
+    return lib
+
+
+def version() -> str:
+    return _lib().kbisim_version().decode()
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _check(t: Optional[torch.Tensor], dtype, name: str, device):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or t.dtype != dtype or not t.is_cuda or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous {dtype} device tensor")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+    return t
+
+
+def _stream_handle(stream) -> ctypes.c_void_p:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Refiner:
+    """A context bound to one graph: P0 and the degree schedule are computed once.
+
+    ``refine(k)`` may then be called repeatedly; each call restarts from P0.
+    """
+
+    def __init__(self, row_ptr: torch.Tensor, col: torch.Tensor, elabel: Optional[torch.Tensor] = None,
+                 vlabel: Optional[torch.Tensor] = None, vlabel_ptr: Optional[torch.Tensor] = None,
+                 kmax: int = 10, stream=None):
+        lib = _lib()
+        self.device = row_ptr.device
+        self.row_ptr = _check(row_ptr, torch.int64, "row_ptr", self.device)
+        self.col = _check(col, torch.int32, "col", self.device)
+        self.elabel = _check(elabel, torch.int32, "elabel", self.device)
+        self.vlabel = _check(vlabel, torch.int32, "vlabel", self.device)
+        self.vlabel_ptr = _check(vlabel_ptr, torch.int64, "vlabel_ptr", self.device)
+        self.n = int(row_ptr.numel()) - 1
+        self.m = int(col.numel())
+        self.kmax = int(kmax)
+        nl = int(vlabel.numel()) if (vlabel is not None and vlabel_ptr is not None) else 0
+        self._g = _Graph(self.n, self.m, nl, _ptr(self.row_ptr), _ptr(self.col), _ptr(self.elabel),
+                         _ptr(self.vlabel_ptr), _ptr(self.vlabel))
+        nbytes = ctypes.c_size_t(0)
+        rc = lib.kbisim_workspace_bytes(ctypes.byref(self._g), self.kmax, ctypes.byref(nbytes))
+        if rc:
+            raise KbisimError(rc, "kbisim_workspace_bytes")
+        self.workspace_bytes = int(nbytes.value)
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
+            self.stream = torch.cuda.current_stream() if stream is None else stream
+            ctx = ctypes.c_void_p(0)
+            rc = lib.kbisim_create(ctypes.byref(self._g), self.kmax, _ptr(self.workspace), self.workspace_bytes,
+                                   _stream_handle(self.stream), ctypes.byref(ctx))
+        if rc:
+            raise KbisimError(rc, "kbisim_create")
+        self._ctx = ctx
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            _lib().kbisim_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def initial(self) -> Tuple[torch.Tensor, int]:
+        out = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        cnt = ctypes.c_int64(0)
+        rc = _lib().kbisim_initial(self._ctx, _ptr(out), ctypes.byref(cnt))
+        if rc:
+            raise KbisimError(rc, "kbisim_initial")
+        return out, int(cnt.value)
+
+    def alloc_outputs(self, k: int) -> List[torch.Tensor]:
+        return [torch.empty(self.n, dtype=torch.int32, device=self.device) for _ in range(k)]
+
+    def refine(self, k: int, out: Optional[Sequence[torch.Tensor]] = None,
+               start: Optional[torch.Tensor] = None) -> Tuple[List[torch.Tensor], List[int]]:
+        """P_1..P_k (or P_{i+1}.. from ``start`` = P_i) and their block counts."""
+        if out is None:
+            out = self.alloc_outputs(k)
+        if len(out) < k:
+            raise ValueError("need k output tensors")
+        for t in out[:k]:
+            _check(t, torch.int32, "out", self.device)
+            if t.numel() != self.n:
+                raise ValueError("output tensors must hold n ids")
+        ptrs = (ctypes.c_void_p * max(k, 1))(*[t.data_ptr() for t in out[:k]])
+        counts = (ctypes.c_int64 * max(k, 1))()
+        if start is None:
+            rc = _lib().kbisim_refine(self._ctx, k, ptrs, counts)
+        else:
+            _check(start, torch.int32, "start", self.device)
+            rc = _lib().kbisim_refine_from(self._ctx, _ptr(start), k, ptrs, counts)
+        if rc:
+            raise KbisimError(rc, "kbisim_refine")
+        return list(out[:k]), [int(counts[i]) for i in range(k)]
+
+
+def refine(row_ptr, col, elabel=None, vlabel=None, vlabel_ptr=None, k: int = 10):
+    """One-shot: partitions P_1..P_k and their block counts."""
+    r = Refiner(row_ptr, col, elabel, vlabel, vlabel_ptr, kmax=max(k, 1))
+    try:
+        return r.refine(k)
+    finally:
+        r.close()
+
+
+def to_device(g, device="cuda"):
+    """Device tensors (row_ptr, col, elabel, vlabel, vlabel_ptr) of a host graph with numpy arrays."""
+    def t(a):
+        return None if a is None else torch.from_numpy(a).to(device)
+    return t(g.row_ptr), t(g.col), t(g.elabel), t(g.vlabel), t(g.vlabel_ptr)
+
+
+def refiner_for(g, kmax: int = 10, device="cuda") -> Refiner:
+    rp, col, el, vl, vp = to_device(g, device)
+    return Refiner(rp, col, el, vl, vp, kmax=kmax)

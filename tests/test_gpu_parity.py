@@ -1,0 +1,272 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU reference, bit-exact.
+
+Every test here needs an MI355X and the built libkbisim.so; the library is
+called through its C ABI (ctypes binding), never through a fallback.
+"""
+from __future__ import annotations
+
+import os
+import random
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+from tests import helpers
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _kb():
+    import paper_2204_05821_amd as kb
+    return kb
+
+
+def gpu_all(g, k, kmax=None):
+    """[P0, ..., Pk] (numpy int32) and counts from the GPU library."""
+    kb = _kb()
+    r = kb.refiner_for(g, kmax=max(k, 1) if kmax is None else kmax)
+    p0, c0 = r.initial()
+    ids, counts = r.refine(k)
+    torch.cuda.synchronize()
+    out = [p0.cpu().numpy()] + [t.cpu().numpy() for t in ids]
+    r.close()
+    return out, [c0] + counts
+
+
+def ref_all(g, k):
+    p0, c0 = oracle.initial(g)
+    ids, counts = oracle.refine(g, k)
+    return [p0] + ids, [c0] + counts
+
+
+def assert_same(g, k, label=""):
+    print(f"[parity] {label or g.name} n={g.n} m={g.m} k={k}", flush=True)
+    got, gc = gpu_all(g, k)
+    exp, ec = ref_all(g, k)
+    assert gc == ec, (label, gc, ec)
+    for i, (a, b) in enumerate(zip(got, exp)):
+        if not np.array_equal(a, b):
+            bad = np.nonzero(a != b)[0]
+            raise AssertionError(f"{label}: P{i} differs at {bad[:10]} (of {len(bad)}): got {a[bad[:10]]} want {b[bad[:10]]}")
+
+
+# ------------------------------------------------------------------ worked example
+
+@pytest.mark.parametrize("mode", ["fw", "bw", "schaetzle", "kaushik", "full_fw", "full_bw"])
+def test_paper_example(mode):
+    g = helpers.example_variant(mode)
+    got, gc = gpu_all(g, 3)
+    if mode in helpers.parse_paper_example():
+        for k, expect in helpers.parse_paper_example()[mode].items():
+            assert list(got[k]) == expect
+    assert_same(g, 3, "example-" + mode)
+
+
+# ------------------------------------------------------------------ configurations
+
+def test_tiny_config_k10():
+    """Uniform 10k vertices / 50k edges, 4 vertex and 8 edge labels, k = 1..10."""
+    assert_same(graphgen.tiny(seed=1), 10, "tiny")
+
+
+@pytest.mark.parametrize("seed,avg", [(7, 1.0), (8, 1.5), (9, 2.0)])
+def test_deep_graphs_k10(seed, avg):
+    """Sparse unlabeled graphs that keep refining through k = 10."""
+    g = graphgen.deep(seed=seed, n=20_000, avg_degree=avg)
+    _, counts = ref_all(g, 10)
+    assert counts[10] > counts[3]          # really deep
+    assert_same(g, 10, f"deep{seed}")
+
+
+@pytest.mark.parametrize("scale,m", [(12, 60_000), (14, 200_000), (16, 900_000)])
+def test_rmat_k10(scale, m):
+    assert_same(graphgen.rmat(scale, m, seed=2), 10, f"rmat{scale}")
+
+
+def test_rdf_label_sets():
+    """0-3 type labels per vertex (empty sets included), 1,000 edge labels."""
+    assert_same(graphgen.rmat_rdf(14, 150_000, seed=3), 10, "rdf14")
+
+
+def test_batch_style_graphs():
+    for g_idx in [0, 1, 6, 7]:
+        g = graphgen.batch_graph(g_idx, 5000 + 1000 * g_idx)
+        assert_same(g, 6, f"batch{g_idx}")
+
+
+# ------------------------------------------------------------------ degree tiers
+
+def tier_graph(seed=3, labels=3, shared_targets=50):
+    """Vertices at every tier boundary (0,1,15-17,63-65,511-513,4095-4097, hubs up to 3 chunks),
+    with few labels and targets so rows are full of duplicates, plus twin rows so the
+    large-row exact check finds matches."""
+    rng = np.random.default_rng(seed)
+    degs = [0, 1, 2, 15, 16, 17, 63, 64, 65, 511, 512, 513, 1000, 4095, 4096, 4097, 8191, 8192, 8193, 20000]
+    n_small = 3000
+    n = len(degs) * 2 + n_small
+    src, dst, lbl = [], [], []
+    for i, d in enumerate(degs):
+        a, b = 2 * i, 2 * i + 1            # twins: identical rows (same multiset, shuffled)
+        tg = rng.integers(2 * len(degs), 2 * len(degs) + shared_targets, size=d)
+        lb = rng.integers(0, labels, size=d)
+        perm = rng.permutation(d)
+        src += [a] * d + [b] * d
+        dst += list(tg) + list(tg[perm])
+        lbl += list(lb) + list(lb[perm])
+    base = 2 * len(degs)
+    for v in range(base, n):
+        d = int(rng.integers(0, 5))
+        src += [v] * d
+        dst += list(rng.integers(base, n, size=d))
+        lbl += list(rng.integers(0, labels, size=d))
+    vl = np.zeros(n, dtype=np.int32)
+    vl[base:] = rng.integers(0, 3, size=n - base)
+    return graphgen.from_edges(n, np.array(src), np.array(dst), np.array(lbl), vl, name="tiers")
+
+
+def test_degree_tier_boundaries():
+    g = tier_graph()
+    exp, _ = ref_all(g, 4)
+    # twins must be in the same block in P1 (identical pair sets)
+    for i in range(0, 40, 2):
+        assert exp[1][i] == exp[1][i + 1]
+    assert_same(g, 6, "tiers")
+
+
+def test_degree_tiers_many_labels():
+    assert_same(tier_graph(seed=4, labels=200, shared_targets=3000), 5, "tiers-many")
+
+
+# ------------------------------------------------------------------ hash collisions
+
+@pytest.mark.parametrize("bits", [0, 3, 8])
+def test_forced_collisions_small(bits, monkeypatch):
+    """Truncated hashes make collisions routine; the exact check must keep results exact."""
+    monkeypatch.setenv("KBISIM_DEBUG_HASH_BITS", str(bits))
+    for mode in ["full_fw", "kaushik", "schaetzle"]:
+        assert_same(helpers.example_variant(mode), 3, f"collide{bits}-{mode}")
+    assert_same(graphgen.tiny(seed=2, n=300, m=900), 5, f"collide{bits}-tiny300")
+
+
+@pytest.mark.parametrize("bits", [10, 16, 24])
+def test_forced_collisions_tiny_config(bits, monkeypatch):
+    monkeypatch.setenv("KBISIM_DEBUG_HASH_BITS", str(bits))
+    assert_same(graphgen.tiny(seed=1), 4, f"collide{bits}-tiny")
+
+
+def test_forced_collisions_tiers(monkeypatch):
+    monkeypatch.setenv("KBISIM_DEBUG_HASH_BITS", "6")
+    assert_same(tier_graph(seed=5), 3, "collide-tiers")
+
+
+# ------------------------------------------------------------------ edge cases
+
+def test_empty_and_degenerate_graphs():
+    kb = _kb()
+    cases = [graphgen.from_edges(1, [], []),
+             graphgen.from_edges(1, [0, 0], [0, 0], [1, 1]),
+             graphgen.from_edges(5, [0, 1, 2, 3, 4], [0, 1, 2, 3, 4], [0, 1, 0, 1, 0]),   # self-loops
+             graphgen.from_edges(64, [], [], None, np.arange(64) % 5),                   # m = 0
+             graphgen.from_edges(300, [], [], None, None)]                               # no labels at all
+    for g in cases:
+        assert_same(g, 4, f"degenerate n={g.n} m={g.m}")
+    # n = 0
+    g = graphgen.from_edges(0, [], [])
+    r = kb.refiner_for(g, kmax=3)
+    ids, counts = r.refine(3)
+    assert counts == [0, 0, 0]
+
+
+def test_empty_label_sets_and_repeats():
+    rng = random.Random(3)
+    for _ in range(30):
+        g = helpers.random_small_graph(rng, n_max=40, m_max=120, vlabels_max=4)
+        if g.vlabel is None:
+            continue
+        assert_same(g, 5, "small-random")
+
+
+def test_random_small_graphs_against_brute_force_reference():
+    rng = random.Random(9)
+    for _ in range(40):
+        g = helpers.random_small_graph(rng)
+        if rng.random() < 0.5:
+            g = graphgen.transpose(g)
+        assert_same(g, 6, "brute-sized")
+
+
+def test_repeated_calls_and_epoch_wrap():
+    """More than 15 steps on one context: table epochs wrap and tables are cleared."""
+    kb = _kb()
+    g = graphgen.deep(seed=11, n=5000)
+    exp, ec = ref_all(g, 10)
+    r = kb.refiner_for(g, kmax=10)
+    for rep in range(4):
+        ids, counts = r.refine(10)
+        assert counts == ec[1:]
+        for a, b in zip(ids, exp[1:]):
+            assert np.array_equal(a.cpu().numpy(), b)
+    r.close()
+
+
+def test_refine_from_resume():
+    kb = _kb()
+    g = graphgen.deep(seed=12, n=8000, avg_degree=1.3)
+    exp, ec = ref_all(g, 9)
+    r = kb.refiner_for(g, kmax=9)
+    ids, counts = r.refine(4)
+    start = ids[3].clone()
+    ids2, counts2 = r.refine(5, start=start)
+    for a, b in zip(ids2, exp[5:]):
+        assert np.array_equal(a.cpu().numpy(), b)
+    assert counts2 == ec[5:]
+    # arbitrary (non-canonical) start labels: same partitions as the reference started there
+    lab = torch.from_numpy((exp[2].astype(np.int64) * 7 + 3).astype(np.int32)).cuda()
+    ids3, c3 = r.refine(3, start=lab)
+    ref3, rc3 = oracle.refine(g, 3, start=(exp[2] * 7 + 3).astype(np.int32))
+    assert c3 == rc3
+    for a, b in zip(ids3, ref3):
+        assert np.array_equal(a.cpu().numpy(), b)
+    r.close()
+
+
+def test_vertex_permutation_on_gpu():
+    g = graphgen.rmat(13, 100_000, seed=5)
+    perm = np.random.default_rng(1).permutation(g.n).astype(np.int32)
+    src = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    vl = np.empty(g.n, dtype=np.int32)
+    vl[perm] = g.vlabel
+    h = graphgen.from_edges(g.n, perm[src], perm[g.col], g.elabel, vl)
+    a, _ = gpu_all(g, 5)
+    b, _ = gpu_all(h, 5)
+    for x, y in zip(a, b):
+        assert helpers.as_blocks(x, perm) == helpers.as_blocks(y)
+
+
+# ------------------------------------------------------------------ errors through the ABI
+
+def test_invalid_graphs_rejected():
+    kb = _kb()
+    g = graphgen.tiny(seed=3, n=100, m=400)
+    rp, col, el, vl, _ = kb.to_device(g)
+    bad_rp = rp.clone(); bad_rp[10] = bad_rp[11] + 1          # not monotone
+    bad_col = col.clone(); bad_col[5] = 100                     # out of range
+    bad_el = el.clone(); bad_el[7] = -1                         # negative label
+    bad_vl = vl.clone(); bad_vl[3] = -2
+    for args in [(bad_rp, col, el, vl), (rp, bad_col, el, vl), (rp, col, bad_el, vl), (rp, col, el, bad_vl)]:
+        with pytest.raises(kb.KbisimError) as ei:
+            kb.Refiner(*args, kmax=2)
+        assert ei.value.code == kb.EGRAPH
+    r = kb.Refiner(rp, col, el, vl, kmax=2)
+    with pytest.raises(kb.KbisimError) as ei:
+        r.refine(3)
+    assert ei.value.code == kb.EINVAL
+    neg = torch.full((g.n,), -1, dtype=torch.int32, device=rp.device)
+    with pytest.raises(kb.KbisimError) as ei:
+        r.refine(1, start=neg)
+    assert ei.value.code == kb.EINVAL
+    r.close()
