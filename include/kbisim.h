@@ -109,12 +109,52 @@ int kbisim_initial(kbisim_ctx *c, int32_t *out_ids, int64_t *out_count);
 int kbisim_refine(kbisim_ctx *c, int k, int32_t *const *out_block_ids, int64_t *out_counts);
 
 /* As kbisim_refine, but start from a given labelling pid_i (device int32
- * [n], values >= 0; vertices with equal values form the blocks) instead of
- * P_0.  Resuming from the P_i of an earlier call reproduces P_{i+1}.. of an
- * uninterrupted run, since each step depends only on the previous partition
- * and G.  Errors as kbisim_refine, plus EINVAL for negative pid values.     */
+ * [n], values in [0, n); vertices with equal values form the blocks) instead
+ * of P_0.  Resuming from the P_i of an earlier call reproduces P_{i+1}.. of
+ * an uninterrupted run, since each step depends only on the previous
+ * partition and G.  Errors as kbisim_refine, plus EINVAL for values outside
+ * [0, n).                                                                   */
 int kbisim_refine_from(kbisim_ctx *c, const int32_t *pid_i, int k, int32_t *const *out_block_ids,
                        int64_t *out_counts);
+
+/* ---- tracing and measurement -------------------------------------------- */
+
+/* Kernel kinds reported by the per-kernel profiler. */
+#define KBISIM_K_SIG_RANGE 0   /* signatures of runs of low-degree vertices        */
+#define KBISIM_K_SIG_BLOCK 1   /* signatures, one workgroup per mid-degree vertex  */
+#define KBISIM_K_HUB_STAGE 2   /* hub rows: chunk dedupe and partitioned staging   */
+#define KBISIM_K_HUB_REDUCE 3  /* hub rows: per-partition dedupe and sums          */
+#define KBISIM_K_HUB_FINAL 4   /* hub key hashes (and very large hubs)             */
+#define KBISIM_K_LOOKUP 5      /* representative lookup + small exact checks       */
+#define KBISIM_K_VERIFY 6      /* exact checks of larger rows                      */
+#define KBISIM_K_PEEL 7        /* collision peeling rounds                         */
+#define KBISIM_K_SCAN 8        /* first-vertex numbering scan                      */
+#define KBISIM_K_ASSIGN 9      /* ids of non-representatives                       */
+#define KBISIM_K_FILL 10       /* table clears and counter resets                  */
+#define KBISIM_NKERNELS 11
+
+/* Enable (1) or disable (0) per-kernel timing for later kbisim_refine calls:
+ * every launch is bracketed by HIP events on the context's stream and the
+ * elapsed times are summed per kernel kind.  Enabling resets the sums.      */
+int kbisim_profile_enable(kbisim_ctx *c, int enable);
+
+/* Sums since kbisim_profile_enable: ms[KBISIM_NKERNELS] milliseconds and
+ * launches[KBISIM_NKERNELS] launch counts (host arrays; either may be NULL).
+ * Synchronises the stream.                                                  */
+int kbisim_profile_read(kbisim_ctx *c, double *ms, int64_t *launches);
+
+/* Name of a kernel kind, or NULL. */
+const char *kbisim_kernel_name(int kind);
+
+/* Static degree schedule of the graph rows (host int64 [8]): vertices and
+ * CSR entries in the range tier (degree <= 512), the workgroup tier (<= 4096),
+ * the staged hub tier and the global-set hub tier, in that order.          */
+int kbisim_schedule_info(kbisim_ctx *c, int64_t *info);
+
+/* Plain device-to-device copy of `bytes` bytes (a multiple of 16) with the
+ * library's streaming copy kernel, enqueued on `stream`.  Used to measure
+ * achievable HBM bandwidth and to calibrate hardware byte counters.        */
+int kbisim_copy_probe(void *dst, const void *src, size_t bytes, void *stream);
 
 /* Release the context (host memory only; the workspace stays the caller's). */
 int kbisim_destroy(kbisim_ctx *c);

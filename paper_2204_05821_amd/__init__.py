@@ -58,11 +58,18 @@ def _lib():
     lib.kbisim_refine.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(i64)]
     lib.kbisim_refine_from.argtypes = [vp, vp, i32, ctypes.POINTER(vp), ctypes.POINTER(i64)]
     lib.kbisim_destroy.argtypes = [vp]
+    lib.kbisim_profile_enable.argtypes = [vp, i32]
+    lib.kbisim_profile_read.argtypes = [vp, vp, vp]
+    lib.kbisim_kernel_name.argtypes = [i32]
+    lib.kbisim_kernel_name.restype = ctypes.c_char_p
+    lib.kbisim_schedule_info.argtypes = [vp, vp]
+    lib.kbisim_copy_probe.argtypes = [vp, vp, sz, vp]
     lib.kbisim_strerror.argtypes = [i32]
     lib.kbisim_strerror.restype = ctypes.c_char_p
     lib.kbisim_version.restype = ctypes.c_char_p
     for f in ("kbisim_workspace_bytes", "kbisim_create", "kbisim_initial", "kbisim_refine", "kbisim_refine_from",
-              "kbisim_destroy"):
+              "kbisim_destroy", "kbisim_profile_enable", "kbisim_profile_read", "kbisim_schedule_info",
+              "kbisim_copy_probe"):
         getattr(lib, f).restype = i32
     _LIB = lib
     return lib
@@ -70,6 +77,23 @@ def _lib():
 
 def version() -> str:
     return _lib().kbisim_version().decode()
+
+
+NKERNELS = 11
+
+
+def kernel_names() -> List[str]:
+    return [_lib().kbisim_kernel_name(i).decode() for i in range(NKERNELS)]
+
+
+def copy_probe(dst: torch.Tensor, src: torch.Tensor, stream=None) -> None:
+    """Copy src to dst (same byte size, multiple of 16) with the library's streaming copy kernel."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("size mismatch")
+    rc = _lib().kbisim_copy_probe(_ptr(dst), _ptr(src), nbytes, _stream_handle(stream))
+    if rc:
+        raise KbisimError(rc, "kbisim_copy_probe")
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -146,6 +170,30 @@ class Refiner:
         if rc:
             raise KbisimError(rc, "kbisim_initial")
         return out, int(cnt.value)
+
+    def profile(self, enable: bool = True) -> None:
+        """Start (and reset) or stop per-kernel event timing of later refine calls."""
+        rc = _lib().kbisim_profile_enable(self._ctx, 1 if enable else 0)
+        if rc:
+            raise KbisimError(rc, "kbisim_profile_enable")
+
+    def profile_read(self):
+        """{kernel name: (total ms, launches)} since profile(True)."""
+        ms = (ctypes.c_double * NKERNELS)()
+        cnt = (ctypes.c_int64 * NKERNELS)()
+        rc = _lib().kbisim_profile_read(self._ctx, ms, cnt)
+        if rc:
+            raise KbisimError(rc, "kbisim_profile_read")
+        return {name: (float(ms[i]), int(cnt[i])) for i, name in enumerate(kernel_names())}
+
+    def schedule_info(self):
+        """Vertices and CSR entries per degree tier (range, workgroup, staged hub, global-set hub)."""
+        info = (ctypes.c_int64 * 8)()
+        rc = _lib().kbisim_schedule_info(self._ctx, info)
+        if rc:
+            raise KbisimError(rc, "kbisim_schedule_info")
+        names = ["range", "workgroup", "hub", "hub_global"]
+        return {names[i]: {"vertices": int(info[2 * i]), "entries": int(info[2 * i + 1])} for i in range(4)}
 
     def alloc_outputs(self, k: int) -> List[torch.Tensor]:
         return [torch.empty(self.n, dtype=torch.int32, device=self.device) for _ in range(k)]

@@ -39,11 +39,12 @@ uint64_t pow2_at_least(uint64_t x) {
 }
 
 struct Plan {
-  size_t off_H, off_DC, off_rep, off_p0, off_vlist, off_clA, off_clB, off_lw, off_lb, off_lh;
-  size_t off_table, off_ctable, off_hubv, off_hacc, off_hcnt, off_hoff, off_hsize, off_hdeg, off_chunks;
-  size_t off_status, off_counters, off_dcounts, off_err, off_hubsets;
+  size_t off_H, off_DC, off_rep, off_p0, off_vlist, off_clA, off_clB, off_ranges, off_lists, off_gcol, off_rank,
+      off_gpid;
+  size_t off_table, off_ctable, off_hacc, off_hcnt, off_chunks, off_parts, off_gchunks, off_poff;
+  size_t off_status, off_counters, off_dcounts, off_err, off_stats, off_hubsets, off_zrep;
   uint64_t tslots;
-  int64_t nhub_max, nchunk_max, ntiles, hubset_slots;
+  int64_t max_ranges, max_lists, nhub_max, nchunk_max, npart_max, ngchunk_max, npoff_max, ntiles, hubset_slots;
   int ncounter_steps;
   size_t total;
 };
@@ -59,8 +60,18 @@ Plan make_plan(int64_t n, int64_t m, int64_t nl, int kmax) {
   const size_t N = (size_t)std::max<int64_t>(n, 1);
   const int64_t big = std::max<int64_t>(std::max<int64_t>(m, nl), 1);
   p.tslots = pow2_at_least(2 * (uint64_t)N);
-  p.nhub_max = big / BLOCK_MAX + 1;
+  // A range closes at a hub, when the next row would overflow its entries
+  // (the closed range and that row together hold more than RANGE_EDGES
+  // entries, and each row is "next" once), when full of vertices, or at the end.
+  // Rows above RANGE_EDGES add a range of their own and close the current one.
+  p.max_ranges = big / (RANGE_DMAX + 1) + 2 * big / (RANGE_EDGES + 1) + 2 * big / RANGE_EDGES +
+                 (int64_t)N / RANGE_VERTS + 8;
+  p.max_lists = big / (RANGE_DMAX + 1) + 8;
+  p.nhub_max = big / (BLOCK_MAX + 1) + 1;
   p.nchunk_max = big / HUB_CHUNK + p.nhub_max + 1;
+  p.npart_max = big / (HUB_PART_TARGET / 2) + 2 * p.nhub_max + 1;
+  p.ngchunk_max = big / HUB_GCHUNK + p.nhub_max + 1;
+  p.npoff_max = big / 16 + 4 * (HUB_PMAX + 1) + p.nchunk_max;
   p.ntiles = (int64_t)(N + SCAN_TILE - 1) / SCAN_TILE + 1;
   p.hubset_slots = 2 * big + 64;
   p.ncounter_steps = kmax + 4;
@@ -71,31 +82,39 @@ Plan make_plan(int64_t n, int64_t m, int64_t nl, int kmax) {
   p.off_vlist = take(4 * N);
   p.off_clA = take(4 * N);
   p.off_clB = take(4 * N);
-  p.off_lw = take(4 * N);
-  p.off_lb = take(4 * N);
-  p.off_lh = take(4 * N);
+  p.off_ranges = take(sizeof(Range) * (size_t)p.max_ranges);
+  p.off_gcol = take(4 * (size_t)std::max<int64_t>(m, 1));
+  p.off_rank = take(4 * N);
+  p.off_gpid = take(8 * N);
+  p.off_zrep = take(8 * N);
+  p.off_lists = take(4 * (size_t)p.max_lists);
   p.off_table = take(8 * p.tslots);
   p.off_ctable = take(8 * p.tslots);
-  p.off_hubv = take(4 * (size_t)p.nhub_max);
   p.off_hacc = take(8 * (size_t)p.nhub_max);
   p.off_hcnt = take(4 * (size_t)p.nhub_max);
-  p.off_hoff = take(8 * (size_t)p.nhub_max);
-  p.off_hsize = take(8 * (size_t)p.nhub_max);
-  p.off_hdeg = take(8 * (size_t)p.nhub_max);
   p.off_chunks = take(sizeof(HubChunk) * (size_t)p.nchunk_max);
-  p.off_status = take(8 * (size_t)p.ntiles);
+  p.off_parts = take(sizeof(HubPart) * (size_t)p.npart_max);
+  p.off_gchunks = take(sizeof(HubGChunk) * (size_t)p.ngchunk_max);
+  p.off_poff = take(4 * (size_t)p.npoff_max);
+  p.off_status = take(4 * (size_t)p.ntiles);
   p.off_counters = take(4 * (size_t)CNT_STRIDE * (size_t)p.ncounter_steps);
   p.off_dcounts = take(8 * (size_t)p.ncounter_steps);
   p.off_err = take(16);
+  p.off_stats = take(64);
   p.off_hubsets = take(8 * (size_t)p.hubset_slots);
   p.total = at;
   return p;
 }
 
-// Degree schedule of one row structure (graph rows or label-set rows).
+// Static degree schedule of one row structure (graph rows or label-set rows),
+// built on the host at create time; degrees never change across iterations.
 struct Schedule {
-  int nW = 0, nB = 0, nH = 0, nchunks = 0;
-  int64_t hubset_used = 0;
+  int nranges = 0;      // multi-vertex ranges (at most RANGE_EDGES entries)
+  int nbig = 0;         // single-row ranges of RANGE_EDGES < deg <= RANGE_DMAX
+  int nhub = 0, hub_off = 0;
+  int nchunks = 0, nparts = 0, ngchunks = 0;
+  int64_t gset_begin = 0, gset_end = 0;  // global hash sets of very large hubs
+  int64_t info[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // vertices, entries per tier
 };
 
 }  // namespace
@@ -106,13 +125,25 @@ struct kbisim_ctx {
   hipStream_t stream;
   Plan plan;
   char *ws;
-  u64 *H, *table, *ctable, *hacc, *hubsets, *status;
-  u32 *DC, *hcnt, *err;
-  int *rep, *p0, *vlist, *clA, *clB, *lw, *lb, *lh, *hubv, *counters;
-  int64_t *hoff, *hsize, *hdeg, *dcounts;
+  u64 *H, *table, *ctable, *hacc, *hubsets, *zrep;
+  u32 *DC, *hcnt, *err, *tiles;
+  int *rep, *p0, *vlist, *clA, *clB, *lists, *counters, *poff, *gcol, *rank, *gpid[2];
+  int64_t *dcounts;
+  u64 *stats;
+  Range *ranges;
   HubChunk *chunks;
+  HubPart *parts;
+  HubGChunk *gchunks;
   Schedule sched;      // graph rows
-  u32 epoch = 0, cepoch = 0, hepoch = 0, stamp = 0;
+  // per-kernel profiling
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  struct Pending { int kind; size_t a, b; };
+  std::vector<Pending> ev_pending;  // (kind, start event, end event)
+  double prof_ms[KBISIM_NKERNELS] = {0};
+  int64_t prof_n[KBISIM_NKERNELS] = {0};
+  u32 epoch = 0, cepoch = 0, hepoch = 0, stamp = 0, zepoch = 0;
   u64 hmask = ~0ULL;
   int64_t p0_count = 0;
 };
@@ -134,8 +165,52 @@ int hip_fail(hipError_t e) {
 
 inline unsigned blocks_for(int64_t items, int per) { return (unsigned)((items + per - 1) / per); }
 
+// ---- per-kernel profiling: events around each launch, resolved after syncs.
+hipEvent_t prof_event(kbisim_ctx *c) {
+  if (c->ev_used == c->ev_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    c->ev_pool.push_back(e);
+  }
+  return c->ev_pool[c->ev_used++];
+}
+
+struct ProfScope {
+  kbisim_ctx *c;
+  int kind;
+  size_t start = (size_t)-1;
+  ProfScope(kbisim_ctx *c_, int kind_) : c(c_), kind(kind_) {
+    if (!c->prof) return;
+    hipEvent_t e = prof_event(c);
+    if (!e) return;
+    start = c->ev_used - 1;
+    (void)hipEventRecord(e, c->stream);
+  }
+  ~ProfScope() {
+    if (start == (size_t)-1) return;
+    hipEvent_t e = prof_event(c);
+    if (!e) return;
+    (void)hipEventRecord(e, c->stream);
+    c->ev_pending.push_back({kind, start, c->ev_used - 1});
+  }
+};
+
+// Fold pending event pairs into the sums (the stream must be synchronised).
+void prof_collect(kbisim_ctx *c) {
+  for (auto &p : c->ev_pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->ev_pool[p.a], c->ev_pool[p.b]) == hipSuccess) {
+      c->prof_ms[p.kind] += ms;
+      c->prof_n[p.kind] += 1;
+    }
+  }
+  c->ev_pending.clear();
+  c->ev_used = 0;
+}
+
 int fill_u64(kbisim_ctx *c, u64 *p, int64_t cnt, u64 val) {
   if (cnt <= 0) return 0;
+  ProfScope ps(c, KBISIM_K_FILL);
   unsigned g = (unsigned)std::min<int64_t>(blocks_for(cnt, 256), 65536);
   k_fill_u64<<<g, 256, 0, c->stream>>>(p, cnt, val);
   LAUNCH_CHECK();
@@ -144,6 +219,7 @@ int fill_u64(kbisim_ctx *c, u64 *p, int64_t cnt, u64 val) {
 
 int fill_i32(kbisim_ctx *c, int *p, int64_t cnt, int val) {
   if (cnt <= 0) return 0;
+  ProfScope ps(c, KBISIM_K_FILL);
   unsigned g = (unsigned)std::min<int64_t>(blocks_for(cnt, 256), 65536);
   k_fill_i32<<<g, 256, 0, c->stream>>>(p, cnt, val);
   LAUNCH_CHECK();
@@ -163,7 +239,7 @@ int next_epoch(kbisim_ctx *c, u32 &e, u64 *table) {
 
 int next_hub_epoch(kbisim_ctx *c, const Schedule &s) {
   if (c->hepoch >= 3) {
-    int rc = fill_u64(c, c->hubsets, s.hubset_used, 0);
+    int rc = fill_u64(c, c->hubsets + s.gset_begin, s.gset_end - s.gset_begin, 0);
     if (rc) return rc;
     c->hepoch = 0;
   }
@@ -177,62 +253,180 @@ int read_err(kbisim_ctx *c, u32 *out) {
   return 0;
 }
 
-// Classify rows of `ptr` (NULL: every row has one item) into the wave, block
-// and hub tiers and lay out hub hash sets and chunks.  Synchronises.
+// Build the static schedule of the rows of `ptr` (NULL: every row has one
+// item) on the host: runs of low-degree vertices, the workgroup tier by set
+// size, and hub chunks, partitions and staging areas.  Synchronises.
 int build_schedule(kbisim_ctx *c, const int64_t *ptr, Schedule &s) {
-  const int n = (int)c->g.n;
+  const int64_t n = c->g.n;
   s = Schedule{};
-  int *cnt = c->counters + CNT_STRIDE * (c->plan.ncounter_steps - 1);
-  int rc = fill_i32(c, cnt, CNT_STRIDE, 0);
-  if (rc) return rc;
-  if (n > 0) {
-    k_classify<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, ptr, cnt, c->lw, c->lb, c->lh);
-    LAUNCH_CHECK();
-  }
-  int h_cnt[3] = {0, 0, 0};
-  HIP_TRY(hipMemcpyAsync(h_cnt, cnt, sizeof h_cnt, hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(hipStreamSynchronize(c->stream));
-  s.nW = h_cnt[0];
-  s.nB = h_cnt[1];
-  s.nH = h_cnt[2];
-  if (s.nH > c->plan.nhub_max) return KBISIM_EINTERNAL;
-  if (s.nH > 0) {
-    k_hub_degrees<<<blocks_for(s.nH, 256), 256, 0, c->stream>>>(c->lh, s.nH, ptr, c->hdeg);
-    LAUNCH_CHECK();
-    std::vector<int64_t> deg((size_t)s.nH), off((size_t)s.nH), size((size_t)s.nH);
-    HIP_TRY(hipMemcpyAsync(deg.data(), c->hdeg, 8 * (size_t)s.nH, hipMemcpyDeviceToHost, c->stream));
+  std::vector<int64_t> rp;
+  if (ptr && n > 0) {
+    rp.resize((size_t)n + 1);
+    HIP_TRY(hipMemcpyAsync(rp.data(), ptr, 8 * (size_t)(n + 1), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
-    std::vector<HubChunk> chunks;
-    int64_t at = 0;
-    for (int i = 0; i < s.nH; ++i) {
-      off[(size_t)i] = at;
-      size[(size_t)i] = 2 * deg[(size_t)i];
-      at += size[(size_t)i];
-      for (int64_t b = 0; b < deg[(size_t)i]; b += HUB_CHUNK) {
+  }
+  auto deg = [&](int64_t v) -> int64_t { return ptr ? rp[(size_t)v + 1] - rp[(size_t)v] : 1; };
+  std::vector<Range> ranges;
+  std::vector<int> hubs;
+  int64_t cur0 = -1, cur_e = 0;
+  auto close = [&](int64_t v_end) {
+    if (cur0 >= 0) ranges.push_back(Range{(int)cur0, (int)v_end});
+    cur0 = -1;
+    cur_e = 0;
+  };
+  std::vector<Range> big_ranges;
+  for (int64_t v = 0; v < n; ++v) {
+    const int64_t d = deg(v);
+    if (d > RANGE_DMAX) {
+      close(v);
+      hubs.push_back((int)v);
+      continue;
+    }
+    if (d > RANGE_EDGES) {
+      close(v);
+      big_ranges.push_back(Range{(int)v, (int)v + 1});
+      s.info[2] += 1;
+      s.info[3] += d;
+      continue;
+    }
+    if (cur0 >= 0 && (cur_e + d > RANGE_EDGES || v - cur0 == RANGE_VERTS)) close(v);
+    if (cur0 < 0) cur0 = v;
+    cur_e += d;
+    s.info[0] += 1;
+    s.info[1] += d;
+  }
+  close(n);
+  s.nranges = (int)ranges.size();
+  s.nbig = (int)big_ranges.size();
+  ranges.insert(ranges.end(), big_ranges.begin(), big_ranges.end());
+  // hubs: staged (partitioned) unless very large or out of offset space
+  std::vector<HubChunk> chunks;
+  std::vector<HubPart> parts;
+  std::vector<HubGChunk> gchunks;
+  int64_t stage_at = 0, poff_at = 0;
+  int64_t gset_at = 0;
+  std::vector<int64_t> gsize;
+  std::vector<char> is_staged(hubs.size(), 0);
+  for (size_t i = 0; i < hubs.size(); ++i) {
+    const int64_t d = deg(hubs[i]);
+    const int64_t C = (d + HUB_CHUNK - 1) / HUB_CHUNK;
+    int P = 1;
+    while ((int64_t)P * HUB_PART_TARGET < d && P < HUB_PMAX) P <<= 1;
+    const bool staged = d <= HUB_STAGED_MAX && poff_at + C * (P + 1) <= c->plan.npoff_max;
+    if (staged) {
+      HubPart hp;
+      hp.hub = (int)i;
+      hp.chunk0 = (int)chunks.size();
+      hp.nchunks = (int)C;
+      for (int64_t k = 0; k < C; ++k) {
         HubChunk hc;
-        hc.hub = i;
-        hc.pad = 0;
-        hc.b = b;
-        hc.e = std::min<int64_t>(b + HUB_CHUNK, deg[(size_t)i]);
+        hc.hub = (int)i;
+        hc.parts = P;
+        hc.b = k * HUB_CHUNK;
+        hc.e = std::min<int64_t>(d, (k + 1) * HUB_CHUNK);
+        hc.stage = stage_at;
+        hc.poff = poff_at;
+        stage_at += HUB_CHUNK;
+        poff_at += P + 1;
         chunks.push_back(hc);
       }
+      for (int q = 0; q < P; ++q) {
+        hp.part = q;
+        parts.push_back(hp);
+      }
+      is_staged[i] = 1;
+      s.info[4] += 1;
+      s.info[5] += d;
+    } else {
+      gsize.push_back(2 * d);
+      s.info[6] += 1;
+      s.info[7] += d;
     }
-    if (at > c->plan.hubset_slots || (int64_t)chunks.size() > c->plan.nchunk_max) return KBISIM_EINTERNAL;
-    s.nchunks = (int)chunks.size();
-    s.hubset_used = at;
-    HIP_TRY(hipMemcpyAsync(c->hoff, off.data(), 8 * (size_t)s.nH, hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(hipMemcpyAsync(c->hsize, size.data(), 8 * (size_t)s.nH, hipMemcpyHostToDevice, c->stream));
+  }
+  // global sets follow the staging areas
+  s.gset_begin = stage_at;
+  gset_at = stage_at;
+  size_t gi = 0;
+  for (size_t i = 0; i < hubs.size(); ++i) {
+    const int64_t d = deg(hubs[i]);
+    if (is_staged[i]) continue;
+    const int64_t size = gsize[gi++];
+    for (int64_t b = 0; b < d; b += HUB_GCHUNK) {
+      HubGChunk g;
+      g.hub = (int)i;
+      g.pad = 0;
+      g.b = b;
+      g.e = std::min<int64_t>(d, b + HUB_GCHUNK);
+      g.set_off = gset_at;
+      g.set_size = size;
+      gchunks.push_back(g);
+    }
+    gset_at += size;
+  }
+  s.gset_end = gset_at;
+  if ((int64_t)ranges.size() > c->plan.max_ranges || gset_at > c->plan.hubset_slots ||
+      (int64_t)chunks.size() > c->plan.nchunk_max || (int64_t)parts.size() > c->plan.npart_max ||
+      (int64_t)gchunks.size() > c->plan.ngchunk_max || (int64_t)hubs.size() > c->plan.nhub_max)
+    return KBISIM_EINTERNAL;
+  std::vector<int> lists;
+  s.hub_off = 0;
+  s.nhub = (int)hubs.size();
+  lists.insert(lists.end(), hubs.begin(), hubs.end());
+  if ((int64_t)lists.size() > c->plan.max_lists) return KBISIM_EINTERNAL;
+  s.nchunks = (int)chunks.size();
+  s.nparts = (int)parts.size();
+  s.ngchunks = (int)gchunks.size();
+  if (!ranges.empty())
+    HIP_TRY(hipMemcpyAsync(c->ranges, ranges.data(), sizeof(Range) * ranges.size(), hipMemcpyHostToDevice, c->stream));
+  if (!lists.empty())
+    HIP_TRY(hipMemcpyAsync(c->lists, lists.data(), 4 * lists.size(), hipMemcpyHostToDevice, c->stream));
+  if (!chunks.empty())
     HIP_TRY(hipMemcpyAsync(c->chunks, chunks.data(), sizeof(HubChunk) * chunks.size(), hipMemcpyHostToDevice,
                            c->stream));
-    rc = fill_u64(c, c->hubsets, at, 0);
-    if (rc) return rc;
-    rc = fill_u64(c, c->hacc, s.nH, 0);
-    if (rc) return rc;
-    rc = fill_i32(c, (int *)c->hcnt, s.nH, 0);
-    if (rc) return rc;
-    c->hepoch = 0;
-    HIP_TRY(hipStreamSynchronize(c->stream));
+  if (!parts.empty())
+    HIP_TRY(hipMemcpyAsync(c->parts, parts.data(), sizeof(HubPart) * parts.size(), hipMemcpyHostToDevice, c->stream));
+  if (!gchunks.empty())
+    HIP_TRY(hipMemcpyAsync(c->gchunks, gchunks.data(), sizeof(HubGChunk) * gchunks.size(), hipMemcpyHostToDevice,
+                           c->stream));
+  int rc = 0;
+  if (s.nhub) {
+    if ((rc = fill_u64(c, c->hacc, s.nhub, 0))) return rc;
+    if ((rc = fill_i32(c, (int *)c->hcnt, s.nhub, 0))) return rc;
+    if ((rc = fill_u64(c, c->hubsets + s.gset_begin, s.gset_end - s.gset_begin, 0))) return rc;
   }
+  c->hepoch = 0;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return 0;
+}
+
+// Rank vertices by decreasing in-degree (ties by vertex id) and renumber the
+// targets of every CSR entry: gcol[e] = rank[col[e]].  Synchronises.
+int build_rank(kbisim_ctx *c) {
+  const int64_t n = c->g.n, m = c->g.m;
+  if (n == 0) return 0;
+  int *indeg = c->vlist;  // scratch
+  int rc = fill_i32(c, indeg, n, 0);
+  if (rc) return rc;
+  if (m > 0) {
+    k_indegree<<<(unsigned)std::min<int64_t>(blocks_for(m, 256), 1 << 16), 256, 0, c->stream>>>(m, c->g.col, indeg);
+    LAUNCH_CHECK();
+  }
+  std::vector<int> deg((size_t)n), rank((size_t)n);
+  HIP_TRY(hipMemcpyAsync(deg.data(), indeg, 4 * (size_t)n, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  const int KEYS = 1 << 20;
+  std::vector<int64_t> start((size_t)KEYS + 1, 0);
+  for (int64_t v = 0; v < n; ++v) start[(size_t)(KEYS - 1 - std::min(deg[(size_t)v], KEYS - 1)) + 1]++;
+  for (int k = 0; k < KEYS; ++k) start[(size_t)k + 1] += start[(size_t)k];
+  for (int64_t v = 0; v < n; ++v)
+    rank[(size_t)v] = (int)start[(size_t)(KEYS - 1 - std::min(deg[(size_t)v], KEYS - 1))]++;
+  HIP_TRY(hipMemcpyAsync(c->rank, rank.data(), 4 * (size_t)n, hipMemcpyHostToDevice, c->stream));
+  if (m > 0) {
+    k_remap<<<(unsigned)std::min<int64_t>(blocks_for(m, 256), 1 << 16), 256, 0, c->stream>>>(m, c->g.col, c->rank,
+                                                                                          c->gcol);
+    LAUNCH_CHECK();
+  }
+  HIP_TRY(hipStreamSynchronize(c->stream));
   return 0;
 }
 
@@ -241,6 +435,7 @@ template <class Src>
 int peel_round(kbisim_ctx *c, const Src &src, int *in_cnt, int *in_list, int *out_cnt, int *out_list) {
   int rc = next_epoch(c, c->cepoch, c->ctable);
   if (rc) return rc;
+  ProfScope ps(c, KBISIM_K_PEEL);
   k_res_insert<<<RES_GRID, 256, 0, c->stream>>>(in_cnt, in_list, c->H, c->ctable, c->plan.tslots - 1, c->cepoch);
   LAUNCH_CHECK();
   k_res_verify<Src><<<RES_GRID, 256, 0, c->stream>>>(src, in_cnt, in_list, c->H, c->DC, c->ctable,
@@ -255,39 +450,66 @@ int peel_round(kbisim_ctx *c, const Src &src, int *in_cnt, int *in_list, int *ou
 // careful: settle every collision with host-driven peeling rounds.
 template <class Src>
 int run_step(kbisim_ctx *c, const Src &src, const Schedule &s, int *out, int64_t *count_dev, int *cnt,
-             bool careful) {
+             bool careful, int *gpid_next) {
   const int n = (int)c->g.n;
   if (n == 0) return 0;
   const u64 tmask = c->plan.tslots - 1;
   int rc = next_epoch(c, c->epoch, c->table);
   if (rc) return rc;
   const u32 ep = c->epoch;
-  k_sig_small<Src><<<blocks_for(n, 256), 256, 0, c->stream>>>(src, n, c->H, c->DC, c->table, tmask, ep, c->hmask);
-  LAUNCH_CHECK();
-  if (s.nW) {
-    k_sig_wave<Src><<<blocks_for(s.nW, 4), 256, 0, c->stream>>>(src, c->lw, s.nW, c->H, c->DC, c->table, tmask, ep,
-                                                                c->hmask);
+  const u32 zep = ++c->zepoch;
+  if (s.nranges) {
+    ProfScope ps(c, KBISIM_K_SIG_RANGE);
+    k_sig_range<Src, RANGE_EDGES><<<(unsigned)s.nranges, 256, 0, c->stream>>>(src, c->ranges, c->H, c->DC, c->table,
+                                                                              tmask, ep, c->hmask, c->zrep, zep);
     LAUNCH_CHECK();
   }
-  if (s.nB) {
-    k_sig_block<Src><<<(unsigned)s.nB, 256, 0, c->stream>>>(src, c->lb, c->H, c->DC, c->table, tmask, ep, c->hmask);
+  if (s.nbig) {
+    ProfScope ps(c, KBISIM_K_SIG_BLOCK);
+    k_sig_range<Src, 2 * RANGE_EDGES><<<(unsigned)s.nbig, 256, 0, c->stream>>>(src, c->ranges + s.nranges, c->H,
+                                                                               c->DC, c->table, tmask, ep, c->hmask,
+                                                                               c->zrep, zep);
     LAUNCH_CHECK();
   }
-  if (s.nH) {
-    rc = next_hub_epoch(c, s);
-    if (rc) return rc;
-    k_sig_hub<Src><<<(unsigned)s.nchunks, 256, 0, c->stream>>>(src, c->chunks, c->lh, c->hoff, c->hsize, c->hubsets,
-                                                               c->hacc, c->hcnt, c->hepoch);
-    LAUNCH_CHECK();
-    k_hub_final<Src><<<blocks_for(s.nH, 256), 256, 0, c->stream>>>(src, c->lh, s.nH, c->hacc, c->hcnt, c->H, c->DC,
-                                                                   c->table, tmask, ep, c->hmask);
+  if (s.nhub) {
+    const int *hubs = c->lists + s.hub_off;
+    if (s.nchunks) {
+      {
+        ProfScope ps(c, KBISIM_K_HUB_STAGE);
+        k_hub_stage<Src><<<(unsigned)s.nchunks, 256, 0, c->stream>>>(src, c->chunks, hubs, c->hubsets, c->poff,
+                                                                     c->err);
+        LAUNCH_CHECK();
+      }
+      ProfScope ps(c, KBISIM_K_HUB_REDUCE);
+      k_hub_reduce<Src><<<(unsigned)s.nparts, 256, 0, c->stream>>>(c->parts, c->chunks, c->hubsets, c->poff, c->hacc,
+                                                                   c->hcnt, c->err);
+      LAUNCH_CHECK();
+    }
+    if (s.ngchunks) {
+      rc = next_hub_epoch(c, s);
+      if (rc) return rc;
+      ProfScope ps(c, KBISIM_K_HUB_STAGE);
+      k_sig_hub_global<Src><<<(unsigned)s.ngchunks, 256, 0, c->stream>>>(src, c->gchunks, hubs, c->hubsets, c->hacc,
+                                                                         c->hcnt, c->hepoch);
+      LAUNCH_CHECK();
+    }
+    ProfScope ps(c, KBISIM_K_HUB_FINAL);
+    k_hub_final<Src><<<blocks_for(s.nhub, 256), 256, 0, c->stream>>>(src, hubs, s.nhub, c->hacc, c->hcnt, c->H, c->DC,
+                                                                     c->table, tmask, ep, c->hmask, c->zrep, zep);
     LAUNCH_CHECK();
   }
-  k_lookup<Src><<<blocks_for(n, 256), 256, 0, c->stream>>>(src, n, c->H, c->DC, c->table, tmask, ep, c->rep, &cnt[0],
-                                                           c->vlist, &cnt[1], c->clA, c->err);
-  LAUNCH_CHECK();
-  k_verify<Src><<<PERSIST_GRID, 256, 0, c->stream>>>(src, &cnt[0], c->vlist, c->DC, c->rep, &cnt[1], c->clA, c->err);
-  LAUNCH_CHECK();
+  {
+    ProfScope ps(c, KBISIM_K_LOOKUP);
+    k_lookup<Src><<<blocks_for(n, 256), 256, 0, c->stream>>>(src, n, c->H, c->DC, c->table, tmask, ep, c->rep,
+                                                             &cnt[0], c->vlist, &cnt[1], c->clA, c->err, c->zrep, zep);
+    LAUNCH_CHECK();
+  }
+  {
+    ProfScope ps(c, KBISIM_K_VERIFY);
+    k_verify<Src><<<PERSIST_GRID, 256, 0, c->stream>>>(src, &cnt[0], c->vlist, c->DC, c->rep, &cnt[1], c->clA,
+                                                       c->err);
+    LAUNCH_CHECK();
+  }
   rc = peel_round(c, src, &cnt[1], c->clA, &cnt[2], c->clB);
   if (rc) return rc;
   if (careful) {
@@ -297,6 +519,7 @@ int run_step(kbisim_ctx *c, const Src &src, const Schedule &s, int *out, int64_t
       int left = 0;
       HIP_TRY(hipMemcpyAsync(&left, in_cnt, sizeof(int), hipMemcpyDeviceToHost, c->stream));
       HIP_TRY(hipStreamSynchronize(c->stream));
+      prof_collect(c);
       if (left == 0) break;
       if (round > n + 1) return KBISIM_EINTERNAL;
       rc = fill_i32(c, out_cnt, 1, 0);
@@ -307,11 +530,22 @@ int run_step(kbisim_ctx *c, const Src &src, const Schedule &s, int *out, int64_t
       std::swap(in_list, out_list);
     }
   }
-  k_scan<<<blocks_for(n, SCAN_TILE), 256, 0, c->stream>>>(n, c->rep, out, c->status, &cnt[4], count_dev, ++c->stamp,
-                                                           c->err);
-  LAUNCH_CHECK();
-  k_assign<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, c->rep, out);
-  LAUNCH_CHECK();
+  {
+    ProfScope ps(c, KBISIM_K_SCAN);
+    const int ntiles = (int)blocks_for(n, SCAN_TILE);
+    k_tile_count<<<(unsigned)ntiles, 256, 0, c->stream>>>(n, c->rep, c->tiles);
+    LAUNCH_CHECK();
+    k_tile_scan<<<1, 1024, 0, c->stream>>>(ntiles, c->tiles, count_dev);
+    LAUNCH_CHECK();
+    k_scan_write<<<(unsigned)ntiles, 256, 0, c->stream>>>(n, c->rep, c->tiles, out, ((uintptr_t)out & 15) == 0);
+    LAUNCH_CHECK();
+  }
+  {
+    ProfScope ps(c, KBISIM_K_ASSIGN);
+    // label-set steps (P0) need no rank-order copy
+    k_assign<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, c->rep, out, gpid_next ? c->rank : nullptr, gpid_next);
+    LAUNCH_CHECK();
+  }
   return 0;
 }
 
@@ -332,9 +566,11 @@ int refine_impl(kbisim_ctx *c, const int32_t *start, int k, int32_t *const *out,
   rc = fill_i32(c, (int *)c->err, 1, 0);
   if (rc) return rc;
   const int32_t *prev = start ? start : c->p0;
+  k_scatter_rank<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, prev, c->rank, c->gpid[0]);
+  LAUNCH_CHECK();
   for (int i = 0; i < k; ++i) {
-    GraphSrc src{c->g.row_ptr, c->g.col, c->g.elabel, prev};
-    rc = run_step(c, src, c->sched, out[i], &c->dcounts[i], c->counters + CNT_STRIDE * i, false);
+    GraphSrc src{c->g.row_ptr, c->gcol, c->g.elabel, c->gpid[i & 1], prev};
+    rc = run_step(c, src, c->sched, out[i], &c->dcounts[i], c->counters + CNT_STRIDE * i, false, c->gpid[(i + 1) & 1]);
     if (rc) return rc;
     prev = out[i];
   }
@@ -344,23 +580,28 @@ int refine_impl(kbisim_ctx *c, const int32_t *start, int k, int32_t *const *out,
   HIP_TRY(hipMemcpyAsync(counts, c->dcounts, 8 * (size_t)k, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipMemcpyAsync(&err, c->err, sizeof err, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
+  prof_collect(c);
   if (err) return KBISIM_EINTERNAL;
   int first_bad = -1;
   for (int i = 0; i < k; ++i)
     if (hc[(size_t)CNT_STRIDE * i + 2] != 0) { first_bad = i; break; }
   if (first_bad >= 0) {
     prev = first_bad == 0 ? (start ? start : c->p0) : out[first_bad - 1];
+    k_scatter_rank<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, prev, c->rank, c->gpid[first_bad & 1]);
+    LAUNCH_CHECK();
     for (int i = first_bad; i < k; ++i) {
       rc = fill_i32(c, c->counters + CNT_STRIDE * i, CNT_STRIDE, 0);
       if (rc) return rc;
-      GraphSrc src{c->g.row_ptr, c->g.col, c->g.elabel, prev};
-      rc = run_step(c, src, c->sched, out[i], &c->dcounts[i], c->counters + CNT_STRIDE * i, true);
+      GraphSrc src{c->g.row_ptr, c->gcol, c->g.elabel, c->gpid[i & 1], prev};
+      rc = run_step(c, src, c->sched, out[i], &c->dcounts[i], c->counters + CNT_STRIDE * i, true,
+                    c->gpid[(i + 1) & 1]);
       if (rc) return rc;
       prev = out[i];
     }
     HIP_TRY(hipMemcpyAsync(counts, c->dcounts, 8 * (size_t)k, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipMemcpyAsync(&err, c->err, sizeof err, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
+    prof_collect(c);
     if (err) return KBISIM_EINTERNAL;
   }
   return KBISIM_OK;
@@ -416,22 +657,26 @@ int kbisim_create(const kbisim_graph *g, int kmax, void *workspace, size_t ws_by
   c->vlist = (int *)(w + plan.off_vlist);
   c->clA = (int *)(w + plan.off_clA);
   c->clB = (int *)(w + plan.off_clB);
-  c->lw = (int *)(w + plan.off_lw);
-  c->lb = (int *)(w + plan.off_lb);
-  c->lh = (int *)(w + plan.off_lh);
+  c->ranges = (Range *)(w + plan.off_ranges);
+  c->lists = (int *)(w + plan.off_lists);
   c->table = (u64 *)(w + plan.off_table);
   c->ctable = (u64 *)(w + plan.off_ctable);
-  c->hubv = (int *)(w + plan.off_hubv);
   c->hacc = (u64 *)(w + plan.off_hacc);
   c->hcnt = (u32 *)(w + plan.off_hcnt);
-  c->hoff = (int64_t *)(w + plan.off_hoff);
-  c->hsize = (int64_t *)(w + plan.off_hsize);
-  c->hdeg = (int64_t *)(w + plan.off_hdeg);
   c->chunks = (HubChunk *)(w + plan.off_chunks);
-  c->status = (u64 *)(w + plan.off_status);
+  c->parts = (HubPart *)(w + plan.off_parts);
+  c->gchunks = (HubGChunk *)(w + plan.off_gchunks);
+  c->poff = (int *)(w + plan.off_poff);
+  c->tiles = (u32 *)(w + plan.off_status);
+  c->gcol = (int *)(w + plan.off_gcol);
+  c->rank = (int *)(w + plan.off_rank);
+  c->gpid[0] = (int *)(w + plan.off_gpid);
+  c->gpid[1] = c->gpid[0] + std::max<int64_t>(n, 1);
+  c->zrep = (u64 *)(w + plan.off_zrep);
   c->counters = (int *)(w + plan.off_counters);
   c->dcounts = (int64_t *)(w + plan.off_dcounts);
   c->err = (u32 *)(w + plan.off_err);
+  c->stats = (u64 *)(w + plan.off_stats);
   c->hubsets = (u64 *)(w + plan.off_hubsets);
   const char *dbg = getenv("KBISIM_DEBUG_HASH_BITS");
   if (dbg && *dbg) {
@@ -468,7 +713,7 @@ int kbisim_create(const kbisim_graph *g, int kmax, void *workspace, size_t ws_by
   // Fresh state: tables and scan status start empty.
   if ((rc = fill_u64(c, c->table, (int64_t)plan.tslots, 0))) return fail(rc);
   if ((rc = fill_u64(c, c->ctable, (int64_t)plan.tslots, 0))) return fail(rc);
-  if ((rc = fill_u64(c, c->status, plan.ntiles, 0))) return fail(rc);
+  if ((rc = fill_u64(c, c->zrep, std::max<int64_t>(n, 1), ~0ULL))) return fail(rc);
 
   // P0: blocks of equal vertex label sets, numbered by first vertex.
   if (!g->vlabel) {
@@ -481,12 +726,14 @@ int kbisim_create(const kbisim_graph *g, int kmax, void *workspace, size_t ws_by
     if ((rc = fill_i32(c, cnt, CNT_STRIDE, 0))) return fail(rc);
     LabelSrc src{g->vlabel_ptr, g->vlabel};
     int64_t *dcount = c->dcounts + (plan.ncounter_steps - 2);
-    if ((rc = run_step(c, src, ls, c->p0, dcount, cnt, true))) return fail(rc);
+    if ((rc = run_step(c, src, ls, c->p0, dcount, cnt, true, nullptr))) return fail(rc);
     if (hipMemcpyAsync(&c->p0_count, dcount, 8, hipMemcpyDeviceToHost, c->stream) != hipSuccess)
       return fail(KBISIM_EHIP);
     if ((rc = read_err(c, &err))) return fail(rc);
     if (err) return fail(KBISIM_EINTERNAL);
   }
+  // Gather renumbering: rank vertices by decreasing in-degree (ties by id).
+  if ((rc = build_rank(c))) return fail(rc);
   // Static schedule of the graph rows.
   if ((rc = build_schedule(c, g->row_ptr, c->sched))) return fail(rc);
   *out = c;
@@ -514,7 +761,7 @@ int kbisim_refine_from(kbisim_ctx *c, const int32_t *pid_i, int k, int32_t *cons
   if (c->g.n > 0) {
     int rc0 = fill_i32(c, (int *)c->err, 1, 0);
     if (rc0) return rc0;
-    k_validate_vals<<<blocks_for(c->g.n, 256), 256, 0, c->stream>>>(c->g.n, pid_i, -1, c->err, ERR_BAD_PID);
+    k_validate_vals<<<blocks_for(c->g.n, 256), 256, 0, c->stream>>>(c->g.n, pid_i, c->g.n, c->err, ERR_BAD_PID);
     LAUNCH_CHECK();
     u32 err = 0;
     int rc = read_err(c, &err);
@@ -525,7 +772,56 @@ int kbisim_refine_from(kbisim_ctx *c, const int32_t *pid_i, int k, int32_t *cons
 }
 
 int kbisim_destroy(kbisim_ctx *c) {
+  if (c) {
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  }
   delete c;
+  return KBISIM_OK;
+}
+
+int kbisim_profile_enable(kbisim_ctx *c, int enable) {
+  if (!c) return KBISIM_EINVAL;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  prof_collect(c);
+  c->prof = enable != 0;
+  for (int i = 0; i < KBISIM_NKERNELS; ++i) {
+    c->prof_ms[i] = 0.0;
+    c->prof_n[i] = 0;
+  }
+  return KBISIM_OK;
+}
+
+int kbisim_profile_read(kbisim_ctx *c, double *ms, int64_t *launches) {
+  if (!c) return KBISIM_EINVAL;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  prof_collect(c);
+  for (int i = 0; i < KBISIM_NKERNELS; ++i) {
+    if (ms) ms[i] = c->prof_ms[i];
+    if (launches) launches[i] = c->prof_n[i];
+  }
+  return KBISIM_OK;
+}
+
+const char *kbisim_kernel_name(int kind) {
+  static const char *names[KBISIM_NKERNELS] = {"k_sig_range", "k_sig_block", "k_hub_stage", "k_hub_reduce",
+                                               "k_hub_final", "k_lookup",    "k_verify",    "k_res_*",
+                                               "k_scan",      "k_assign",    "k_fill_*"};
+  return (kind >= 0 && kind < KBISIM_NKERNELS) ? names[kind] : nullptr;
+}
+
+int kbisim_schedule_info(kbisim_ctx *c, int64_t *info) {
+  if (!c || !info) return KBISIM_EINVAL;
+  for (int i = 0; i < 8; ++i) info[i] = c->sched.info[i];
+  return KBISIM_OK;
+}
+
+int kbisim_copy_probe(void *dst, const void *src, size_t bytes, void *stream) {
+  if (!dst || !src || bytes % 16) return KBISIM_EINVAL;
+  const int64_t n16 = (int64_t)(bytes / 16);
+  if (n16 == 0) return KBISIM_OK;
+  const unsigned g = (unsigned)std::min<int64_t>((n16 + 255) / 256, 1 << 20);
+  k_copy16<<<g, 256, 0, (hipStream_t)stream>>>((uint4 *)dst, (const uint4 *)src, n16);
+  HIP_TRY(hipGetLastError());
   return KBISIM_OK;
 }
 

@@ -38,18 +38,24 @@ typedef uint32_t u32;
 
 constexpr u64 EMPTY64 = ~0ULL;
 constexpr int WAVE = 64;
-constexpr int SMALL_MAX = 16;      // thread-per-vertex tier
-constexpr int WAVE_MAX = 512;      // wave-per-vertex tier
-constexpr int WAVE_SLOTS = 1024;   // LDS set slots per wave (8 KB)
-constexpr int BLOCK_MAX = 4096;    // workgroup-per-vertex tier
-constexpr int BLOCK_SLOTS = 8192;  // LDS set slots per workgroup (64 KB)
-constexpr int HUB_CHUNK = 8192;    // edges per hub workgroup
-constexpr int SCAN_ITEMS = 16;     // items per thread in the scan
+constexpr int SMALL_MAX = 16;        // inline exact check limit (thread per vertex)
+constexpr int RANGE_EDGES = 2048;    // CSR entries per multi-vertex range workgroup
+constexpr int RANGE_VERTS = 256;     // vertices per range workgroup
+constexpr int RANGE_DMAX = 4096;     // rows above RANGE_EDGES get a range of their own; above this, hubs
+constexpr int BLOCK_MAX = RANGE_DMAX;
+constexpr int BLOCK_SLOTS = 8192;    // LDS set slots for exact checks (64 KB)
+constexpr int HUB_CHUNK = 4096;      // entries per hub staging workgroup (16 per thread)
+constexpr int HUB_U = HUB_CHUNK / 256;
+constexpr int HUB_PMAX = 1024;       // partitions per hub at most
+constexpr int HUB_PART_TARGET = 2048;  // expected entries per hub partition
+constexpr int HUB_PSLOTS = 8192;     // LDS set slots per hub partition workgroup
+constexpr int64_t HUB_STAGED_MAX = (int64_t)HUB_PMAX * 4096;  // larger hubs use a global hash set
+constexpr int HUB_GCHUNK = 8192;     // entries per workgroup in the global-set path
+constexpr int SCAN_ITEMS = 16;       // items per thread in the scan
 constexpr int SCAN_TILE = 256 * SCAN_ITEMS;
 
 // Error bits reported through the workspace error word.
 constexpr u32 ERR_LOOKUP_MISS = 1u;
-constexpr u32 ERR_SPIN = 2u;
 constexpr u32 ERR_VERIFY_OVERFLOW = 4u;
 constexpr u32 ERR_GRAPH_ROWPTR = 16u;
 constexpr u32 ERR_GRAPH_COL = 32u;
@@ -74,7 +80,12 @@ __host__ __device__ inline u64 fmix64(u64 k) {
   return k;
 }
 __device__ inline u64 mix_pair(u64 p) { return fmix64(p ^ 0x9ae16a3b2f90404fULL); }
-__device__ inline u32 set_hash(u64 p) { return (u32)(fmix64(p + 0x2545f4914f6cdd1dULL) >> 32); }
+// Slot position inside LDS hash sets: two 32-bit multiplies and a shift
+// (the sets need spread, not collision resistance; equality is exact).
+__device__ inline u32 set_hash(u64 p) {
+  const u32 h = (u32)p * 0x9E3779B1u ^ ((u32)(p >> 32) + 0x7F4A7C15u) * 0x85EBCA77u;
+  return h ^ (h >> 15);
+}
 __device__ inline u32 part_hash(u64 p) { return (u32)fmix64(p ^ 0x6a09e667f3bcc909ULL); }
 __device__ inline u64 finalize_key(u64 acc, u32 dc, u32 own) {
   return fmix64(acc + fmix64((((u64)own) << 32 | (u64)dc) ^ 0xc2b2ae3d27d4eb4fULL));
@@ -85,16 +96,23 @@ __device__ inline u64 finalize_key(u64 acc, u32 dc, u32 own) {
 // to a 64-bit pair.  GraphSrc is one refinement step: item = CSR entry,
 // pair = (edge label << 31) | previous block of the target.  LabelSrc builds
 // P0: item = one vertex label, pair = the label.
+// Gathers read the previous partition through a renumbered copy: gcol[e] =
+// rank(col[e]) and gpid[rank(w)] = pid[w], where ranks order vertices by
+// decreasing in-degree.  The targets most edges point to then share cache
+// lines, which roughly halves the cost of the per-entry random gather.
 struct GraphSrc {
   const int64_t *row_ptr;
-  const int32_t *col;
+  const int32_t *gcol;    // targets renumbered by in-degree rank
   const int32_t *elabel;  // may be null
-  const int32_t *pid;     // previous partition
+  const int32_t *gpid;    // previous partition in rank order
+  const int32_t *pid;     // previous partition in vertex order
   __device__ inline int64_t begin(int v) const { return row_ptr[v]; }
   __device__ inline int64_t end(int v) const { return row_ptr[v + 1]; }
   __device__ inline u64 pair(int64_t e) const {
-    u32 l = elabel ? (u32)elabel[e] : 0u;
-    return ((u64)l << 31) | (u64)(u32)pid[col[e]];
+    // streamed arrays are read non-temporally so they do not evict the
+    // gather targets from the L2
+    const u32 l = elabel ? (u32)__builtin_nontemporal_load(&elabel[e]) : 0u;
+    return ((u64)l << 31) | (u64)(u32)gpid[__builtin_nontemporal_load(&gcol[e])];
   }
   __device__ inline u32 own(int v) const { return (u32)pid[v]; }
 };
@@ -151,7 +169,10 @@ __device__ inline void table_insert(u64 *table, u64 tmask, u64 h, u32 v, u32 epo
   const u64 want = ((u64)tag << 32) | (u64)v;
   u64 s = h & tmask;
   while (true) {
-    u64 cur = __hip_atomic_load(&table[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // A plain load may return an older value of the slot (empty, or a larger
+    // minimum); every decision taken on it is re-validated by the atomics, so
+    // hot keys are served from the L1 instead of serialising on one L2 line.
+    u64 cur = table[s];
     while ((((u32)(cur >> 32)) & 15u) != epoch) {
       u64 old = atomicCAS(&table[s], cur, want);
       if (old == cur) return;
@@ -177,6 +198,22 @@ __device__ inline int table_lookup(const u64 *table, u64 tmask, u64 h, u32 epoch
   }
 }
 
+// Vertices with an empty signature (no out-edges, or no labels in P0) are
+// grouped exactly by their previous block alone: zrep[block] keeps
+// (~epoch << 32 | min vertex), so entries of older epochs compare larger and
+// are replaced, and no clearing is needed.  No hash and no check involved.
+__device__ inline void zero_insert(u64 *zrep, u32 own, u32 v, u32 zep) {
+  const u64 want = ((u64)(~zep) << 32) | (u64)v;
+  const u64 cur = zrep[own];  // may be stale; atomicMin decides
+  if (cur > want) atomicMin(&zrep[own], want);
+}
+
+__device__ inline void key_insert(u64 *table, u64 tmask, u64 *zrep, u64 h, u32 dc, u32 own, u32 v, u32 epoch,
+                                  u32 zep) {
+  if (dc == 0) zero_insert(zrep, own, v, zep);
+  else table_insert(table, tmask, h, v, epoch);
+}
+
 // ---------------------------------------------------------------- validation
 __global__ void k_validate_rows(int64_t n, int64_t m, const int64_t *__restrict__ ptr, u32 *err, u32 bit) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -197,83 +234,19 @@ __global__ void k_validate_vals(int64_t cnt, const int32_t *__restrict__ vals, i
   if (x < 0 || (upper >= 0 && x >= upper)) atomicOr(err, bit);
 }
 
-// ---------------------------------------------------------------- classification
-// Static degree tiers (degrees never change across iterations).
-__global__ void k_classify(int n, const int64_t *__restrict__ ptr, int *cnt, int *list_w, int *list_b,
-                           int *list_h) {
-  int v = blockIdx.x * blockDim.x + threadIdx.x;
-  bool in = v < n;
-  int64_t d = in ? (ptr ? ptr[v + 1] - ptr[v] : 1) : 0;
-  wave_append(&cnt[0], list_w, in && d > SMALL_MAX && d <= WAVE_MAX, v);
-  wave_append(&cnt[1], list_b, in && d > WAVE_MAX && d <= BLOCK_MAX, v);
-  wave_append(&cnt[2], list_h, in && d > BLOCK_MAX, v);
-}
-
 // ---------------------------------------------------------------- signature tiers
-template <class Src>
-__global__ void __launch_bounds__(256) k_sig_small(Src src, int n, u64 *__restrict__ H, u32 *__restrict__ DC,
-                                                   u64 *table, u64 tmask, u32 epoch, u64 hmask) {
-  __shared__ u64 buf[SMALL_MAX * 256];
-  const int t = threadIdx.x;
-  const int v = blockIdx.x * 256 + t;
-  if (v >= n) return;
-  const int64_t b = src.begin(v), e = src.end(v);
-  if (e - b > SMALL_MAX) return;
-  u64 acc = 0;
-  u32 cnt = 0;
-  for (int64_t i = b; i < e; ++i) {
-    const u64 p = src.pair(i);
-    bool dup = false;
-    for (u32 j = 0; j < cnt; ++j)
-      if (buf[j * 256 + t] == p) { dup = true; break; }
-    if (!dup) {
-      buf[cnt * 256 + t] = p;
-      ++cnt;
-      acc += mix_pair(p);
-    }
-  }
-  const u64 h = finalize_key(acc, cnt, src.own(v)) & hmask;
-  H[v] = h;
-  DC[v] = cnt;
-  table_insert(table, tmask, h, (u32)v, epoch);
-}
+// Range tier: a workgroup takes a run of consecutive vertices of degree <=
+// RANGE_DMAX holding at most RANGE_EDGES entries and RANGE_VERTS vertices.
+// All entries of the run are gathered at once (8 per thread, loads issued
+// before any dependent work, contiguous addresses), then each pair is
+// inserted into its vertex's region of an LDS hash set (2*deg slots at
+// offset 2*row offset); first insertions add the pair's mix to the vertex's
+// accumulator.  Zero-degree vertices cost one row-offset read.
+struct Range {
+  int v0, v1;
+};
 
-template <class Src>
-__global__ void __launch_bounds__(256) k_sig_wave(Src src, const int *__restrict__ list, int count,
-                                                  u64 *__restrict__ H, u32 *__restrict__ DC, u64 *table, u64 tmask,
-                                                  u32 epoch, u64 hmask) {
-  __shared__ u64 sets[4][WAVE_SLOTS];
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int idx = blockIdx.x * 4 + w;
-  u64 *set = sets[w];
-  for (int i = threadIdx.x; i < 4 * WAVE_SLOTS; i += 256) (&sets[0][0])[i] = EMPTY64;
-  __syncthreads();
-  u64 acc = 0;
-  u32 cnt = 0;
-  int v = -1;
-  if (idx < count) {
-    v = list[idx];
-    const int64_t b = src.begin(v), e = src.end(v);
-    for (int64_t i = b + lane; i < e; i += WAVE) {
-      const u64 p = src.pair(i);
-      u32 s = set_hash(p) & (WAVE_SLOTS - 1);
-      while (true) {
-        u64 old = atomicCAS(&set[s], EMPTY64, p);
-        if (old == EMPTY64) { acc += mix_pair(p); ++cnt; break; }
-        if (old == p) break;
-        s = (s + 1) & (WAVE_SLOTS - 1);
-      }
-    }
-  }
-  acc = wave_sum_u64(acc);
-  cnt = wave_sum_u32(cnt);
-  if (v >= 0 && lane == 0) {
-    const u64 h = finalize_key(acc, cnt, src.own(v)) & hmask;
-    H[v] = h;
-    DC[v] = cnt;
-    table_insert(table, tmask, h, (u32)v, epoch);
-  }
-}
+__device__ inline u64 scale_to(u32 a, u64 n) { return __umul64hi(((u64)a) << 32, n); }
 
 __device__ inline void block_reduce_2(u64 &acc, u32 &cnt, u64 *sh_acc, u32 *sh_cnt) {
   acc = wave_sum_u64(acc);
@@ -287,77 +260,371 @@ __device__ inline void block_reduce_2(u64 &acc, u32 &cnt, u64 *sh_acc, u32 *sh_c
   }
 }
 
-template <class Src>
-__global__ void __launch_bounds__(256) k_sig_block(Src src, const int *__restrict__ list, u64 *__restrict__ H,
+// Range tier: a workgroup takes a run of consecutive vertices holding at most
+// EMAX entries and RANGE_VERTS vertices (rows of more than RANGE_EDGES entries
+// form a range of their own, EMAX = 2 * RANGE_EDGES).  All entries are
+// gathered at once (EMAX/256 per thread, loads issued before dependent work,
+// consecutive entries on consecutive lanes), then inserted into their
+// vertex's region of an LDS hash set (2*deg slots at offset 2*row offset);
+// per-vertex sums are formed from the set afterwards.
+template <class Src, int EMAX>
+__global__ void __launch_bounds__(256) k_sig_range(Src src, const Range *__restrict__ ranges, u64 *__restrict__ H,
                                                    u32 *__restrict__ DC, u64 *table, u64 tmask, u32 epoch,
-                                                   u64 hmask) {
-  __shared__ u64 set[BLOCK_SLOTS];
+                                                   u64 hmask, u64 *zrep, u32 zep) {
+  constexpr int U = EMAX / 256;
+  __shared__ u64 set[2 * EMAX];
+  __shared__ u64 acc[RANGE_VERTS];
+  __shared__ u32 cnt[RANGE_VERTS];
+  __shared__ int roff[RANGE_VERTS + 1];
+  __shared__ unsigned char owner[EMAX];
+  __shared__ u32 wmax[4];
   __shared__ u64 sh_acc[4];
   __shared__ u32 sh_cnt[4];
-  for (int i = threadIdx.x; i < BLOCK_SLOTS; i += 256) set[i] = EMPTY64;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const Range rg = ranges[blockIdx.x];
+  const int V = rg.v1 - rg.v0;
+  const bool single = V == 1;
+  const int64_t eb = src.begin(rg.v0);
+  for (int i = t; i <= V; i += 256) roff[i] = (int)(src.begin(rg.v0 + i) - eb);
+  for (int i = t; i < V; i += 256) {
+    acc[i] = 0;
+    cnt[i] = 0;
+  }
+  if (!single)
+    for (int i = t; i < EMAX; i += 256) owner[i] = 0;
   __syncthreads();
-  const int v = list[blockIdx.x];
-  const int64_t b = src.begin(v), e = src.end(v);
+  const int E = roff[V];
+  for (int i = t; i < 2 * E; i += 256) set[i] = EMPTY64;
+  // the row start of every non-empty vertex marks its index; a max-scan then
+  // gives the owner of every entry
+  if (!single)
+    for (int i = t; i < V; i += 256)
+      if (roff[i + 1] > roff[i]) owner[roff[i]] = (unsigned char)i;
+  u64 pr[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int j = t + u * 256;
+    pr[u] = j < E ? src.pair(eb + j) : EMPTY64;
+  }
+  __syncthreads();
+  if (!single) {
+    constexpr int PER = EMAX / 256;
+    u32 run = 0;
+    const int j0 = t * PER;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) run = max(run, (u32)owner[j0 + k]);
+    u32 x = run;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const u32 y = __shfl_up(x, o, WAVE);
+      if (lane >= o) x = max(x, y);
+    }
+    if (lane == 63) wmax[w] = x;
+    __syncthreads();
+    u32 carry = __shfl_up(x, 1, WAVE);
+    if (lane == 0) carry = 0;
+    for (int i = 0; i < w; ++i) carry = max(carry, wmax[i]);
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      carry = max(carry, (u32)owner[j0 + k]);
+      owner[j0 + k] = (unsigned char)carry;
+    }
+    __syncthreads();
+  }
+  if (single) {
+    // one row: thread-local sums, one block reduction
+    u64 a = 0;
+    u32 c = 0;
+    const u32 sz = 2u * (u32)E;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const u64 p = pr[u];
+      if (p == EMPTY64) continue;
+      u32 sl = (u32)scale_to(set_hash(p), sz);
+      while (true) {
+        const u64 old = atomicCAS(&set[sl], EMPTY64, p);
+        if (old == EMPTY64) { a += mix_pair(p); ++c; break; }
+        if (old == p) break;
+        sl = (sl + 1 == sz) ? 0u : sl + 1;
+      }
+    }
+    block_reduce_2(a, c, sh_acc, sh_cnt);
+    if (t == 0) {
+      const int v = rg.v0;
+      const u32 own = src.own(v);
+      const u64 h = finalize_key(a, c, own) & hmask;
+      H[v] = h;
+      DC[v] = c;
+      key_insert(table, tmask, zrep, h, c, own, (u32)v, epoch, zep);
+    }
+    return;
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int j = t + u * 256;
+    if (j < E) {
+      const int lo = owner[j];
+      const u64 p = pr[u];
+      const int base = 2 * roff[lo];
+      const u32 sz = 2u * (u32)(roff[lo + 1] - roff[lo]);
+      u32 sl = (u32)scale_to(set_hash(p), sz);
+      while (true) {
+        const u64 old = atomicCAS(&set[base + sl], EMPTY64, p);
+        if (old == EMPTY64) {
+          atomicAdd(&acc[lo], mix_pair(p));
+          atomicAdd(&cnt[lo], 1u);
+          break;
+        }
+        if (old == p) break;
+        sl = (sl + 1 == sz) ? 0u : sl + 1;
+      }
+    }
+  }
+  __syncthreads();
+  for (int i = t; i < V; i += 256) {
+    const int v = rg.v0 + i;
+    const u32 c = cnt[i];
+    const u32 own = src.own(v);
+    if (c) {
+      const u64 h = finalize_key(acc[i], c, own) & hmask;
+      H[v] = h;
+      table_insert(table, tmask, h, (u32)v, epoch);
+    } else {
+      zero_insert(zrep, own, (u32)v, zep);
+    }
+    DC[v] = c;
+  }
+}
+
+// Hub tier (deg > BLOCK_MAX), two passes without per-entry global atomics.
+//  stage:  a workgroup per chunk of HUB_CHUNK entries removes duplicates
+//          inside the chunk (LDS set), splits the chunk's distinct pairs into
+//          the hub's P partitions by a partition hash and writes them,
+//          grouped by partition, to the chunk's staging area together with
+//          the P+1 partition offsets.
+//  reduce: a workgroup per (hub, partition) reads that partition's segment
+//          of every chunk of the hub, removes duplicates across chunks (LDS
+//          set) and adds its distinct count and mix sum to the hub's totals.
+struct HubChunk {
+  int hub;          // index into the hub arrays
+  int parts;        // partitions of this hub (power of two)
+  int64_t b, e;     // entry range relative to the start of the hub's row
+  int64_t stage;    // offset of the chunk's staging area (HUB_CHUNK slots)
+  int64_t poff;     // offset of the chunk's parts+1 partition offsets
+};
+
+struct HubPart {
+  int hub;
+  int part;
+  int chunk0;       // first chunk of the hub
+  int nchunks;
+};
+
+template <class Src>
+__global__ void __launch_bounds__(256) k_hub_stage(Src src, const HubChunk *__restrict__ chunks,
+                                                   const int *__restrict__ hubs, u64 *__restrict__ stage,
+                                                   int *__restrict__ poff, u32 *err) {
+  __shared__ u64 set[2 * HUB_CHUNK];
+  __shared__ int hist[HUB_PMAX + 1];
+  __shared__ int wtot[4];
+  const HubChunk c = chunks[blockIdx.x];
+  const int P = c.parts;
+  const int64_t row = src.begin(hubs[c.hub]);
+  const int E = (int)(c.e - c.b);
+  for (int i = threadIdx.x; i < 2 * HUB_CHUNK; i += 256) set[i] = EMPTY64;
+  for (int i = threadIdx.x; i <= P; i += 256) hist[i] = 0;
+  u64 pr[HUB_U];
+#pragma unroll
+  for (int u = 0; u < HUB_U; ++u) {
+    const int j = threadIdx.x + u * 256;
+    pr[u] = j < E ? src.pair(row + c.b + j) : EMPTY64;
+  }
+  __syncthreads();
+  int rank[HUB_U];
+#pragma unroll
+  for (int u = 0; u < HUB_U; ++u) {
+    rank[u] = -1;
+    const u64 p = pr[u];
+    if (p == EMPTY64) continue;
+    u32 sl = set_hash(p) & (2 * HUB_CHUNK - 1);
+    while (true) {
+      const u64 old = atomicCAS(&set[sl], EMPTY64, p);
+      if (old == EMPTY64) {
+        rank[u] = atomicAdd(&hist[part_hash(p) & (P - 1)], 1);
+        break;
+      }
+      if (old == p) break;
+      sl = (sl + 1) & (2 * HUB_CHUNK - 1);
+    }
+  }
+  __syncthreads();
+  // exclusive scan of hist[0..P) by the whole workgroup (P <= 1024: 4 per thread)
+  {
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    int v4[4];
+    int sum = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int idx = t * 4 + k;
+      v4[k] = idx < P ? hist[idx] : 0;
+      sum += v4[k];
+    }
+    int x = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(x, o, WAVE);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) wtot[w] = x;
+    __syncthreads();
+    int off = x - sum;
+    for (int i = 0; i < w; ++i) off += wtot[i];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int idx = t * 4 + k;
+      if (idx < P) {
+        hist[idx] = off;
+        poff[c.poff + idx] = off;
+      }
+      off += v4[k];
+    }
+    if (t == 255) poff[c.poff + P] = off;
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < HUB_U; ++u) {
+    if (rank[u] >= 0) {
+      const u64 p = pr[u];
+      stage[c.stage + hist[part_hash(p) & (P - 1)] + rank[u]] = p;
+    }
+  }
+}
+
+template <class Src>
+__global__ void __launch_bounds__(256) k_hub_reduce(const HubPart *__restrict__ parts, const HubChunk *__restrict__ chunks,
+                                                    const u64 *__restrict__ stage, const int *__restrict__ poff,
+                                                    u64 *hub_acc, u32 *hub_cnt, u32 *err) {
+  __shared__ u64 set[HUB_PSLOTS];
+  __shared__ int64_t sbase[HUB_PMAX]; // per chunk: staging position of this partition's segment
+  __shared__ int pre[HUB_PMAX + 1];    // exclusive prefix of segment lengths
+  __shared__ int wtot[4];
+  __shared__ u64 sh_acc[4];
+  __shared__ u32 sh_cnt[4];
+  const HubPart hp = parts[blockIdx.x];
+  const int C = hp.nchunks;
+  for (int i = threadIdx.x; i < HUB_PSLOTS; i += 256) set[i] = EMPTY64;
+  // segment lengths, then an exclusive scan over the (at most 1024) chunks
+  {
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    int len4[4];
+    int sum = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int ci = t * 4 + k;
+      len4[k] = 0;
+      if (ci < C) {
+        const HubChunk c = chunks[hp.chunk0 + ci];
+        const int a = poff[c.poff + hp.part], b = poff[c.poff + hp.part + 1];
+        sbase[ci] = c.stage + a;
+        len4[k] = b - a;
+      }
+      sum += len4[k];
+    }
+    int x = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(x, o, WAVE);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) wtot[w] = x;
+    __syncthreads();
+    int off = x - sum;
+    for (int i = 0; i < w; ++i) off += wtot[i];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int ci = t * 4 + k;
+      if (ci < C) pre[ci] = off;
+      off += len4[k];
+    }
+    if (t == 255) pre[C] = off;
+    __syncthreads();
+  }
+  const int T = pre[C];
   u64 acc = 0;
   u32 cnt = 0;
-  for (int64_t i = b + threadIdx.x; i < e; i += 256) {
-    const u64 p = src.pair(i);
-    u32 s = set_hash(p) & (BLOCK_SLOTS - 1);
-    while (true) {
-      u64 old = atomicCAS(&set[s], EMPTY64, p);
-      if (old == EMPTY64) { acc += mix_pair(p); ++cnt; break; }
-      if (old == p) break;
-      s = (s + 1) & (BLOCK_SLOTS - 1);
+  for (int t0 = 0; t0 < T; t0 += 4 * 256) {
+    u64 pr[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int t = t0 + threadIdx.x + u * 256;
+      pr[u] = EMPTY64;
+      if (t < T) {
+        int lo = 0, hi = C - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (pre[mid] <= t) lo = mid; else hi = mid - 1;
+        }
+        pr[u] = stage[sbase[lo] + (t - pre[lo])];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const u64 p = pr[u];
+      if (p == EMPTY64) continue;
+      u32 sl = set_hash(p) & (HUB_PSLOTS - 1);
+      for (int probes = 0;; ++probes) {
+        if (probes >= HUB_PSLOTS) { atomicOr(err, ERR_VERIFY_OVERFLOW); break; }
+        const u64 old = atomicCAS(&set[sl], EMPTY64, p);
+        if (old == EMPTY64) { acc += mix_pair(p); ++cnt; break; }
+        if (old == p) break;
+        sl = (sl + 1) & (HUB_PSLOTS - 1);
+      }
     }
   }
   block_reduce_2(acc, cnt, sh_acc, sh_cnt);
   if (threadIdx.x == 0) {
-    const u64 h = finalize_key(acc, cnt, src.own(v)) & hmask;
-    H[v] = h;
-    DC[v] = cnt;
-    table_insert(table, tmask, h, (u32)v, epoch);
+    if (acc) atomicAdd(&hub_acc[hp.hub], acc);
+    if (cnt) atomicAdd(&hub_cnt[hp.hub], cnt);
   }
 }
 
-// Hub vertices: the row is split into chunks of HUB_CHUNK entries, one
-// workgroup each.  Workgroups of one hub share a global hash set of 2*deg
-// slots; slot = pair | (epoch << 62), 0 = never used, epochs 1..3.
-struct HubChunk {
-  int hub;     // index into the hub arrays
+// Very large hubs (deg > HUB_STAGED_MAX): workgroups of one hub share a
+// global hash set of 2*deg slots; slot = pair | (epoch << 62), 0 = unused,
+// epochs 1..3.  Pairs are < 2^62.
+struct HubGChunk {
+  int hub;
   int pad;
-  int64_t b, e;  // entry range relative to the start of the hub's row
+  int64_t b, e;      // entry range relative to the start of the hub's row
+  int64_t set_off;   // the hub's global set
+  int64_t set_size;
 };
 
-// floor(a * n / 2^32) for a 32-bit a and any 64-bit n: a slot index in [0, n).
-__device__ inline u64 scale_to(u32 a, u64 n) { return __umul64hi(((u64)a) << 32, n); }
-
 template <class Src>
-__global__ void __launch_bounds__(256) k_sig_hub(Src src, const HubChunk *__restrict__ chunks,
-                                                 const int *__restrict__ hubs, const int64_t *__restrict__ set_off,
-                                                 const int64_t *__restrict__ set_size, u64 *sets,
-                                                 u64 *hub_acc, u32 *hub_cnt, u32 hepoch) {
+__global__ void __launch_bounds__(256) k_sig_hub_global(Src src, const HubGChunk *__restrict__ chunks,
+                                                        const int *__restrict__ hubs, u64 *sets, u64 *hub_acc,
+                                                        u32 *hub_cnt, u32 hepoch) {
   __shared__ u64 sh_acc[4];
   __shared__ u32 sh_cnt[4];
-  const HubChunk c = chunks[blockIdx.x];
-  u64 *set = sets + set_off[c.hub];
-  const u64 size = (u64)set_size[c.hub];
+  const HubGChunk c = chunks[blockIdx.x];
+  u64 *set = sets + c.set_off;
+  const u64 size = (u64)c.set_size;
   const int64_t row = src.begin(hubs[c.hub]);
   u64 acc = 0;
   u32 cnt = 0;
   for (int64_t i = row + c.b + threadIdx.x; i < row + c.e; i += 256) {
     const u64 p = src.pair(i);
     const u64 want = p | ((u64)hepoch << 62);
-    u64 s = scale_to(set_hash(p), size);
+    u64 sl = scale_to(set_hash(p), size);
     while (true) {
-      u64 cur = __hip_atomic_load(&set[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      u64 cur = __hip_atomic_load(&set[sl], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       bool done = false;
       while ((cur >> 62) != (u64)hepoch) {
-        u64 old = atomicCAS(&set[s], cur, want);
+        const u64 old = atomicCAS(&set[sl], cur, want);
         if (old == cur) { acc += mix_pair(p); ++cnt; done = true; break; }
         cur = old;
       }
       if (done || cur == want) break;
-      s = (s + 1 == size) ? 0 : s + 1;
+      sl = (sl + 1 == size) ? 0 : sl + 1;
     }
   }
   block_reduce_2(acc, cnt, sh_acc, sh_cnt);
@@ -370,7 +637,7 @@ __global__ void __launch_bounds__(256) k_sig_hub(Src src, const HubChunk *__rest
 template <class Src>
 __global__ void k_hub_final(Src src, const int *__restrict__ hubs, int nhub, u64 *hub_acc, u32 *hub_cnt,
                             u64 *__restrict__ H, u32 *__restrict__ DC, u64 *table, u64 tmask, u32 epoch,
-                            u64 hmask) {
+                            u64 hmask, u64 *zrep, u32 zep) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nhub) return;
   const int v = hubs[i];
@@ -378,10 +645,11 @@ __global__ void k_hub_final(Src src, const int *__restrict__ hubs, int nhub, u64
   const u32 cnt = hub_cnt[i];
   hub_acc[i] = 0;
   hub_cnt[i] = 0;
-  const u64 h = finalize_key(acc, cnt, src.own(v)) & hmask;
+  const u32 own = src.own(v);
+  const u64 h = finalize_key(acc, cnt, own) & hmask;
   H[v] = h;
   DC[v] = cnt;
-  table_insert(table, tmask, h, (u32)v, epoch);
+  key_insert(table, tmask, zrep, h, cnt, own, (u32)v, epoch, zep);
 }
 
 // ---------------------------------------------------------------- lookup + exact check
@@ -395,12 +663,22 @@ template <class Src>
 __global__ void __launch_bounds__(256) k_lookup(Src src, int n, const u64 *__restrict__ H,
                                                 const u32 *__restrict__ DC, const u64 *table, u64 tmask,
                                                 u32 epoch, int *__restrict__ rep, int *vcount, int *vlist,
-                                                int *ccount, int *clist, u32 *err) {
+                                                int *ccount, int *clist, u32 *err, const u64 *zrep, u32 zep) {
   __shared__ u64 buf[SMALL_MAX * 256];
   const int t = threadIdx.x;
   const int v = blockIdx.x * 256 + t;
   bool to_verify = false, collided = false;
-  if (v < n) {
+  const u32 dcv0 = v < n ? DC[v] : 0u;
+  if (v < n && dcv0 == 0) {
+    // empty signature: exact grouping by previous block
+    const u64 z = zrep[src.own(v)];
+    if ((u32)(z >> 32) != ~zep) {
+      atomicOr(err, ERR_LOOKUP_MISS);
+      rep[v] = v;
+    } else {
+      rep[v] = (int)(u32)z;
+    }
+  } else if (v < n) {
     const int r = table_lookup(table, tmask, H[v], epoch);
     if (r < 0) {
       atomicOr(err, ERR_LOOKUP_MISS);
@@ -582,88 +860,155 @@ __global__ void __launch_bounds__(256) k_res_verify(Src src, const int *__restri
 }
 
 // ---------------------------------------------------------------- numbering
-// Single-pass exclusive scan with decoupled look-back (Merrill and Garland,
-// "Single-pass parallel prefix scan with decoupled look-back", 2016) over the
-// flags "rep[v] == v" in vertex order.  A head's prefix is its dense id; the
-// last tile writes the block count.  Tile status word: value (32 bits) |
-// flag (2 bits: 1 aggregate, 2 inclusive) | stamp (30 bits, unique per scan
-// launch, so the status array needs no clearing).
-__device__ inline u64 pack_status(u32 value, u32 flag, u32 stamp) {
-  return (u64)value | ((u64)flag << 32) | ((u64)stamp << 34);
-}
-
-__global__ void __launch_bounds__(256) k_scan(int n, const int *__restrict__ rep, int *__restrict__ out, u64 *status,
-                                              int *tile_counter, int64_t *count_out, u32 stamp, u32 *err) {
-  __shared__ int sh_tile;
-  __shared__ u32 sh_wsum[4];
-  __shared__ u32 sh_prefix;
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  if (t == 0) sh_tile = atomicAdd(tile_counter, 1);
-  __syncthreads();
-  const int tile = sh_tile;
-  const int64_t base = (int64_t)tile * SCAN_TILE + (int64_t)t * SCAN_ITEMS;
+// Reduce-then-scan over the flags "rep[v] == v" in vertex order (tiles of
+// SCAN_TILE vertices): per-tile head counts, one workgroup scans the tile
+// counts, then every tile numbers its heads.  A head's exclusive prefix is its
+// dense id, so blocks are numbered by their first vertex.  Non-heads get -1
+// here and their representative's id in k_assign.
+__device__ inline u32 tile_flags(int n, const int *__restrict__ rep, int64_t base) {
+  int r[SCAN_ITEMS];
+  if (base + SCAN_ITEMS <= n) {
+    const int4 *p4 = reinterpret_cast<const int4 *>(rep + base);
+#pragma unroll
+    for (int q = 0; q < SCAN_ITEMS / 4; ++q) {
+      const int4 x = p4[q];
+      r[4 * q] = x.x;
+      r[4 * q + 1] = x.y;
+      r[4 * q + 2] = x.z;
+      r[4 * q + 3] = x.w;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; ++j) r[j] = (base + j < n) ? rep[base + j] : -1;
+  }
   u32 bits = 0;
 #pragma unroll
-  for (int j = 0; j < SCAN_ITEMS; ++j) {
-    const int64_t v = base + j;
-    if (v < n && rep[v] == (int)v) bits |= 1u << j;
-  }
-  const u32 mine = __popc(bits);
-  // inclusive wave scan
+  for (int j = 0; j < SCAN_ITEMS; ++j)
+    if (r[j] == (int)(base + j)) bits |= 1u << j;
+  return bits;
+}
+
+// Exclusive block scan (256 threads) of one u32 per thread; returns the
+// thread's prefix and writes the block total to *total.
+__device__ inline u32 block_exclusive_scan(u32 mine, u32 *sh_w, u32 *total) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   u32 x = mine;
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
-    u32 y = __shfl_up(x, o, WAVE);
+    const u32 y = __shfl_up(x, o, WAVE);
     if (lane >= o) x += y;
   }
-  if (lane == 63) sh_wsum[w] = x;
+  if (lane == 63) sh_w[w] = x;
   __syncthreads();
-  u32 wbase = 0;
-  for (int i = 0; i < w; ++i) wbase += sh_wsum[i];
-  const u32 tile_total = sh_wsum[0] + sh_wsum[1] + sh_wsum[2] + sh_wsum[3];
-  const u32 excl_in_tile = wbase + x - mine;
-  if (t == 0) {
-    u32 prefix = 0;
-    if (tile == 0) {
-      __hip_atomic_store(&status[0], pack_status(tile_total, 2u, stamp), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      __hip_atomic_store(&status[tile], pack_status(tile_total, 1u, stamp), __ATOMIC_RELEASE,
-                         __HIP_MEMORY_SCOPE_AGENT);
-      int j = tile - 1;
-      long spins = 0;
-      while (j >= 0) {
-        const u64 s = __hip_atomic_load(&status[j], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-        const u32 f = (u32)(s >> 32) & 3u;
-        if ((u32)(s >> 34) != stamp || f == 0) {
-          if (++spins > (1L << 28)) { atomicOr(err, ERR_SPIN); break; }
-          __builtin_amdgcn_s_sleep(1);
-          continue;
-        }
-        prefix += (u32)s;
-        if (f == 2u) break;
-        --j;
-      }
-      __hip_atomic_store(&status[tile], pack_status(prefix + tile_total, 2u, stamp), __ATOMIC_RELEASE,
-                         __HIP_MEMORY_SCOPE_AGENT);
+  u32 base = 0;
+  for (int i = 0; i < w; ++i) base += sh_w[i];
+  *total = sh_w[0] + sh_w[1] + sh_w[2] + sh_w[3];
+  __syncthreads();
+  return base + x - mine;
+}
+
+__global__ void __launch_bounds__(256) k_tile_count(int n, const int *__restrict__ rep, u32 *__restrict__ tile_sum) {
+  __shared__ u32 sh_w[4];
+  const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+  const u32 mine = __popc(tile_flags(n, rep, base));
+  u32 total;
+  block_exclusive_scan(mine, sh_w, &total);
+  if (threadIdx.x == 0) tile_sum[blockIdx.x] = total;
+}
+
+// One workgroup of 1024 threads: in-place exclusive scan of ntiles counts.
+__global__ void __launch_bounds__(1024) k_tile_scan(int ntiles, u32 *tile_sum, int64_t *count_out) {
+  __shared__ u32 sh_w[16];
+  __shared__ u32 carry;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  if (t == 0) carry = 0;
+  __syncthreads();
+  for (int b0 = 0; b0 < ntiles; b0 += 1024 * 8) {
+    u32 v8[8];
+    u32 sum = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int i = b0 + t * 8 + k;
+      v8[k] = i < ntiles ? tile_sum[i] : 0u;
+      sum += v8[k];
     }
-    sh_prefix = prefix;
-    const int64_t ntiles = ((int64_t)n + SCAN_TILE - 1) / SCAN_TILE;
-    if (tile == ntiles - 1) *count_out = (int64_t)prefix + tile_total;
+    u32 x = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const u32 y = __shfl_up(x, o, WAVE);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) sh_w[w] = x;
+    __syncthreads();
+    u32 off = carry + x - sum;
+    for (int i = 0; i < w; ++i) off += sh_w[i];
+    u32 all = 0;
+    for (int i = 0; i < 16; ++i) all += sh_w[i];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int i = b0 + t * 8 + k;
+      if (i < ntiles) tile_sum[i] = off;
+      off += v8[k];
+    }
+    __syncthreads();
+    if (t == 0) carry += all;
+    __syncthreads();
   }
-  __syncthreads();
-  u32 id = sh_prefix + excl_in_tile;
+  if (t == 0) *count_out = (int64_t)carry;
+}
+
+__global__ void __launch_bounds__(256) k_scan_write(int n, const int *__restrict__ rep, const u32 *__restrict__ tile_pre,
+                                                    int *__restrict__ out, int out_aligned) {
+  __shared__ u32 sh_w[4];
+  const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+  const u32 bits = tile_flags(n, rep, base);
+  u32 total;
+  u32 id = tile_pre[blockIdx.x] + block_exclusive_scan(__popc(bits), sh_w, &total);
+  int o[SCAN_ITEMS];
 #pragma unroll
   for (int j = 0; j < SCAN_ITEMS; ++j) {
-    if (bits & (1u << j)) out[base + j] = (int)id++;
+    o[j] = (bits & (1u << j)) ? (int)id : -1;
+    id += (bits >> j) & 1u;
+  }
+  if (out_aligned && base + SCAN_ITEMS <= n) {
+    int4 *q4 = reinterpret_cast<int4 *>(out + base);
+#pragma unroll
+    for (int q = 0; q < SCAN_ITEMS / 4; ++q) q4[q] = make_int4(o[4 * q], o[4 * q + 1], o[4 * q + 2], o[4 * q + 3]);
+  } else {
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; ++j)
+      if (base + j < n) out[base + j] = o[j];
   }
 }
 
-// Every non-head copies its representative's id (written by k_scan).
-__global__ void k_assign(int n, const int *__restrict__ rep, int *out) {
+// Every non-head copies its representative's id (written by k_scan_write),
+// and the new partition is also written in rank order for the next gather.
+__global__ void k_assign(int n, const int *__restrict__ rep, int *out, const int *__restrict__ rank,
+                         int *__restrict__ gpid_next) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
   const int r = rep[v];
-  if (r != v) out[v] = r >= 0 ? out[r] : -1;
+  int val = out[v];
+  if (r != v) {
+    val = r >= 0 ? out[r] : -1;
+    out[v] = val;
+  }
+  if (rank) gpid_next[rank[v]] = val;
+}
+
+// In-degree histogram, target renumbering and rank-order scatter (create time
+// and the start of each call).
+__global__ void k_indegree(int64_t m, const int *__restrict__ col, int *indeg) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x)
+    atomicAdd(&indeg[col[e]], 1);
+}
+__global__ void k_remap(int64_t m, const int *__restrict__ col, const int *__restrict__ rank, int *__restrict__ gcol) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x)
+    gcol[e] = rank[col[e]];
+}
+__global__ void k_scatter_rank(int n, const int *__restrict__ pid, const int *__restrict__ rank, int *__restrict__ gpid) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n) gpid[rank[v]] = pid[v];
 }
 
 // ---------------------------------------------------------------- utilities
@@ -679,6 +1024,12 @@ __global__ void k_copy_i32(int *dst, const int *src, int64_t cnt) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x)
     dst[i] = src[i];
 }
+// Streaming copy, 16 bytes per thread per step (bandwidth probe).
+__global__ void k_copy16(uint4 *__restrict__ dst, const uint4 *__restrict__ src, int64_t n16) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
 // Degrees of the hub list (for host-side chunking at create time).
 __global__ void k_hub_degrees(const int *hubs, int nhub, const int64_t *ptr, int64_t *deg_out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;

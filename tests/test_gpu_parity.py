@@ -224,10 +224,11 @@ def test_refine_from_resume():
     for a, b in zip(ids2, exp[5:]):
         assert np.array_equal(a.cpu().numpy(), b)
     assert counts2 == ec[5:]
-    # arbitrary (non-canonical) start labels: same partitions as the reference started there
-    lab = torch.from_numpy((exp[2].astype(np.int64) * 7 + 3).astype(np.int32)).cuda()
+    # non-canonical start labels (another numbering of the same blocks): same partitions
+    relab = (g.n - 1 - exp[2]).astype(np.int32)
+    lab = torch.from_numpy(relab).cuda()
     ids3, c3 = r.refine(3, start=lab)
-    ref3, rc3 = oracle.refine(g, 3, start=(exp[2] * 7 + 3).astype(np.int32))
+    ref3, rc3 = oracle.refine(g, 3, start=relab)
     assert c3 == rc3
     for a, b in zip(ids3, ref3):
         assert np.array_equal(a.cpu().numpy(), b)
@@ -268,5 +269,9 @@ def test_invalid_graphs_rejected():
     neg = torch.full((g.n,), -1, dtype=torch.int32, device=rp.device)
     with pytest.raises(kb.KbisimError) as ei:
         r.refine(1, start=neg)
+    assert ei.value.code == kb.EINVAL
+    big = torch.full((g.n,), g.n, dtype=torch.int32, device=rp.device)
+    with pytest.raises(kb.KbisimError) as ei:
+        r.refine(1, start=big)
     assert ei.value.code == kb.EINVAL
     r.close()
