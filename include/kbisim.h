@@ -83,6 +83,18 @@ typedef struct {
 
 typedef struct kbisim_ctx kbisim_ctx;
 
+/* Launch-shape parameters chosen by an autotuner (0 = default).  Results do
+ * not depend on them; only the work split does.
+ *   range_edges      CSR entries per range workgroup: 1024 or 2048 (default)
+ *   hub_chunk        entries per hub staging workgroup: 2048 or 4096 (default)
+ *   hub_part_target  expected entries per hub partition: 1024 or 2048 (default) */
+typedef struct {
+  int range_edges;
+  int hub_chunk;
+  int hub_part_target;
+  int reserved[5];
+} kbisim_tuning;
+
 /* Workspace bytes needed by kbisim_create for a graph of g->n vertices,
  * g->m edges (and g->nlabels set labels) and up to kmax iterations per call.
  * Reads only these sizes; no HIP call.  Errors: EINVAL (null), ERANGE.      */
@@ -94,6 +106,18 @@ int kbisim_workspace_bytes(const kbisim_graph *g, int kmax, size_t *bytes);
  * Errors: EINVAL, ERANGE, ENOSPACE, EGRAPH, EHIP.                           */
 int kbisim_create(const kbisim_graph *g, int kmax, void *workspace, size_t ws_bytes, void *stream,
                   kbisim_ctx **out);
+
+/* As kbisim_create with explicit launch-shape parameters (NULL = defaults).
+ * Errors as kbisim_create, plus EINVAL for unsupported values.              */
+int kbisim_create_tuned(const kbisim_graph *g, int kmax, const kbisim_tuning *tuning, void *workspace,
+                        size_t ws_bytes, void *stream, kbisim_ctx **out);
+
+/* Capture the k-step loop of later kbisim_refine calls as a HIP graph on the
+ * first call for a given (k, outputs, start) and replay it afterwards
+ * (enable = 1), or launch kernels one by one (0, the default).  Needs a
+ * stream other than the null stream; EINVAL otherwise.  Disabled while the
+ * per-kernel profiler is on.                                                */
+int kbisim_use_graphs(kbisim_ctx *c, int enable);
 
 /* Copy P_0 into out_ids (device int32 [n]) and its block count into
  * *out_count (host).  Synchronises the stream.                              */
@@ -116,6 +140,38 @@ int kbisim_refine(kbisim_ctx *c, int k, int32_t *const *out_block_ids, int64_t *
  * [0, n).                                                                   */
 int kbisim_refine_from(kbisim_ctx *c, const int32_t *pid_i, int k, int32_t *const *out_block_ids,
                        int64_t *out_counts);
+
+/* ---- batches ------------------------------------------------------------- */
+
+/* A batch refines many independent graphs with the same launches.  The
+ * caller passes their disjoint union as one kbisim_graph whose column ids are
+ * global (graph g owns vertices [vert_off[g], vert_off[g+1]), and no entry
+ * leaves its graph) and vert_off (HOST int64 [num_graphs + 1], vert_off[0] =
+ * 0, non-decreasing, vert_off[num_graphs] = n).  Each graph gets exactly the
+ * partitions kbisim_refine would give it alone: blocks never span graphs and
+ * ids are numbered by first vertex within each graph.  Vertex labels (either
+ * form) are per vertex of the union; label-set CSR offsets are global.      */
+typedef struct kbisim_batch kbisim_batch;
+
+int kbisim_batch_workspace_bytes(const kbisim_graph *u, int64_t num_graphs, int kmax, size_t *bytes);
+
+/* Validates (including that no entry crosses graphs: EGRAPH) and computes
+ * every graph's P_0 and the schedule of the union.  Synchronises.           */
+int kbisim_batch_create(const kbisim_graph *u, int64_t num_graphs, const int64_t *vert_off, int kmax,
+                        const kbisim_tuning *tuning, void *workspace, size_t ws_bytes, void *stream,
+                        kbisim_batch **out);
+
+/* P_1..P_k of every graph.  out_ids: HOST array of k device pointers, each
+ * int32 [n] in union order holding per-graph ids; out_counts: HOST int64
+ * [num_graphs * k], counts[g * k + i] = number of blocks of graph g in
+ * P_{i+1}.  Synchronises once at the end.                                   */
+int kbisim_batch_refine(kbisim_batch *b, int k, int32_t *const *out_ids, int64_t *out_counts);
+
+/* The context that runs the batch (for kbisim_use_graphs, profiling and
+ * schedule statistics).  It is owned by the batch.                         */
+int kbisim_batch_context(kbisim_batch *b, kbisim_ctx **ctx);
+
+int kbisim_batch_destroy(kbisim_batch *b);
 
 /* ---- tracing and measurement -------------------------------------------- */
 

@@ -41,6 +41,20 @@ class _Graph(ctypes.Structure):
                 ("vlabel_ptr", ctypes.c_void_p), ("vlabel", ctypes.c_void_p)]
 
 
+class Tuning(ctypes.Structure):
+    """Launch-shape parameters (0 = default); results never depend on them."""
+    _fields_ = [("range_edges", ctypes.c_int), ("hub_chunk", ctypes.c_int), ("hub_part_target", ctypes.c_int),
+                ("reserved", ctypes.c_int * 5)]
+
+    def as_dict(self):
+        return {"range_edges": self.range_edges, "hub_chunk": self.hub_chunk,
+                "hub_part_target": self.hub_part_target}
+
+
+def tuning(range_edges: int = 0, hub_chunk: int = 0, hub_part_target: int = 0) -> Tuning:
+    return Tuning(range_edges, hub_chunk, hub_part_target)
+
+
 _LIB = None
 
 
@@ -54,6 +68,15 @@ def _lib():
     vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_size_t
     lib.kbisim_workspace_bytes.argtypes = [ctypes.POINTER(_Graph), i32, ctypes.POINTER(sz)]
     lib.kbisim_create.argtypes = [ctypes.POINTER(_Graph), i32, vp, sz, vp, ctypes.POINTER(vp)]
+    lib.kbisim_create_tuned.argtypes = [ctypes.POINTER(_Graph), i32, ctypes.POINTER(Tuning), vp, sz, vp,
+                                        ctypes.POINTER(vp)]
+    lib.kbisim_use_graphs.argtypes = [vp, i32]
+    lib.kbisim_batch_workspace_bytes.argtypes = [ctypes.POINTER(_Graph), i64, i32, ctypes.POINTER(sz)]
+    lib.kbisim_batch_create.argtypes = [ctypes.POINTER(_Graph), i64, vp, i32, ctypes.POINTER(Tuning), vp, sz, vp,
+                                        ctypes.POINTER(vp)]
+    lib.kbisim_batch_refine.argtypes = [vp, i32, ctypes.POINTER(vp), vp]
+    lib.kbisim_batch_context.argtypes = [vp, ctypes.POINTER(vp)]
+    lib.kbisim_batch_destroy.argtypes = [vp]
     lib.kbisim_initial.argtypes = [vp, vp, ctypes.POINTER(i64)]
     lib.kbisim_refine.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(i64)]
     lib.kbisim_refine_from.argtypes = [vp, vp, i32, ctypes.POINTER(vp), ctypes.POINTER(i64)]
@@ -69,7 +92,8 @@ def _lib():
     lib.kbisim_version.restype = ctypes.c_char_p
     for f in ("kbisim_workspace_bytes", "kbisim_create", "kbisim_initial", "kbisim_refine", "kbisim_refine_from",
               "kbisim_destroy", "kbisim_profile_enable", "kbisim_profile_read", "kbisim_schedule_info",
-              "kbisim_copy_probe"):
+              "kbisim_copy_probe", "kbisim_create_tuned", "kbisim_use_graphs", "kbisim_batch_workspace_bytes",
+              "kbisim_batch_create", "kbisim_batch_refine", "kbisim_batch_context", "kbisim_batch_destroy"):
         getattr(lib, f).restype = i32
     _LIB = lib
     return lib
@@ -123,7 +147,7 @@ class Refiner:
 
     def __init__(self, row_ptr: torch.Tensor, col: torch.Tensor, elabel: Optional[torch.Tensor] = None,
                  vlabel: Optional[torch.Tensor] = None, vlabel_ptr: Optional[torch.Tensor] = None,
-                 kmax: int = 10, stream=None):
+                 kmax: int = 10, stream=None, tuning: Optional[Tuning] = None, graphs: bool = False):
         lib = _lib()
         self.device = row_ptr.device
         self.row_ptr = _check(row_ptr, torch.int64, "row_ptr", self.device)
@@ -144,13 +168,24 @@ class Refiner:
         self.workspace_bytes = int(nbytes.value)
         with torch.cuda.device(self.device):
             self.workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
-            self.stream = torch.cuda.current_stream() if stream is None else stream
+            if stream is None:
+                # graph capture needs a stream of its own (default priority)
+                stream = torch.cuda.Stream(device=self.device) if graphs else torch.cuda.current_stream()
+            self.stream = stream
+            self.tuning = tuning
             ctx = ctypes.c_void_p(0)
-            rc = lib.kbisim_create(ctypes.byref(self._g), self.kmax, _ptr(self.workspace), self.workspace_bytes,
-                                   _stream_handle(self.stream), ctypes.byref(ctx))
+            torch.cuda.current_stream().synchronize()
+            rc = lib.kbisim_create_tuned(ctypes.byref(self._g), self.kmax,
+                                         ctypes.byref(tuning) if tuning is not None else None,
+                                         _ptr(self.workspace), self.workspace_bytes, _stream_handle(self.stream),
+                                         ctypes.byref(ctx))
         if rc:
             raise KbisimError(rc, "kbisim_create")
         self._ctx = ctx
+        if graphs:
+            rc = lib.kbisim_use_graphs(self._ctx, 1)
+            if rc:
+                raise KbisimError(rc, "kbisim_use_graphs")
 
     def close(self):
         if getattr(self, "_ctx", None):
@@ -240,3 +275,155 @@ def to_device(g, device="cuda"):
 def refiner_for(g, kmax: int = 10, device="cuda") -> Refiner:
     rp, col, el, vl, vp = to_device(g, device)
     return Refiner(rp, col, el, vl, vp, kmax=kmax)
+
+
+class Batch:
+    """Many independent graphs refined by the same launches (their disjoint union).
+
+    ``refine(k)`` returns the k packed id arrays (per-graph ids, union vertex
+    order) and counts as a list of lists ``counts[g][i]``.
+    """
+
+    def __init__(self, row_ptr, col, elabel, vlabel, vlabel_ptr, vert_off, kmax: int = 10, stream=None,
+                 tuning: Optional[Tuning] = None, graphs: bool = False):
+        import numpy as np
+        lib = _lib()
+        self.device = row_ptr.device
+        self.row_ptr = _check(row_ptr, torch.int64, "row_ptr", self.device)
+        self.col = _check(col, torch.int32, "col", self.device)
+        self.elabel = _check(elabel, torch.int32, "elabel", self.device)
+        self.vlabel = _check(vlabel, torch.int32, "vlabel", self.device)
+        self.vlabel_ptr = _check(vlabel_ptr, torch.int64, "vlabel_ptr", self.device)
+        self.vert_off = np.ascontiguousarray(vert_off, dtype=np.int64)
+        self.num_graphs = len(self.vert_off) - 1
+        self.n = int(row_ptr.numel()) - 1
+        self.m = int(col.numel())
+        self.kmax = int(kmax)
+        nl = int(vlabel.numel()) if (vlabel is not None and vlabel_ptr is not None) else 0
+        self._g = _Graph(self.n, self.m, nl, _ptr(self.row_ptr), _ptr(self.col), _ptr(self.elabel),
+                         _ptr(self.vlabel_ptr), _ptr(self.vlabel))
+        nbytes = ctypes.c_size_t(0)
+        rc = lib.kbisim_batch_workspace_bytes(ctypes.byref(self._g), self.num_graphs, self.kmax, ctypes.byref(nbytes))
+        if rc:
+            raise KbisimError(rc, "kbisim_batch_workspace_bytes")
+        self.workspace_bytes = int(nbytes.value)
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
+            if stream is None:
+                stream = torch.cuda.Stream(device=self.device) if graphs else torch.cuda.current_stream()
+            self.stream = stream
+            torch.cuda.current_stream().synchronize()
+            b = ctypes.c_void_p(0)
+            rc = lib.kbisim_batch_create(ctypes.byref(self._g), self.num_graphs,
+                                         ctypes.c_void_p(self.vert_off.ctypes.data), self.kmax,
+                                         ctypes.byref(tuning) if tuning is not None else None,
+                                         _ptr(self.workspace), self.workspace_bytes, _stream_handle(self.stream),
+                                         ctypes.byref(b))
+        if rc:
+            raise KbisimError(rc, "kbisim_batch_create")
+        self._b = b
+        ctx = ctypes.c_void_p(0)
+        lib.kbisim_batch_context(self._b, ctypes.byref(ctx))
+        self._ctx = ctx
+        if graphs:
+            rc = lib.kbisim_use_graphs(self._ctx, 1)
+            if rc:
+                raise KbisimError(rc, "kbisim_use_graphs")
+
+    def close(self):
+        if getattr(self, "_b", None):
+            _lib().kbisim_batch_destroy(self._b)
+            self._b = None
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def alloc_outputs(self, k: int) -> List[torch.Tensor]:
+        return [torch.empty(self.n, dtype=torch.int32, device=self.device) for _ in range(k)]
+
+    def refine(self, k: int, out: Optional[Sequence[torch.Tensor]] = None):
+        if out is None:
+            out = self.alloc_outputs(k)
+        for t in out[:k]:
+            _check(t, torch.int32, "out", self.device)
+            if t.numel() != self.n:
+                raise ValueError("output tensors must hold n ids")
+        ptrs = (ctypes.c_void_p * max(k, 1))(*[t.data_ptr() for t in out[:k]])
+        counts = (ctypes.c_int64 * max(self.num_graphs * k, 1))()
+        rc = _lib().kbisim_batch_refine(self._b, k, ptrs, counts)
+        if rc:
+            raise KbisimError(rc, "kbisim_batch_refine")
+        cl = [[int(counts[g * k + i]) for i in range(k)] for g in range(self.num_graphs)]
+        return list(out[:k]), cl
+
+    def profile(self, enable: bool = True) -> None:
+        rc = _lib().kbisim_profile_enable(self._ctx, 1 if enable else 0)
+        if rc:
+            raise KbisimError(rc, "kbisim_profile_enable")
+
+    def profile_read(self):
+        ms = (ctypes.c_double * NKERNELS)()
+        cnt = (ctypes.c_int64 * NKERNELS)()
+        rc = _lib().kbisim_profile_read(self._ctx, ms, cnt)
+        if rc:
+            raise KbisimError(rc, "kbisim_profile_read")
+        return {name: (float(ms[i]), int(cnt[i])) for i, name in enumerate(kernel_names())}
+
+
+def union_of(graphs):
+    """Disjoint union of host graphs (numpy CSR): global column ids and vertex offsets.
+
+    Returns (row_ptr, col, elabel, vlabel, vlabel_ptr, vert_off) as numpy arrays.
+    All graphs must use the same label form (edge labels or none; one label per
+    vertex, label sets, or none).
+    """
+    import numpy as np
+    vert_off = np.zeros(len(graphs) + 1, dtype=np.int64)
+    for i, g in enumerate(graphs):
+        vert_off[i + 1] = vert_off[i] + g.n
+    edge_off = np.zeros(len(graphs) + 1, dtype=np.int64)
+    for i, g in enumerate(graphs):
+        edge_off[i + 1] = edge_off[i] + g.m
+    row_ptr = np.concatenate([g.row_ptr[:-1] + edge_off[i] for i, g in enumerate(graphs)] + [edge_off[-1:]])
+    col = np.concatenate([g.col + np.int32(vert_off[i]) for i, g in enumerate(graphs)]).astype(np.int32)
+    # A graph without edge labels is the same as one whose edges all carry
+    # label 0; a graph without vertex labels is the same as one whose
+    # vertices all carry one label (or all the empty set): P0 = {V} either way.
+    if any(g.elabel is not None for g in graphs):
+        elabel = np.concatenate([g.elabel if g.elabel is not None else np.zeros(g.m, dtype=np.int32)
+                                 for g in graphs]).astype(np.int32)
+    else:
+        elabel = None
+    kinds = {("sets" if g.vlabel_ptr is not None else ("one" if g.vlabel is not None else "none")) for g in graphs}
+    vlabel = vlabel_ptr = None
+    if "sets" in kinds:
+        ptrs, labs, base = [], [], 0
+        for g in graphs:
+            if g.vlabel_ptr is not None:
+                p, l = g.vlabel_ptr, g.vlabel
+            elif g.vlabel is not None:
+                p, l = np.arange(g.n + 1, dtype=np.int64), g.vlabel
+            else:
+                p, l = np.zeros(g.n + 1, dtype=np.int64), np.zeros(0, dtype=np.int32)
+            ptrs.append(p[:-1] + base)
+            labs.append(np.asarray(l, dtype=np.int32))
+            base += int(p[-1])
+        vlabel_ptr = np.concatenate(ptrs + [np.array([base], dtype=np.int64)])
+        vlabel = np.concatenate(labs).astype(np.int32)
+    elif "one" in kinds:
+        vlabel = np.concatenate([g.vlabel if g.vlabel is not None else np.zeros(g.n, dtype=np.int32)
+                                 for g in graphs]).astype(np.int32)
+    return (row_ptr.astype(np.int64), col, elabel, vlabel,
+            None if vlabel_ptr is None else vlabel_ptr.astype(np.int64), vert_off)
+
+
+def batch_for(graphs, kmax: int = 10, device="cuda", tuning: Optional[Tuning] = None, graphs_mode: bool = False):
+    rp, col, el, vl, vp, off = union_of(graphs)
+
+    def t(a):
+        return None if a is None else torch.from_numpy(a).to(device)
+    return Batch(t(rp), t(col), t(el), t(vl), t(vp), off, kmax=kmax, tuning=tuning, graphs=graphs_mode)

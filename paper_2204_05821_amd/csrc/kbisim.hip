@@ -2,18 +2,23 @@
 //
 // The engine owns no device memory: kbisim_create carves every buffer from
 // the caller's workspace, validates the graph, computes P0 (vertex label-set
-// equality) and a static degree schedule, and kbisim_refine enqueues k
-// refinement steps on the caller's stream with no host synchronisation
-// inside the loop.  A step that met a hash collision it could not settle in
-// its one in-loop peeling round is detected after the final synchronisation
-// and recomputed, from that step on, with peeling rounds driven by the host.
+// equality), renumbers gather targets by in-degree and builds a static degree
+// schedule; kbisim_refine enqueues k refinement steps on the caller's stream
+// with no host synchronisation inside the loop (and, when enabled, replays
+// the whole loop as a captured HIP graph).  A step that met a hash collision
+// it could not settle in its one in-loop peeling round is detected after the
+// final synchronisation and recomputed, from that step on, with peeling
+// rounds driven by the host.  A batch is the disjoint union of many graphs
+// refined by the same launches, with per-graph ids and counts.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <new>
+#include <utility>
 #include <vector>
 
 #include "../../include/kbisim.h"
@@ -29,6 +34,10 @@ constexpr size_t ALIGN = 256;
 constexpr int CNT_STRIDE = 16;  // device counters per step
 constexpr int PERSIST_GRID = 2048;
 constexpr int RES_GRID = 256;
+constexpr int CLEAR_GRID = 2048;
+constexpr int MIN_RANGE_EDGES = 1024;  // smallest tunable range capacity
+constexpr int MIN_HUB_CHUNK = 2048;    // smallest tunable hub chunk
+constexpr int MAX_GRAPH_CACHE = 8;
 
 inline size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
@@ -40,16 +49,17 @@ uint64_t pow2_at_least(uint64_t x) {
 
 struct Plan {
   size_t off_H, off_DC, off_rep, off_p0, off_vlist, off_clA, off_clB, off_ranges, off_lists, off_gcol, off_rank,
-      off_gpid;
+      off_gpid, off_zrep;
   size_t off_table, off_ctable, off_hacc, off_hcnt, off_chunks, off_parts, off_gchunks, off_poff;
-  size_t off_status, off_counters, off_dcounts, off_err, off_stats, off_hubsets, off_zrep;
+  size_t off_status, off_counters, off_dcounts, off_err, off_dep, off_hubsets;
+  size_t off_gid, off_ibuf, off_first, off_next, off_bcounts;  // batches only
   uint64_t tslots;
   int64_t max_ranges, max_lists, nhub_max, nchunk_max, npart_max, ngchunk_max, npoff_max, ntiles, hubset_slots;
   int ncounter_steps;
   size_t total;
 };
 
-Plan make_plan(int64_t n, int64_t m, int64_t nl, int kmax) {
+Plan make_plan(int64_t n, int64_t m, int64_t nl, int kmax, int64_t num_graphs) {
   Plan p{};
   size_t at = 0;
   auto take = [&](size_t bytes) {
@@ -60,16 +70,16 @@ Plan make_plan(int64_t n, int64_t m, int64_t nl, int kmax) {
   const size_t N = (size_t)std::max<int64_t>(n, 1);
   const int64_t big = std::max<int64_t>(std::max<int64_t>(m, nl), 1);
   p.tslots = pow2_at_least(2 * (uint64_t)N);
-  // A range closes at a hub, when the next row would overflow its entries
-  // (the closed range and that row together hold more than RANGE_EDGES
-  // entries, and each row is "next" once), when full of vertices, or at the end.
-  // Rows above RANGE_EDGES add a range of their own and close the current one.
-  p.max_ranges = big / (RANGE_DMAX + 1) + 2 * big / (RANGE_EDGES + 1) + 2 * big / RANGE_EDGES +
+  // A range closes at a hub, when the next row would overflow it (the closed
+  // range and that row hold more than its capacity together, and each row is
+  // "next" once), when full of vertices, or at the end; rows above the
+  // capacity form ranges of their own.  Bounds use the smallest capacity.
+  p.max_ranges = big / (RANGE_DMAX + 1) + 2 * big / (MIN_RANGE_EDGES + 1) + 2 * big / MIN_RANGE_EDGES +
                  (int64_t)N / RANGE_VERTS + 8;
   p.max_lists = big / (RANGE_DMAX + 1) + 8;
   p.nhub_max = big / (BLOCK_MAX + 1) + 1;
-  p.nchunk_max = big / HUB_CHUNK + p.nhub_max + 1;
-  p.npart_max = big / (HUB_PART_TARGET / 2) + 2 * p.nhub_max + 1;
+  p.nchunk_max = big / MIN_HUB_CHUNK + p.nhub_max + 1;
+  p.npart_max = big / (HUB_PART_TARGET / 4) + 2 * p.nhub_max + 1;
   p.ngchunk_max = big / HUB_GCHUNK + p.nhub_max + 1;
   p.npoff_max = big / 16 + 4 * (HUB_PMAX + 1) + p.nchunk_max;
   p.ntiles = (int64_t)(N + SCAN_TILE - 1) / SCAN_TILE + 1;
@@ -83,11 +93,11 @@ Plan make_plan(int64_t n, int64_t m, int64_t nl, int kmax) {
   p.off_clA = take(4 * N);
   p.off_clB = take(4 * N);
   p.off_ranges = take(sizeof(Range) * (size_t)p.max_ranges);
+  p.off_lists = take(4 * (size_t)p.max_lists);
   p.off_gcol = take(4 * (size_t)std::max<int64_t>(m, 1));
   p.off_rank = take(4 * N);
   p.off_gpid = take(8 * N);
   p.off_zrep = take(8 * N);
-  p.off_lists = take(4 * (size_t)p.max_lists);
   p.off_table = take(8 * p.tslots);
   p.off_ctable = take(8 * p.tslots);
   p.off_hacc = take(8 * (size_t)p.nhub_max);
@@ -100,8 +110,15 @@ Plan make_plan(int64_t n, int64_t m, int64_t nl, int kmax) {
   p.off_counters = take(4 * (size_t)CNT_STRIDE * (size_t)p.ncounter_steps);
   p.off_dcounts = take(8 * (size_t)p.ncounter_steps);
   p.off_err = take(16);
-  p.off_stats = take(64);
+  p.off_dep = take(64);
   p.off_hubsets = take(8 * (size_t)p.hubset_slots);
+  if (num_graphs > 0) {
+    p.off_gid = take(4 * N);
+    p.off_ibuf = take(8 * N);
+    p.off_first = take(8 * (size_t)(num_graphs + 1));
+    p.off_next = take(8 * (size_t)num_graphs);
+    p.off_bcounts = take(8 * (size_t)num_graphs * (size_t)std::max(kmax, 1));
+  }
   p.total = at;
   return p;
 }
@@ -109,12 +126,29 @@ Plan make_plan(int64_t n, int64_t m, int64_t nl, int kmax) {
 // Static degree schedule of one row structure (graph rows or label-set rows),
 // built on the host at create time; degrees never change across iterations.
 struct Schedule {
-  int nranges = 0;      // multi-vertex ranges (at most RANGE_EDGES entries)
-  int nbig = 0;         // single-row ranges of RANGE_EDGES < deg <= RANGE_DMAX
+  int nranges = 0;  // multi-vertex ranges (at most range_edges entries)
+  int nbig = 0;     // single-row ranges of range_edges < deg <= RANGE_DMAX
   int nhub = 0, hub_off = 0;
   int nchunks = 0, nparts = 0, ngchunks = 0;
   int64_t gset_begin = 0, gset_end = 0;  // global hash sets of very large hubs
   int64_t info[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // vertices, entries per tier
+};
+
+struct Tuning {
+  int range_edges = RANGE_EDGES;
+  int hub_chunk = HUB_CHUNK;
+  int hub_part_target = HUB_PART_TARGET;
+};
+
+struct GraphKey {
+  const void *start;
+  int k;
+  std::vector<const void *> outs;
+  bool operator<(const GraphKey &o) const {
+    if (start != o.start) return start < o.start;
+    if (k != o.k) return k < o.k;
+    return outs < o.outs;
+  }
 };
 
 }  // namespace
@@ -124,28 +158,41 @@ struct kbisim_ctx {
   int kmax;
   hipStream_t stream;
   Plan plan;
+  Tuning tune;
   char *ws;
   u64 *H, *table, *ctable, *hacc, *hubsets, *zrep;
-  u32 *DC, *hcnt, *err, *tiles;
+  u32 *DC, *hcnt, *err, *tiles, *dep;
   int *rep, *p0, *vlist, *clA, *clB, *lists, *counters, *poff, *gcol, *rank, *gpid[2];
   int64_t *dcounts;
-  u64 *stats;
   Range *ranges;
   HubChunk *chunks;
   HubPart *parts;
   HubGChunk *gchunks;
-  Schedule sched;      // graph rows
+  Schedule sched;  // graph rows
+  u64 hmask = ~0ULL;
+  int64_t p0_count = 0;
+  // batches
+  int64_t num_graphs = 0;
+  int *gid = nullptr, *ibuf[2] = {nullptr, nullptr};
+  int64_t *first = nullptr, *next = nullptr, *bcounts = nullptr;
   // per-kernel profiling
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
-  struct Pending { int kind; size_t a, b; };
-  std::vector<Pending> ev_pending;  // (kind, start event, end event)
+  struct Pending {
+    int kind;
+    size_t a, b;
+  };
+  std::vector<Pending> ev_pending;
   double prof_ms[KBISIM_NKERNELS] = {0};
   int64_t prof_n[KBISIM_NKERNELS] = {0};
-  u32 epoch = 0, cepoch = 0, hepoch = 0, stamp = 0, zepoch = 0;
-  u64 hmask = ~0ULL;
-  int64_t p0_count = 0;
+  // captured refinement loops
+  bool use_graphs = false;
+  std::map<GraphKey, hipGraphExec_t> graphs;
+};
+
+struct kbisim_batch {
+  kbisim_ctx *c;
 };
 
 namespace {
@@ -155,9 +202,9 @@ int hip_fail(hipError_t e) {
   return KBISIM_EHIP;
 }
 
-#define HIP_TRY(expr)                         \
-  do {                                        \
-    hipError_t _e = (expr);                   \
+#define HIP_TRY(expr)                          \
+  do {                                         \
+    hipError_t _e = (expr);                    \
     if (_e != hipSuccess) return hip_fail(_e); \
   } while (0)
 
@@ -226,24 +273,15 @@ int fill_i32(kbisim_ctx *c, int *p, int64_t cnt, int val) {
   return 0;
 }
 
-// Next table epoch in 1..15; the table is cleared before an epoch repeats.
-int next_epoch(kbisim_ctx *c, u32 &e, u64 *table) {
-  if (e >= 15) {
-    int rc = fill_u64(c, table, (int64_t)c->plan.tslots, 0);
-    if (rc) return rc;
-    e = 0;
-  }
-  ++e;
-  return 0;
-}
-
-int next_hub_epoch(kbisim_ctx *c, const Schedule &s) {
-  if (c->hepoch >= 3) {
-    int rc = fill_u64(c, c->hubsets + s.gset_begin, s.gset_end - s.gset_begin, 0);
-    if (rc) return rc;
-    c->hepoch = 0;
-  }
-  ++c->hepoch;
+// Advance the device-side epochs named in `mask` and clear the tables whose
+// epoch wrapped.
+int advance(kbisim_ctx *c, u32 mask, const Schedule &s) {
+  ProfScope ps(c, KBISIM_K_FILL);
+  k_advance<<<1, 64, 0, c->stream>>>(c->dep, mask);
+  LAUNCH_CHECK();
+  k_clear_if<<<CLEAR_GRID, 256, 0, c->stream>>>(c->dep, c->table, (int64_t)c->plan.tslots, c->ctable,
+                                                c->hubsets + s.gset_begin, s.gset_end - s.gset_begin);
+  LAUNCH_CHECK();
   return 0;
 }
 
@@ -253,11 +291,18 @@ int read_err(kbisim_ctx *c, u32 *out) {
   return 0;
 }
 
+int hub_parts_for(const Tuning &t, int64_t d) {
+  int P = 1;
+  while ((int64_t)P * t.hub_part_target < d && P < HUB_PMAX) P <<= 1;
+  return P;
+}
+
 // Build the static schedule of the rows of `ptr` (NULL: every row has one
-// item) on the host: runs of low-degree vertices, the workgroup tier by set
-// size, and hub chunks, partitions and staging areas.  Synchronises.
+// item) on the host: runs of consecutive low-degree vertices, single-row
+// ranges, and hub chunks, partitions and staging areas.  Synchronises.
 int build_schedule(kbisim_ctx *c, const int64_t *ptr, Schedule &s) {
   const int64_t n = c->g.n;
+  const Tuning &t = c->tune;
   s = Schedule{};
   std::vector<int64_t> rp;
   if (ptr && n > 0) {
@@ -266,7 +311,7 @@ int build_schedule(kbisim_ctx *c, const int64_t *ptr, Schedule &s) {
     HIP_TRY(hipStreamSynchronize(c->stream));
   }
   auto deg = [&](int64_t v) -> int64_t { return ptr ? rp[(size_t)v + 1] - rp[(size_t)v] : 1; };
-  std::vector<Range> ranges;
+  std::vector<Range> ranges, big_ranges;
   std::vector<int> hubs;
   int64_t cur0 = -1, cur_e = 0;
   auto close = [&](int64_t v_end) {
@@ -274,7 +319,6 @@ int build_schedule(kbisim_ctx *c, const int64_t *ptr, Schedule &s) {
     cur0 = -1;
     cur_e = 0;
   };
-  std::vector<Range> big_ranges;
   for (int64_t v = 0; v < n; ++v) {
     const int64_t d = deg(v);
     if (d > RANGE_DMAX) {
@@ -282,14 +326,14 @@ int build_schedule(kbisim_ctx *c, const int64_t *ptr, Schedule &s) {
       hubs.push_back((int)v);
       continue;
     }
-    if (d > RANGE_EDGES) {
+    if (d > t.range_edges) {
       close(v);
       big_ranges.push_back(Range{(int)v, (int)v + 1});
       s.info[2] += 1;
       s.info[3] += d;
       continue;
     }
-    if (cur0 >= 0 && (cur_e + d > RANGE_EDGES || v - cur0 == RANGE_VERTS)) close(v);
+    if (cur0 >= 0 && (cur_e + d > t.range_edges || v - cur0 == RANGE_VERTS)) close(v);
     if (cur0 < 0) cur0 = v;
     cur_e += d;
     s.info[0] += 1;
@@ -303,54 +347,45 @@ int build_schedule(kbisim_ctx *c, const int64_t *ptr, Schedule &s) {
   std::vector<HubChunk> chunks;
   std::vector<HubPart> parts;
   std::vector<HubGChunk> gchunks;
-  int64_t stage_at = 0, poff_at = 0;
-  int64_t gset_at = 0;
-  std::vector<int64_t> gsize;
   std::vector<char> is_staged(hubs.size(), 0);
+  int64_t stage_at = 0, poff_at = 0;
   for (size_t i = 0; i < hubs.size(); ++i) {
     const int64_t d = deg(hubs[i]);
-    const int64_t C = (d + HUB_CHUNK - 1) / HUB_CHUNK;
-    int P = 1;
-    while ((int64_t)P * HUB_PART_TARGET < d && P < HUB_PMAX) P <<= 1;
-    const bool staged = d <= HUB_STAGED_MAX && poff_at + C * (P + 1) <= c->plan.npoff_max;
-    if (staged) {
-      HubPart hp;
-      hp.hub = (int)i;
-      hp.chunk0 = (int)chunks.size();
-      hp.nchunks = (int)C;
-      for (int64_t k = 0; k < C; ++k) {
-        HubChunk hc;
-        hc.hub = (int)i;
-        hc.parts = P;
-        hc.b = k * HUB_CHUNK;
-        hc.e = std::min<int64_t>(d, (k + 1) * HUB_CHUNK);
-        hc.stage = stage_at;
-        hc.poff = poff_at;
-        stage_at += HUB_CHUNK;
-        poff_at += P + 1;
-        chunks.push_back(hc);
-      }
-      for (int q = 0; q < P; ++q) {
-        hp.part = q;
-        parts.push_back(hp);
-      }
-      is_staged[i] = 1;
-      s.info[4] += 1;
-      s.info[5] += d;
-    } else {
-      gsize.push_back(2 * d);
-      s.info[6] += 1;
-      s.info[7] += d;
+    const int64_t C = (d + t.hub_chunk - 1) / t.hub_chunk;
+    const int P = hub_parts_for(t, d);
+    const bool staged = d <= HUB_STAGED_MAX && C <= HUB_PMAX && poff_at + C * (P + 1) <= c->plan.npoff_max;
+    if (!staged) continue;
+    HubPart hp;
+    hp.hub = (int)i;
+    hp.chunk0 = (int)chunks.size();
+    hp.nchunks = (int)C;
+    for (int64_t k = 0; k < C; ++k) {
+      HubChunk hc;
+      hc.hub = (int)i;
+      hc.parts = P;
+      hc.b = k * t.hub_chunk;
+      hc.e = std::min<int64_t>(d, (k + 1) * t.hub_chunk);
+      hc.stage = stage_at;
+      hc.poff = poff_at;
+      stage_at += t.hub_chunk;
+      poff_at += P + 1;
+      chunks.push_back(hc);
     }
+    for (int q = 0; q < P; ++q) {
+      hp.part = q;
+      parts.push_back(hp);
+    }
+    is_staged[i] = 1;
+    s.info[4] += 1;
+    s.info[5] += d;
   }
-  // global sets follow the staging areas
+  // global sets of the remaining hubs follow the staging areas
   s.gset_begin = stage_at;
-  gset_at = stage_at;
-  size_t gi = 0;
+  int64_t gset_at = stage_at;
   for (size_t i = 0; i < hubs.size(); ++i) {
-    const int64_t d = deg(hubs[i]);
     if (is_staged[i]) continue;
-    const int64_t size = gsize[gi++];
+    const int64_t d = deg(hubs[i]);
+    const int64_t size = 2 * d;
     for (int64_t b = 0; b < d; b += HUB_GCHUNK) {
       HubGChunk g;
       g.hub = (int)i;
@@ -362,24 +397,24 @@ int build_schedule(kbisim_ctx *c, const int64_t *ptr, Schedule &s) {
       gchunks.push_back(g);
     }
     gset_at += size;
+    s.info[6] += 1;
+    s.info[7] += d;
   }
   s.gset_end = gset_at;
   if ((int64_t)ranges.size() > c->plan.max_ranges || gset_at > c->plan.hubset_slots ||
       (int64_t)chunks.size() > c->plan.nchunk_max || (int64_t)parts.size() > c->plan.npart_max ||
-      (int64_t)gchunks.size() > c->plan.ngchunk_max || (int64_t)hubs.size() > c->plan.nhub_max)
+      (int64_t)gchunks.size() > c->plan.ngchunk_max || (int64_t)hubs.size() > c->plan.nhub_max ||
+      (int64_t)hubs.size() > c->plan.max_lists)
     return KBISIM_EINTERNAL;
-  std::vector<int> lists;
   s.hub_off = 0;
   s.nhub = (int)hubs.size();
-  lists.insert(lists.end(), hubs.begin(), hubs.end());
-  if ((int64_t)lists.size() > c->plan.max_lists) return KBISIM_EINTERNAL;
   s.nchunks = (int)chunks.size();
   s.nparts = (int)parts.size();
   s.ngchunks = (int)gchunks.size();
   if (!ranges.empty())
     HIP_TRY(hipMemcpyAsync(c->ranges, ranges.data(), sizeof(Range) * ranges.size(), hipMemcpyHostToDevice, c->stream));
-  if (!lists.empty())
-    HIP_TRY(hipMemcpyAsync(c->lists, lists.data(), 4 * lists.size(), hipMemcpyHostToDevice, c->stream));
+  if (!hubs.empty())
+    HIP_TRY(hipMemcpyAsync(c->lists, hubs.data(), 4 * hubs.size(), hipMemcpyHostToDevice, c->stream));
   if (!chunks.empty())
     HIP_TRY(hipMemcpyAsync(c->chunks, chunks.data(), sizeof(HubChunk) * chunks.size(), hipMemcpyHostToDevice,
                            c->stream));
@@ -394,7 +429,6 @@ int build_schedule(kbisim_ctx *c, const int64_t *ptr, Schedule &s) {
     if ((rc = fill_i32(c, (int *)c->hcnt, s.nhub, 0))) return rc;
     if ((rc = fill_u64(c, c->hubsets + s.gset_begin, s.gset_end - s.gset_begin, 0))) return rc;
   }
-  c->hepoch = 0;
   HIP_TRY(hipStreamSynchronize(c->stream));
   return 0;
 }
@@ -433,51 +467,61 @@ int build_rank(kbisim_ctx *c) {
 // One peeling round over `in_list` (count at in_cnt) into out_list/out_cnt.
 template <class Src>
 int peel_round(kbisim_ctx *c, const Src &src, int *in_cnt, int *in_list, int *out_cnt, int *out_list) {
-  int rc = next_epoch(c, c->cepoch, c->ctable);
-  if (rc) return rc;
   ProfScope ps(c, KBISIM_K_PEEL);
-  k_res_insert<<<RES_GRID, 256, 0, c->stream>>>(in_cnt, in_list, c->H, c->ctable, c->plan.tslots - 1, c->cepoch);
+  k_res_insert<<<RES_GRID, 256, 0, c->stream>>>(in_cnt, in_list, c->H, c->ctable, c->plan.tslots - 1, c->dep);
   LAUNCH_CHECK();
   k_res_verify<Src><<<RES_GRID, 256, 0, c->stream>>>(src, in_cnt, in_list, c->H, c->DC, c->ctable,
-                                                     c->plan.tslots - 1, c->cepoch, c->rep, out_cnt, out_list,
-                                                     c->err);
+                                                     c->plan.tslots - 1, c->dep, c->rep, out_cnt, out_list, c->err);
   LAUNCH_CHECK();
+  return 0;
+}
+
+template <class Src>
+int launch_ranges(kbisim_ctx *c, const Src &src, const Schedule &s) {
+  const u64 tmask = c->plan.tslots - 1;
+  if (s.nranges) {
+    ProfScope ps(c, KBISIM_K_SIG_RANGE);
+    if (c->tune.range_edges == 1024)
+      k_sig_range<Src, 1024><<<(unsigned)s.nranges, 256, 0, c->stream>>>(src, c->ranges, c->H, c->DC, c->table, tmask,
+                                                                         c->dep, c->hmask, c->zrep);
+    else
+      k_sig_range<Src, 2048><<<(unsigned)s.nranges, 256, 0, c->stream>>>(src, c->ranges, c->H, c->DC, c->table, tmask,
+                                                                         c->dep, c->hmask, c->zrep);
+    LAUNCH_CHECK();
+  }
+  if (s.nbig) {
+    ProfScope ps(c, KBISIM_K_SIG_BLOCK);
+    k_sig_range<Src, RANGE_DMAX><<<(unsigned)s.nbig, 256, 0, c->stream>>>(src, c->ranges + s.nranges, c->H, c->DC,
+                                                                          c->table, tmask, c->dep, c->hmask, c->zrep);
+    LAUNCH_CHECK();
+  }
   return 0;
 }
 
 // One refinement step: src (previous partition inside) -> out, block count
 // into *count_dev.  cnt: CNT_STRIDE zeroed device counters for this step.
 // careful: settle every collision with host-driven peeling rounds.
+// gpid_next: where to write the new partition in rank order (NULL: not needed).
 template <class Src>
 int run_step(kbisim_ctx *c, const Src &src, const Schedule &s, int *out, int64_t *count_dev, int *cnt,
              bool careful, int *gpid_next) {
   const int n = (int)c->g.n;
   if (n == 0) return 0;
   const u64 tmask = c->plan.tslots - 1;
-  int rc = next_epoch(c, c->epoch, c->table);
+  int rc = advance(c, ADV_TABLE | ADV_CTABLE | ADV_ZERO | (s.ngchunks ? ADV_HUB : 0u), s);
   if (rc) return rc;
-  const u32 ep = c->epoch;
-  const u32 zep = ++c->zepoch;
-  if (s.nranges) {
-    ProfScope ps(c, KBISIM_K_SIG_RANGE);
-    k_sig_range<Src, RANGE_EDGES><<<(unsigned)s.nranges, 256, 0, c->stream>>>(src, c->ranges, c->H, c->DC, c->table,
-                                                                              tmask, ep, c->hmask, c->zrep, zep);
-    LAUNCH_CHECK();
-  }
-  if (s.nbig) {
-    ProfScope ps(c, KBISIM_K_SIG_BLOCK);
-    k_sig_range<Src, 2 * RANGE_EDGES><<<(unsigned)s.nbig, 256, 0, c->stream>>>(src, c->ranges + s.nranges, c->H,
-                                                                               c->DC, c->table, tmask, ep, c->hmask,
-                                                                               c->zrep, zep);
-    LAUNCH_CHECK();
-  }
+  if ((rc = launch_ranges(c, src, s))) return rc;
   if (s.nhub) {
     const int *hubs = c->lists + s.hub_off;
     if (s.nchunks) {
       {
         ProfScope ps(c, KBISIM_K_HUB_STAGE);
-        k_hub_stage<Src><<<(unsigned)s.nchunks, 256, 0, c->stream>>>(src, c->chunks, hubs, c->hubsets, c->poff,
-                                                                     c->err);
+        if (c->tune.hub_chunk == 2048)
+          k_hub_stage<Src, 2048><<<(unsigned)s.nchunks, 256, 0, c->stream>>>(src, c->chunks, hubs, c->hubsets, c->poff,
+                                                                             c->err);
+        else
+          k_hub_stage<Src, 4096><<<(unsigned)s.nchunks, 256, 0, c->stream>>>(src, c->chunks, hubs, c->hubsets, c->poff,
+                                                                             c->err);
         LAUNCH_CHECK();
       }
       ProfScope ps(c, KBISIM_K_HUB_REDUCE);
@@ -486,22 +530,20 @@ int run_step(kbisim_ctx *c, const Src &src, const Schedule &s, int *out, int64_t
       LAUNCH_CHECK();
     }
     if (s.ngchunks) {
-      rc = next_hub_epoch(c, s);
-      if (rc) return rc;
       ProfScope ps(c, KBISIM_K_HUB_STAGE);
       k_sig_hub_global<Src><<<(unsigned)s.ngchunks, 256, 0, c->stream>>>(src, c->gchunks, hubs, c->hubsets, c->hacc,
-                                                                         c->hcnt, c->hepoch);
+                                                                         c->hcnt, c->dep);
       LAUNCH_CHECK();
     }
     ProfScope ps(c, KBISIM_K_HUB_FINAL);
     k_hub_final<Src><<<blocks_for(s.nhub, 256), 256, 0, c->stream>>>(src, hubs, s.nhub, c->hacc, c->hcnt, c->H, c->DC,
-                                                                     c->table, tmask, ep, c->hmask, c->zrep, zep);
+                                                                     c->table, tmask, c->dep, c->hmask, c->zrep);
     LAUNCH_CHECK();
   }
   {
     ProfScope ps(c, KBISIM_K_LOOKUP);
-    k_lookup<Src><<<blocks_for(n, 256), 256, 0, c->stream>>>(src, n, c->H, c->DC, c->table, tmask, ep, c->rep,
-                                                             &cnt[0], c->vlist, &cnt[1], c->clA, c->err, c->zrep, zep);
+    k_lookup<Src><<<blocks_for(n, 256), 256, 0, c->stream>>>(src, n, c->H, c->DC, c->table, tmask, c->dep, c->rep,
+                                                             &cnt[0], c->vlist, &cnt[1], c->clA, c->err, c->zrep);
     LAUNCH_CHECK();
   }
   {
@@ -522,10 +564,9 @@ int run_step(kbisim_ctx *c, const Src &src, const Schedule &s, int *out, int64_t
       prof_collect(c);
       if (left == 0) break;
       if (round > n + 1) return KBISIM_EINTERNAL;
-      rc = fill_i32(c, out_cnt, 1, 0);
-      if (rc) return rc;
-      rc = peel_round(c, src, in_cnt, in_list, out_cnt, out_list);
-      if (rc) return rc;
+      if ((rc = fill_i32(c, out_cnt, 1, 0))) return rc;
+      if ((rc = advance(c, ADV_CTABLE, s))) return rc;
+      if ((rc = peel_round(c, src, in_cnt, in_list, out_cnt, out_list))) return rc;
       std::swap(in_cnt, out_cnt);
       std::swap(in_list, out_list);
     }
@@ -542,9 +583,36 @@ int run_step(kbisim_ctx *c, const Src &src, const Schedule &s, int *out, int64_t
   }
   {
     ProfScope ps(c, KBISIM_K_ASSIGN);
-    // label-set steps (P0) need no rank-order copy
     k_assign<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, c->rep, out, gpid_next ? c->rank : nullptr, gpid_next);
     LAUNCH_CHECK();
+  }
+  return 0;
+}
+
+// Enqueue steps [i0, k) starting from partition `prev` (no host
+// synchronisation unless careful).  In a batch, step i refines into an
+// internal buffer of global ids and writes the caller's per-graph ids and
+// counts.
+int enqueue_steps(kbisim_ctx *c, const int32_t *prev, int i0, int k, int32_t *const *out, bool careful) {
+  const int n = (int)c->g.n;
+  const bool batch = c->num_graphs > 0;
+  int rc = 0;
+  k_scatter_rank<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, prev, c->rank, c->gpid[i0 & 1]);
+  LAUNCH_CHECK();
+  for (int i = i0; i < k; ++i) {
+    if (careful && (rc = fill_i32(c, c->counters + CNT_STRIDE * i, CNT_STRIDE, 0))) return rc;
+    int *dst = batch ? c->ibuf[i & 1] : out[i];
+    GraphSrc src{c->g.row_ptr, c->gcol, c->g.elabel, c->gpid[i & 1], prev};
+    rc = run_step(c, src, c->sched, dst, &c->dcounts[i], c->counters + CNT_STRIDE * i, careful, c->gpid[(i + 1) & 1]);
+    if (rc) return rc;
+    if (batch) {
+      k_rebase<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, c->gid, c->first, dst, out[i]);
+      LAUNCH_CHECK();
+      k_batch_counts<<<blocks_for(c->num_graphs, 256), 256, 0, c->stream>>>((int)c->num_graphs, c->first, c->next,
+                                                                            dst, &c->dcounts[i], k, i, c->bcounts);
+      LAUNCH_CHECK();
+    }
+    prev = dst;
   }
   return 0;
 }
@@ -557,53 +625,73 @@ int refine_impl(kbisim_ctx *c, const int32_t *start, int k, int32_t *const *out,
   for (int i = 0; i < k; ++i)
     if (!out[i] && c->g.n > 0) return KBISIM_EINVAL;
   const int n = (int)c->g.n;
+  const bool batch = c->num_graphs > 0;
+  const int64_t ncounts = batch ? c->num_graphs * (int64_t)k : (int64_t)k;
   if (n == 0) {
-    for (int i = 0; i < k; ++i) counts[i] = 0;
+    for (int64_t i = 0; i < ncounts; ++i) counts[i] = 0;
     return KBISIM_OK;
   }
-  int rc = fill_i32(c, c->counters, (int64_t)CNT_STRIDE * k, 0);
-  if (rc) return rc;
-  rc = fill_i32(c, (int *)c->err, 1, 0);
-  if (rc) return rc;
-  const int32_t *prev = start ? start : c->p0;
-  k_scatter_rank<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, prev, c->rank, c->gpid[0]);
-  LAUNCH_CHECK();
-  for (int i = 0; i < k; ++i) {
-    GraphSrc src{c->g.row_ptr, c->gcol, c->g.elabel, c->gpid[i & 1], prev};
-    rc = run_step(c, src, c->sched, out[i], &c->dcounts[i], c->counters + CNT_STRIDE * i, false, c->gpid[(i + 1) & 1]);
-    if (rc) return rc;
-    prev = out[i];
+  const int32_t *p0 = start ? start : c->p0;
+  int rc = 0;
+  const bool graphed = c->use_graphs && !c->prof;
+  if (graphed) {
+    GraphKey key{start, k, std::vector<const void *>(out, out + k)};
+    auto it = c->graphs.find(key);
+    if (it == c->graphs.end()) {
+      if ((int)c->graphs.size() >= MAX_GRAPH_CACHE) {
+        (void)hipGraphExecDestroy(c->graphs.begin()->second);
+        c->graphs.erase(c->graphs.begin());
+      }
+      HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+      int rc1 = fill_i32(c, c->counters, (int64_t)CNT_STRIDE * k, 0);
+      if (!rc1) rc1 = fill_i32(c, (int *)c->err, 1, 0);
+      if (!rc1) rc1 = enqueue_steps(c, p0, 0, k, out, false);
+      hipGraph_t graph = nullptr;
+      hipError_t e = hipStreamEndCapture(c->stream, &graph);
+      if (rc1) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc1;
+      }
+      if (e != hipSuccess) return hip_fail(e);
+      hipGraphExec_t exec = nullptr;
+      e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (e != hipSuccess) return hip_fail(e);
+      it = c->graphs.emplace(key, exec).first;
+    }
+    HIP_TRY(hipGraphLaunch(it->second, c->stream));
+  } else {
+    if ((rc = fill_i32(c, c->counters, (int64_t)CNT_STRIDE * k, 0))) return rc;
+    if ((rc = fill_i32(c, (int *)c->err, 1, 0))) return rc;
+    if ((rc = enqueue_steps(c, p0, 0, k, out, false))) return rc;
   }
   std::vector<int> hc((size_t)CNT_STRIDE * k);
   u32 err = 0;
   HIP_TRY(hipMemcpyAsync(hc.data(), c->counters, 4 * hc.size(), hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(hipMemcpyAsync(counts, c->dcounts, 8 * (size_t)k, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipMemcpyAsync(&err, c->err, sizeof err, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   prof_collect(c);
   if (err) return KBISIM_EINTERNAL;
   int first_bad = -1;
   for (int i = 0; i < k; ++i)
-    if (hc[(size_t)CNT_STRIDE * i + 2] != 0) { first_bad = i; break; }
-  if (first_bad >= 0) {
-    prev = first_bad == 0 ? (start ? start : c->p0) : out[first_bad - 1];
-    k_scatter_rank<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, prev, c->rank, c->gpid[first_bad & 1]);
-    LAUNCH_CHECK();
-    for (int i = first_bad; i < k; ++i) {
-      rc = fill_i32(c, c->counters + CNT_STRIDE * i, CNT_STRIDE, 0);
-      if (rc) return rc;
-      GraphSrc src{c->g.row_ptr, c->gcol, c->g.elabel, c->gpid[i & 1], prev};
-      rc = run_step(c, src, c->sched, out[i], &c->dcounts[i], c->counters + CNT_STRIDE * i, true,
-                    c->gpid[(i + 1) & 1]);
-      if (rc) return rc;
-      prev = out[i];
+    if (hc[(size_t)CNT_STRIDE * i + 2] != 0) {
+      first_bad = i;
+      break;
     }
-    HIP_TRY(hipMemcpyAsync(counts, c->dcounts, 8 * (size_t)k, hipMemcpyDeviceToHost, c->stream));
+  if (first_bad >= 0) {
+    const int32_t *prev = first_bad == 0 ? p0 : (batch ? c->ibuf[(first_bad - 1) & 1] : out[first_bad - 1]);
+    if ((rc = enqueue_steps(c, prev, first_bad, k, out, true))) return rc;
     HIP_TRY(hipMemcpyAsync(&err, c->err, sizeof err, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     prof_collect(c);
     if (err) return KBISIM_EINTERNAL;
   }
+  if (batch) {
+    HIP_TRY(hipMemcpyAsync(counts, c->bcounts, 8 * (size_t)ncounts, hipMemcpyDeviceToHost, c->stream));
+  } else {
+    HIP_TRY(hipMemcpyAsync(counts, c->dcounts, 8 * (size_t)k, hipMemcpyDeviceToHost, c->stream));
+  }
+  HIP_TRY(hipStreamSynchronize(c->stream));
   return KBISIM_OK;
 }
 
@@ -615,30 +703,46 @@ int check_sizes(const kbisim_graph *g) {
   return 0;
 }
 
-}  // namespace
-
-extern "C" {
-
-int kbisim_workspace_bytes(const kbisim_graph *g, int kmax, size_t *bytes) {
-  int rc = check_sizes(g);
-  if (rc) return rc;
-  if (!bytes || kmax < 0 || kmax > (1 << 20)) return KBISIM_EINVAL;
-  *bytes = make_plan(g->n, g->m, g->vlabel_ptr ? g->nlabels : 0, kmax).total;
-  return KBISIM_OK;
+int read_tuning(const kbisim_tuning *t, Tuning &out) {
+  out = Tuning{};
+  if (!t) return 0;
+  if (t->range_edges) {
+    if (t->range_edges != 1024 && t->range_edges != 2048) return KBISIM_EINVAL;
+    out.range_edges = t->range_edges;
+  }
+  if (t->hub_chunk) {
+    if (t->hub_chunk != 2048 && t->hub_chunk != 4096) return KBISIM_EINVAL;
+    out.hub_chunk = t->hub_chunk;
+  }
+  if (t->hub_part_target) {
+    if (t->hub_part_target != 1024 && t->hub_part_target != 2048) return KBISIM_EINVAL;
+    out.hub_part_target = t->hub_part_target;
+  }
+  return 0;
 }
 
-int kbisim_create(const kbisim_graph *g, int kmax, void *workspace, size_t ws_bytes, void *stream, kbisim_ctx **out) {
+// Shared by kbisim_create and kbisim_batch_create.  With vert_off (host,
+// num_graphs + 1) the graph is a batch of disjoint graphs.
+int create_impl(const kbisim_graph *g, int kmax, const kbisim_tuning *tuning, void *workspace, size_t ws_bytes,
+                void *stream, int64_t num_graphs, const int64_t *vert_off, kbisim_ctx **out) {
   int rc = check_sizes(g);
   if (rc) return rc;
   if (!out || kmax < 0 || kmax > (1 << 20)) return KBISIM_EINVAL;
   *out = nullptr;
+  Tuning tune;
+  if ((rc = read_tuning(tuning, tune))) return rc;
   const int64_t n = g->n, m = g->m;
   if (n > 0 && !g->row_ptr) return KBISIM_EINVAL;
   if (m > 0 && !g->col) return KBISIM_EINVAL;
   if (g->vlabel_ptr && !g->vlabel && g->nlabels > 0) return KBISIM_EINVAL;
   if (!g->vlabel_ptr && !g->vlabel && g->nlabels > 0) return KBISIM_EINVAL;
+  if (num_graphs > 0) {
+    if (!vert_off || vert_off[0] != 0 || vert_off[num_graphs] != n) return KBISIM_EINVAL;
+    for (int64_t i = 0; i < num_graphs; ++i)
+      if (vert_off[i + 1] < vert_off[i]) return KBISIM_EINVAL;
+  }
   const int64_t nl = g->vlabel_ptr ? g->nlabels : 0;
-  Plan plan = make_plan(n, m, nl, kmax);
+  Plan plan = make_plan(n, m, nl, kmax, num_graphs);
   if (!workspace) return KBISIM_EINVAL;
   if (ws_bytes < plan.total) return KBISIM_ENOSPACE;
 
@@ -648,6 +752,7 @@ int kbisim_create(const kbisim_graph *g, int kmax, void *workspace, size_t ws_by
   c->kmax = kmax;
   c->stream = (hipStream_t)stream;
   c->plan = plan;
+  c->tune = tune;
   c->ws = (char *)workspace;
   char *w = c->ws;
   c->H = (u64 *)(w + plan.off_H);
@@ -676,8 +781,17 @@ int kbisim_create(const kbisim_graph *g, int kmax, void *workspace, size_t ws_by
   c->counters = (int *)(w + plan.off_counters);
   c->dcounts = (int64_t *)(w + plan.off_dcounts);
   c->err = (u32 *)(w + plan.off_err);
-  c->stats = (u64 *)(w + plan.off_stats);
+  c->dep = (u32 *)(w + plan.off_dep);
   c->hubsets = (u64 *)(w + plan.off_hubsets);
+  if (num_graphs > 0) {
+    c->num_graphs = num_graphs;
+    c->gid = (int *)(w + plan.off_gid);
+    c->ibuf[0] = (int *)(w + plan.off_ibuf);
+    c->ibuf[1] = c->ibuf[0] + std::max<int64_t>(n, 1);
+    c->first = (int64_t *)(w + plan.off_first);
+    c->next = (int64_t *)(w + plan.off_next);
+    c->bcounts = (int64_t *)(w + plan.off_bcounts);
+  }
   const char *dbg = getenv("KBISIM_DEBUG_HASH_BITS");
   if (dbg && *dbg) {
     int b = atoi(dbg);
@@ -690,6 +804,7 @@ int kbisim_create(const kbisim_graph *g, int kmax, void *workspace, size_t ws_by
   };
   // Validation (Def. multi-relational-labeled-property-graph as a CSR contract).
   if ((rc = fill_i32(c, (int *)c->err, 4, 0))) return fail(rc);
+  if ((rc = fill_i32(c, (int *)c->dep, 16, 0))) return fail(rc);
   if (n == 0 && m > 0) return fail(KBISIM_EGRAPH);
   if (n > 0) {
     k_validate_rows<<<blocks_for(n + 1, 256), 256, 0, c->stream>>>(n, m, g->row_ptr, c->err, ERR_GRAPH_ROWPTR);
@@ -710,21 +825,45 @@ int kbisim_create(const kbisim_graph *g, int kmax, void *workspace, size_t ws_by
   if ((rc = read_err(c, &err))) return fail(rc);
   if (err) return fail(KBISIM_EGRAPH);
 
-  // Fresh state: tables and scan status start empty.
+  if (num_graphs > 0) {
+    // graph of every vertex; first vertex of the next non-empty graph
+    std::vector<int64_t> nxt((size_t)num_graphs, -1);
+    int64_t after = -1;
+    for (int64_t i = num_graphs - 1; i >= 0; --i) {
+      nxt[(size_t)i] = after;
+      if (vert_off[i + 1] > vert_off[i]) after = vert_off[i];
+    }
+    if (hipMemcpyAsync(c->first, vert_off, 8 * (size_t)(num_graphs + 1), hipMemcpyHostToDevice, c->stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(c->next, nxt.data(), 8 * (size_t)num_graphs, hipMemcpyHostToDevice, c->stream) != hipSuccess)
+      return fail(KBISIM_EHIP);
+    k_graph_ids<<<(unsigned)num_graphs, 256, 0, c->stream>>>((int)num_graphs, c->first, c->gid);
+    if (hipGetLastError() != hipSuccess) return fail(KBISIM_EHIP);
+    if (n > 0) {
+      k_validate_batch<<<blocks_for(n, 256), 256, 0, c->stream>>>((int)n, g->row_ptr, g->col, c->gid, c->err);
+      if (hipGetLastError() != hipSuccess) return fail(KBISIM_EHIP);
+    }
+    if ((rc = read_err(c, &err))) return fail(rc);
+    if (err) return fail(KBISIM_EGRAPH);
+  }
+
+  // Fresh state: tables start empty; empty-signature slots start above any entry.
   if ((rc = fill_u64(c, c->table, (int64_t)plan.tslots, 0))) return fail(rc);
   if ((rc = fill_u64(c, c->ctable, (int64_t)plan.tslots, 0))) return fail(rc);
   if ((rc = fill_u64(c, c->zrep, std::max<int64_t>(n, 1), ~0ULL))) return fail(rc);
 
-  // P0: blocks of equal vertex label sets, numbered by first vertex.
-  if (!g->vlabel) {
+  // P0: blocks of equal vertex label sets, numbered by first vertex; in a
+  // batch the graph id joins the key, so no block spans two graphs.
+  if (!g->vlabel && num_graphs == 0) {
     if ((rc = fill_i32(c, c->p0, n, 0))) return fail(rc);
     c->p0_count = n > 0 ? 1 : 0;
   } else if (n > 0) {
     Schedule ls;
-    if ((rc = build_schedule(c, g->vlabel_ptr, ls))) return fail(rc);
+    LabelSrc src{g->vlabel_ptr, g->vlabel, c->gid};
+    if (!g->vlabel) src = LabelSrc{nullptr, c->gid, nullptr};  // batch without labels: one block per graph
+    if ((rc = build_schedule(c, src.ptr, ls))) return fail(rc);
     int *cnt = c->counters + CNT_STRIDE * (plan.ncounter_steps - 2);
     if ((rc = fill_i32(c, cnt, CNT_STRIDE, 0))) return fail(rc);
-    LabelSrc src{g->vlabel_ptr, g->vlabel};
     int64_t *dcount = c->dcounts + (plan.ncounter_steps - 2);
     if ((rc = run_step(c, src, ls, c->p0, dcount, cnt, true, nullptr))) return fail(rc);
     if (hipMemcpyAsync(&c->p0_count, dcount, 8, hipMemcpyDeviceToHost, c->stream) != hipSuccess)
@@ -740,6 +879,27 @@ int kbisim_create(const kbisim_graph *g, int kmax, void *workspace, size_t ws_by
   return KBISIM_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+int kbisim_workspace_bytes(const kbisim_graph *g, int kmax, size_t *bytes) {
+  int rc = check_sizes(g);
+  if (rc) return rc;
+  if (!bytes || kmax < 0 || kmax > (1 << 20)) return KBISIM_EINVAL;
+  *bytes = make_plan(g->n, g->m, g->vlabel_ptr ? g->nlabels : 0, kmax, 0).total;
+  return KBISIM_OK;
+}
+
+int kbisim_create(const kbisim_graph *g, int kmax, void *workspace, size_t ws_bytes, void *stream, kbisim_ctx **out) {
+  return create_impl(g, kmax, nullptr, workspace, ws_bytes, stream, 0, nullptr, out);
+}
+
+int kbisim_create_tuned(const kbisim_graph *g, int kmax, const kbisim_tuning *tuning, void *workspace,
+                        size_t ws_bytes, void *stream, kbisim_ctx **out) {
+  return create_impl(g, kmax, tuning, workspace, ws_bytes, stream, 0, nullptr, out);
+}
+
 int kbisim_initial(kbisim_ctx *c, int32_t *out_ids, int64_t *out_count) {
   if (!c || !out_count || (c->g.n > 0 && !out_ids)) return KBISIM_EINVAL;
   if (c->g.n > 0) {
@@ -752,12 +912,13 @@ int kbisim_initial(kbisim_ctx *c, int32_t *out_ids, int64_t *out_count) {
 }
 
 int kbisim_refine(kbisim_ctx *c, int k, int32_t *const *out_block_ids, int64_t *out_counts) {
+  if (c && c->num_graphs > 0) return KBISIM_EINVAL;
   return refine_impl(c, nullptr, k, out_block_ids, out_counts);
 }
 
 int kbisim_refine_from(kbisim_ctx *c, const int32_t *pid_i, int k, int32_t *const *out_block_ids,
                        int64_t *out_counts) {
-  if (!c || (c->g.n > 0 && !pid_i)) return KBISIM_EINVAL;
+  if (!c || c->num_graphs > 0 || (c->g.n > 0 && !pid_i)) return KBISIM_EINVAL;
   if (c->g.n > 0) {
     int rc0 = fill_i32(c, (int *)c->err, 1, 0);
     if (rc0) return rc0;
@@ -771,9 +932,17 @@ int kbisim_refine_from(kbisim_ctx *c, const int32_t *pid_i, int k, int32_t *cons
   return refine_impl(c, pid_i, k, out_block_ids, out_counts);
 }
 
+int kbisim_use_graphs(kbisim_ctx *c, int enable) {
+  if (!c) return KBISIM_EINVAL;
+  if (enable && c->stream == nullptr) return KBISIM_EINVAL;  // the null stream cannot be captured
+  c->use_graphs = enable != 0;
+  return KBISIM_OK;
+}
+
 int kbisim_destroy(kbisim_ctx *c) {
   if (c) {
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
   }
   delete c;
   return KBISIM_OK;
@@ -825,6 +994,50 @@ int kbisim_copy_probe(void *dst, const void *src, size_t bytes, void *stream) {
   return KBISIM_OK;
 }
 
+int kbisim_batch_workspace_bytes(const kbisim_graph *u, int64_t num_graphs, int kmax, size_t *bytes) {
+  int rc = check_sizes(u);
+  if (rc) return rc;
+  if (!bytes || num_graphs < 1 || num_graphs >= (int64_t(1) << 31) || kmax < 0 || kmax > (1 << 20))
+    return KBISIM_EINVAL;
+  *bytes = make_plan(u->n, u->m, u->vlabel_ptr ? u->nlabels : 0, kmax, num_graphs).total;
+  return KBISIM_OK;
+}
+
+int kbisim_batch_create(const kbisim_graph *u, int64_t num_graphs, const int64_t *vert_off, int kmax,
+                        const kbisim_tuning *tuning, void *workspace, size_t ws_bytes, void *stream,
+                        kbisim_batch **out) {
+  if (!out || num_graphs < 1 || num_graphs >= (int64_t(1) << 31) || !vert_off) return KBISIM_EINVAL;
+  *out = nullptr;
+  kbisim_ctx *c = nullptr;
+  int rc = create_impl(u, kmax, tuning, workspace, ws_bytes, stream, num_graphs, vert_off, &c);
+  if (rc) return rc;
+  kbisim_batch *b = new (std::nothrow) kbisim_batch();
+  if (!b) {
+    kbisim_destroy(c);
+    return KBISIM_EINTERNAL;
+  }
+  b->c = c;
+  *out = b;
+  return KBISIM_OK;
+}
+
+int kbisim_batch_refine(kbisim_batch *b, int k, int32_t *const *out_ids, int64_t *out_counts) {
+  if (!b) return KBISIM_EINVAL;
+  return refine_impl(b->c, nullptr, k, out_ids, out_counts);
+}
+
+int kbisim_batch_context(kbisim_batch *b, kbisim_ctx **ctx) {
+  if (!b || !ctx) return KBISIM_EINVAL;
+  *ctx = b->c;
+  return KBISIM_OK;
+}
+
+int kbisim_batch_destroy(kbisim_batch *b) {
+  if (b) kbisim_destroy(b->c);
+  delete b;
+  return KBISIM_OK;
+}
+
 const char *kbisim_strerror(int code) {
   switch (code) {
     case KBISIM_OK: return "ok";
@@ -838,6 +1051,6 @@ const char *kbisim_strerror(int code) {
   }
 }
 
-const char *kbisim_version(void) { return "kbisim 0.1 gfx950"; }
+const char *kbisim_version(void) { return "kbisim 0.2 gfx950"; }
 
 }  // extern "C"

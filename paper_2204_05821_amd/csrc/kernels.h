@@ -44,8 +44,7 @@ constexpr int RANGE_VERTS = 256;     // vertices per range workgroup
 constexpr int RANGE_DMAX = 4096;     // rows above RANGE_EDGES get a range of their own; above this, hubs
 constexpr int BLOCK_MAX = RANGE_DMAX;
 constexpr int BLOCK_SLOTS = 8192;    // LDS set slots for exact checks (64 KB)
-constexpr int HUB_CHUNK = 4096;      // entries per hub staging workgroup (16 per thread)
-constexpr int HUB_U = HUB_CHUNK / 256;
+constexpr int HUB_CHUNK = 4096;      // default entries per hub staging workgroup (16 per thread)
 constexpr int HUB_PMAX = 1024;       // partitions per hub at most
 constexpr int HUB_PART_TARGET = 2048;  // expected entries per hub partition
 constexpr int HUB_PSLOTS = 8192;     // LDS set slots per hub partition workgroup
@@ -53,6 +52,15 @@ constexpr int64_t HUB_STAGED_MAX = (int64_t)HUB_PMAX * 4096;  // larger hubs use
 constexpr int HUB_GCHUNK = 8192;     // entries per workgroup in the global-set path
 constexpr int SCAN_ITEMS = 16;       // items per thread in the scan
 constexpr int SCAN_TILE = 256 * SCAN_ITEMS;
+
+// Device-resident epoch state (read by kernels at launch, advanced by
+// k_advance), so a captured sequence of steps can be replayed.
+constexpr int EP_TABLE = 0;    // grouping table epoch, 1..15
+constexpr int EP_CTABLE = 1;   // peeling table epoch, 1..15
+constexpr int EP_ZERO = 2;     // empty-signature epoch, increasing
+constexpr int EP_HUB = 3;      // global hub set epoch, 1..3
+constexpr int EP_CLR_TABLE = 4, EP_CLR_CTABLE = 5, EP_CLR_HUB = 6;
+constexpr u32 ADV_TABLE = 1, ADV_CTABLE = 2, ADV_ZERO = 4, ADV_HUB = 8;
 
 // Error bits reported through the workspace error word.
 constexpr u32 ERR_LOOKUP_MISS = 1u;
@@ -120,10 +128,11 @@ struct GraphSrc {
 struct LabelSrc {
   const int64_t *ptr;  // may be null: one label per vertex
   const int32_t *lab;
+  const int32_t *gid;  // may be null; in a batch, the graph of each vertex (P0 never joins graphs)
   __device__ inline int64_t begin(int v) const { return ptr ? ptr[v] : (int64_t)v; }
   __device__ inline int64_t end(int v) const { return ptr ? ptr[v + 1] : (int64_t)v + 1; }
   __device__ inline u64 pair(int64_t e) const { return (u64)(u32)lab[e]; }
-  __device__ inline u32 own(int) const { return 0u; }
+  __device__ inline u32 own(int v) const { return gid ? (u32)gid[v] : 0u; }
 };
 
 // ---------------------------------------------------------------- wave helpers
@@ -269,9 +278,10 @@ __device__ inline void block_reduce_2(u64 &acc, u32 &cnt, u64 *sh_acc, u32 *sh_c
 // per-vertex sums are formed from the set afterwards.
 template <class Src, int EMAX>
 __global__ void __launch_bounds__(256) k_sig_range(Src src, const Range *__restrict__ ranges, u64 *__restrict__ H,
-                                                   u32 *__restrict__ DC, u64 *table, u64 tmask, u32 epoch,
-                                                   u64 hmask, u64 *zrep, u32 zep) {
+                                                   u32 *__restrict__ DC, u64 *table, u64 tmask,
+                                                   const u32 *__restrict__ dep, u64 hmask, u64 *zrep) {
   constexpr int U = EMAX / 256;
+  const u32 epoch = dep[EP_TABLE], zep = dep[EP_ZERO];
   __shared__ u64 set[2 * EMAX];
   __shared__ u64 acc[RANGE_VERTS];
   __shared__ u32 cnt[RANGE_VERTS];
@@ -420,18 +430,19 @@ struct HubPart {
   int nchunks;
 };
 
-template <class Src>
+template <class Src, int CHUNK>
 __global__ void __launch_bounds__(256) k_hub_stage(Src src, const HubChunk *__restrict__ chunks,
                                                    const int *__restrict__ hubs, u64 *__restrict__ stage,
                                                    int *__restrict__ poff, u32 *err) {
-  __shared__ u64 set[2 * HUB_CHUNK];
+  constexpr int HUB_U = CHUNK / 256;
+  __shared__ u64 set[2 * CHUNK];
   __shared__ int hist[HUB_PMAX + 1];
   __shared__ int wtot[4];
   const HubChunk c = chunks[blockIdx.x];
   const int P = c.parts;
   const int64_t row = src.begin(hubs[c.hub]);
   const int E = (int)(c.e - c.b);
-  for (int i = threadIdx.x; i < 2 * HUB_CHUNK; i += 256) set[i] = EMPTY64;
+  for (int i = threadIdx.x; i < 2 * CHUNK; i += 256) set[i] = EMPTY64;
   for (int i = threadIdx.x; i <= P; i += 256) hist[i] = 0;
   u64 pr[HUB_U];
 #pragma unroll
@@ -446,7 +457,7 @@ __global__ void __launch_bounds__(256) k_hub_stage(Src src, const HubChunk *__re
     rank[u] = -1;
     const u64 p = pr[u];
     if (p == EMPTY64) continue;
-    u32 sl = set_hash(p) & (2 * HUB_CHUNK - 1);
+    u32 sl = set_hash(p) & (2 * CHUNK - 1);
     while (true) {
       const u64 old = atomicCAS(&set[sl], EMPTY64, p);
       if (old == EMPTY64) {
@@ -454,7 +465,7 @@ __global__ void __launch_bounds__(256) k_hub_stage(Src src, const HubChunk *__re
         break;
       }
       if (old == p) break;
-      sl = (sl + 1) & (2 * HUB_CHUNK - 1);
+      sl = (sl + 1) & (2 * CHUNK - 1);
     }
   }
   __syncthreads();
@@ -602,7 +613,8 @@ struct HubGChunk {
 template <class Src>
 __global__ void __launch_bounds__(256) k_sig_hub_global(Src src, const HubGChunk *__restrict__ chunks,
                                                         const int *__restrict__ hubs, u64 *sets, u64 *hub_acc,
-                                                        u32 *hub_cnt, u32 hepoch) {
+                                                        u32 *hub_cnt, const u32 *__restrict__ dep) {
+  const u32 hepoch = dep[EP_HUB];
   __shared__ u64 sh_acc[4];
   __shared__ u32 sh_cnt[4];
   const HubGChunk c = chunks[blockIdx.x];
@@ -636,8 +648,9 @@ __global__ void __launch_bounds__(256) k_sig_hub_global(Src src, const HubGChunk
 
 template <class Src>
 __global__ void k_hub_final(Src src, const int *__restrict__ hubs, int nhub, u64 *hub_acc, u32 *hub_cnt,
-                            u64 *__restrict__ H, u32 *__restrict__ DC, u64 *table, u64 tmask, u32 epoch,
-                            u64 hmask, u64 *zrep, u32 zep) {
+                            u64 *__restrict__ H, u32 *__restrict__ DC, u64 *table, u64 tmask,
+                            const u32 *__restrict__ dep, u64 hmask, u64 *zrep) {
+  const u32 epoch = dep[EP_TABLE], zep = dep[EP_ZERO];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nhub) return;
   const int v = hubs[i];
@@ -662,8 +675,9 @@ __global__ void k_hub_final(Src src, const int *__restrict__ hubs, int nhub, u64
 template <class Src>
 __global__ void __launch_bounds__(256) k_lookup(Src src, int n, const u64 *__restrict__ H,
                                                 const u32 *__restrict__ DC, const u64 *table, u64 tmask,
-                                                u32 epoch, int *__restrict__ rep, int *vcount, int *vlist,
-                                                int *ccount, int *clist, u32 *err, const u64 *zrep, u32 zep) {
+                                                const u32 *__restrict__ dep, int *__restrict__ rep, int *vcount,
+                                                int *vlist, int *ccount, int *clist, u32 *err, const u64 *zrep) {
+  const u32 epoch = dep[EP_TABLE], zep = dep[EP_ZERO];
   __shared__ u64 buf[SMALL_MAX * 256];
   const int t = threadIdx.x;
   const int v = blockIdx.x * 256 + t;
@@ -815,7 +829,8 @@ __global__ void __launch_bounds__(256) k_verify(Src src, const int *__restrict__
 // the rest go to the next round's list.  Every round settles at least one
 // block per hash value, so rounds end.
 __global__ void k_res_insert(const int *__restrict__ count, const int *__restrict__ list, const u64 *__restrict__ H,
-                             u64 *ctable, u64 tmask, u32 epoch) {
+                             u64 *ctable, u64 tmask, const u32 *__restrict__ dep) {
+  const u32 epoch = dep[EP_CTABLE];
   const int total = *count;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
     const int v = list[i];
@@ -826,8 +841,9 @@ __global__ void k_res_insert(const int *__restrict__ count, const int *__restric
 template <class Src>
 __global__ void __launch_bounds__(256) k_res_verify(Src src, const int *__restrict__ count, const int *__restrict__ list,
                                                     const u64 *__restrict__ H, const u32 *__restrict__ DC,
-                                                    const u64 *ctable, u64 tmask, u32 epoch, int *__restrict__ rep,
-                                                    int *next_count, int *next_list, u32 *err) {
+                                                    const u64 *ctable, u64 tmask, const u32 *__restrict__ dep,
+                                                    int *__restrict__ rep, int *next_count, int *next_list, u32 *err) {
+  const u32 epoch = dep[EP_CTABLE];
   __shared__ u64 set[BLOCK_SLOTS];
   __shared__ int sh_flag[2];
   const int total = *count;
@@ -1009,6 +1025,90 @@ __global__ void k_remap(int64_t m, const int *__restrict__ col, const int *__res
 __global__ void k_scatter_rank(int n, const int *__restrict__ pid, const int *__restrict__ rank, int *__restrict__ gpid) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v < n) gpid[rank[v]] = pid[v];
+}
+
+// ---------------------------------------------------------------- batches
+// A batch is the disjoint union of G graphs (vertex ranges [first[g],
+// first[g+1])).  Blocks never span graphs, so each graph's first vertex heads
+// a block and its global id is the number of blocks in earlier graphs:
+// per-graph ids are global ids minus that base.
+__global__ void k_graph_ids(int G, const int64_t *__restrict__ first, int *__restrict__ gid) {
+  const int g = blockIdx.x;
+  if (g >= G) return;
+  for (int64_t v = first[g] + threadIdx.x; v < first[g + 1]; v += blockDim.x) gid[v] = g;
+}
+
+// Every CSR entry must stay inside its row's graph.
+__global__ void k_validate_batch(int n, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+                                 const int *__restrict__ gid, u32 *err) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const int g = gid[v];
+  for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e)
+    if (gid[col[e]] != g) { atomicOr(err, ERR_GRAPH_COL); return; }
+}
+
+__global__ void k_rebase(int n, const int *__restrict__ gid, const int64_t *__restrict__ first,
+                         const int *__restrict__ global_ids, int *__restrict__ out) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  out[v] = global_ids[v] - global_ids[first[gid[v]]];
+}
+
+// counts[g * k + i] for step i; `next[g]` is the first vertex of the next
+// non-empty graph after g, or -1 (then the total count closes the range).
+__global__ void k_batch_counts(int G, const int64_t *__restrict__ first, const int64_t *__restrict__ next,
+                               const int *__restrict__ global_ids, const int64_t *__restrict__ total, int k, int i,
+                               int64_t *__restrict__ counts) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= G) return;
+  int64_t c = 0;
+  if (first[g + 1] > first[g]) {
+    const int64_t base = global_ids[first[g]];
+    const int64_t end = next[g] >= 0 ? (int64_t)global_ids[next[g]] : *total;
+    c = end - base;
+  }
+  counts[(int64_t)g * k + i] = c;
+}
+
+// ---------------------------------------------------------------- epochs
+__global__ void k_advance(u32 *dep, u32 mask) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (mask & ADV_TABLE) {
+    dep[EP_TABLE] = dep[EP_TABLE] % 15u + 1u;
+    dep[EP_CLR_TABLE] = dep[EP_TABLE] == 1u;
+  } else {
+    dep[EP_CLR_TABLE] = 0;
+  }
+  if (mask & ADV_CTABLE) {
+    dep[EP_CTABLE] = dep[EP_CTABLE] % 15u + 1u;
+    dep[EP_CLR_CTABLE] = dep[EP_CTABLE] == 1u;
+  } else {
+    dep[EP_CLR_CTABLE] = 0;
+  }
+  if (mask & ADV_ZERO) dep[EP_ZERO] = dep[EP_ZERO] + 1u;
+  if (mask & ADV_HUB) {
+    dep[EP_HUB] = dep[EP_HUB] % 3u + 1u;
+    dep[EP_CLR_HUB] = dep[EP_HUB] == 1u;
+  } else {
+    dep[EP_CLR_HUB] = 0;
+  }
+}
+
+// Clears the tables whose epoch just wrapped (one launch; exits at once when
+// nothing wrapped).
+__global__ void k_clear_if(const u32 *__restrict__ dep, u64 *table, int64_t tslots, u64 *ctable, u64 *hub_sets,
+                           int64_t hub_slots) {
+  const bool ct = dep[EP_CLR_TABLE] != 0, cc = dep[EP_CLR_CTABLE] != 0, ch = dep[EP_CLR_HUB] != 0;
+  if (!ct && !cc && !ch) return;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (ct)
+    for (int64_t i = i0; i < tslots; i += stride) table[i] = 0;
+  if (cc)
+    for (int64_t i = i0; i < tslots; i += stride) ctable[i] = 0;
+  if (ch)
+    for (int64_t i = i0; i < hub_slots; i += stride) hub_sets[i] = 0;
 }
 
 // ---------------------------------------------------------------- utilities

@@ -1,0 +1,166 @@
+"""GPU tests of the batched form, HIP-graph replay and launch-shape tunings.
+
+Every graph of a batch must get exactly what it gets alone (the disjoint-union
+property), every replay of a captured refinement loop must equal the eager
+result, and every tuning must give identical outputs.  All comparisons are
+against the CPU reference, bit-exact.
+"""
+from __future__ import annotations
+
+import itertools
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+from tests import helpers
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _kb():
+    import paper_2204_05821_amd as kb
+    return kb
+
+
+def ref(g, k):
+    ids, counts = oracle.refine(g, k)
+    return ids, counts
+
+
+def check_batch(graphs, k, label, **kw):
+    kb = _kb()
+    print(f"[batch] {label}: {len(graphs)} graphs, k={k}", flush=True)
+    b = kb.batch_for(graphs, kmax=k, **kw)
+    outs, counts = b.refine(k)
+    torch.cuda.synchronize()
+    got = [o.cpu().numpy() for o in outs]
+    off = b.vert_off
+    for gi, g in enumerate(graphs):
+        exp, ec = ref(g, k)
+        assert counts[gi] == ec, (label, gi, counts[gi], ec)
+        for i in range(k):
+            part = got[i][off[gi]:off[gi + 1]]
+            if not np.array_equal(part, exp[i]):
+                bad = np.nonzero(part != exp[i])[0]
+                raise AssertionError(f"{label}: graph {gi} P{i + 1} differs at {bad[:8]}")
+    b.close()
+
+
+def mixed_graphs(seed=0, count=24):
+    rng = np.random.default_rng(seed)
+    out = []
+    for j in range(count):
+        m = int(np.exp(rng.uniform(np.log(200), np.log(20000))))
+        out.append(graphgen.batch_graph(j, m, seed=seed + 11))
+    return out
+
+
+def test_batch_equals_solo_mixed_sizes():
+    check_batch(mixed_graphs(), 6, "mixed")
+
+
+def test_batch_with_degenerate_members():
+    gs = [graphgen.batch_graph(1, 3000),
+          graphgen.from_edges(1, [], [], None, [3]),
+          graphgen.from_edges(40, [], [], None, np.arange(40) % 3),
+          graphgen.from_edges(5, [0, 1, 2, 3, 4], [0, 1, 2, 3, 4], [0, 1, 0, 1, 0], [1, 1, 1, 1, 1]),
+          graphgen.batch_graph(2, 2500),
+          graphgen.from_edges(0, [], [], None, np.zeros(0, dtype=np.int32)),
+          graphgen.batch_graph(3, 8000)]
+    check_batch(gs, 5, "degenerate")
+
+
+def test_batch_without_vertex_labels():
+    gs = [graphgen.deep(seed=s, n=3000 + 500 * s, avg_degree=1.2) for s in range(5)]
+    for g in gs:
+        g.vlabel = None
+    check_batch(gs, 8, "unlabelled")
+
+
+def test_batch_with_label_sets():
+    gs = [graphgen.rmat_rdf(10 + (s % 3), 8000 + 1000 * s, seed=20 + s, types=30, elabels=20) for s in range(6)]
+    check_batch(gs, 5, "label-sets")
+
+
+def test_batch_with_hubs_and_collisions(monkeypatch):
+    monkeypatch.setenv("KBISIM_DEBUG_HASH_BITS", "12")
+    from tests.test_gpu_parity import tier_graph
+    gs = [tier_graph(seed=7), graphgen.tiny(seed=3, n=2000, m=9000), tier_graph(seed=8, labels=50)]
+    check_batch(gs, 4, "hubs+collisions")
+
+
+def test_batch_rejects_crossing_edges():
+    kb = _kb()
+    a = graphgen.tiny(seed=1, n=100, m=300)
+    b = graphgen.tiny(seed=2, n=100, m=300)
+    rp, col, el, vl, vp, off = kb.union_of([a, b])
+    col = col.copy()
+    col[5] = 150          # an entry of graph 0 pointing into graph 1
+    t = lambda x: None if x is None else torch.from_numpy(x).cuda()
+    with pytest.raises(kb.KbisimError) as ei:
+        kb.Batch(t(rp), t(col), t(el), t(vl), t(vp), off, kmax=2)
+    assert ei.value.code == kb.EGRAPH
+
+
+def test_batch_graph_replay():
+    check_batch(mixed_graphs(seed=3, count=16), 7, "batch-graphs", graphs_mode=True)
+
+
+# ------------------------------------------------------------------ HIP graphs
+
+def test_graph_replays_match_eager():
+    kb = _kb()
+    g = graphgen.deep(seed=21, n=12000, avg_degree=1.4)
+    exp, ec = ref(g, 9)
+    r = kb.refiner_for(g, kmax=9)
+    kb._lib().kbisim_use_graphs(r._ctx, 0)
+    rg = kb.Refiner(*kb.to_device(g), kmax=9, graphs=True)
+    outs = rg.alloc_outputs(9)
+    for rep in range(4):
+        ids, counts = rg.refine(9, out=outs)          # capture once, then replay
+        assert counts == ec
+        for a, b in zip(ids, exp):
+            assert np.array_equal(a.cpu().numpy(), b)
+        # eager work on the same device between replays
+        ids2, c2 = r.refine(3)
+        assert c2 == ec[:3]
+    # a different output set and k: a second captured graph
+    ids, counts = rg.refine(4)
+    assert counts == ec[:4]
+    rg.close()
+    r.close()
+
+
+def test_graph_replay_with_collision_fallback(monkeypatch):
+    monkeypatch.setenv("KBISIM_DEBUG_HASH_BITS", "5")
+    kb = _kb()
+    g = graphgen.tiny(seed=4, n=3000, m=12000)
+    exp, ec = ref(g, 5)
+    rg = kb.Refiner(*kb.to_device(g), kmax=5, graphs=True)
+    outs = rg.alloc_outputs(5)
+    for rep in range(3):
+        ids, counts = rg.refine(5, out=outs)
+        assert counts == ec
+        for a, b in zip(ids, exp):
+            assert np.array_equal(a.cpu().numpy(), b)
+    rg.close()
+
+
+# ------------------------------------------------------------------ tunings
+
+@pytest.mark.parametrize("re,hc,hp", list(itertools.product([1024, 2048], [2048, 4096], [1024, 2048])))
+def test_every_tuning_gives_identical_results(re, hc, hp):
+    kb = _kb()
+    from tests.test_gpu_parity import tier_graph
+    for g in [graphgen.rmat(14, 250_000, seed=5), tier_graph(seed=9)]:
+        exp, ec = ref(g, 4)
+        r = kb.Refiner(*kb.to_device(g), kmax=4, tuning=kb.tuning(re, hc, hp))
+        ids, counts = r.refine(4)
+        assert counts == ec
+        for a, b in zip(ids, exp):
+            assert np.array_equal(a.cpu().numpy(), b)
+        r.close()
