@@ -14,7 +14,13 @@ its 100M-edge class.
 
 Prints one JSON line with the throughput, a roofline entry for the dominant
 kernel (timed with HIP events inside the timed region) and the CPU reference
-timed on a bounded sample of the same workload.
+timed on a bounded sample of the same workload.  With --mode all (the
+default) the line also carries the batched form (4,096 graphs, edge counts
+log-uniform 1k-2M, half uniform-random and half RMAT, k = 10, autotuned
+launch shapes, against per-graph plain calls) and the served form (Poisson
+arrivals at 200 jobs/s of RMAT jobs with 10k-50M edges and k uniform in
+1..10 under a 200 GB budget: p50/p99 latency and jobs/s, and the capacity of
+the continuous-batching server against a one-job-at-a-time server).
 """
 from __future__ import annotations
 
@@ -123,52 +129,31 @@ def cpu_baseline(g, w, max_iters: int = 1):
             "counts": counts}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="rmat_s23_m100M_k10", choices=sorted(WORKLOADS))
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-profile", action="store_true", help="skip per-kernel event timing")
-    ap.add_argument("--copy-probe-mib", type=int, default=0,
-                    help="only run the library's streaming copy kernel on this many MiB (bandwidth and counter "
-                         "calibration) and print its rate")
-    args = ap.parse_args()
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU; a multi-GPU figure is not produced "
-              "(the sharding design is described in the design notes).", file=sys.stderr)
-        sys.exit(2)
-
-    import torch
-    import paper_2204_05821_amd as kb
-
-    if args.copy_probe_mib:
-        nbytes = args.copy_probe_mib << 20
-        src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
-        dst = torch.empty_like(src)
+def copy_probe(kb, torch, mib):
+    nbytes = mib << 20
+    src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    kb.copy_probe(dst, src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 10
+    e0.record()
+    for _ in range(reps):
         kb.copy_probe(dst, src)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        reps = 10
-        e0.record()
-        for _ in range(reps):
-            kb.copy_probe(dst, src)
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / reps
-        assert torch.equal(dst, src)
-        print(json.dumps({"copy_probe_bytes": nbytes, "ms": ms, "GBs_read_plus_write": 2 * nbytes / ms / 1e6}),
-              flush=True)
-        return
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    assert torch.equal(dst, src)
+    return {"copy_probe_bytes": nbytes, "ms": ms, "GBs_read_plus_write": 2 * nbytes / ms / 1e6}
 
+
+def run_plain(args, kb, torch):
     w = WORKLOADS[args.workload]
     k = w["k"]
     t0 = time.perf_counter()
     g = make_graph(w)
     log(f"[bench] generated {args.workload}: n={g.n} m={g.m} in {time.perf_counter() - t0:.1f}s")
     dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
     rp, col, el, vl, vp = kb.to_device(g, dev)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -219,6 +204,8 @@ def main():
                     "algorithmic_bytes_per_launch": ab, "avg_launch_ms": round(avg, 5)}
     b_alg = 12.0 * g.m + 16.0 * g.n
     step_gbs = b_alg * k / (ms_per_step / 1e3) / 1e9
+    r.close()
+    del rp, col, el, vl, vp, outs, r
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -228,7 +215,7 @@ def main():
         if cpu.pop("counts")[0] != counts[0]:
             log("[bench] WARNING: CPU reference count differs from the GPU count at iteration 1")
 
-    res = {
+    return {
         "metric": "edge-iterations/sec at k=10 (plain)",
         "value": value,
         "unit": "edge-iterations/s",
@@ -252,7 +239,216 @@ def main():
         "kernels": kernels,
         "tiers": tiers,
     }
-    r.close()
+
+
+def run_batched(args, kb, torch):
+    """4,096 graphs as one batch (captured k-loop, autotuned shapes) against per-graph plain calls."""
+    import numpy as np
+    import graphgen
+    from paper_2204_05821_amd import tune
+    k = 10
+    t0 = time.perf_counter()
+    sizes = graphgen.batch_sizes(args.batch_graphs)
+    graphs = [graphgen.batch_graph(i, m) for i, m in enumerate(sizes)]
+    m_total = sum(g.m for g in graphs)
+    log(f"[batched] generated {len(graphs)} graphs, {m_total} edges in {time.perf_counter() - t0:.1f}s")
+    t0 = time.perf_counter()
+    rp, col, el, vl, vp, off = kb.union_of(graphs)
+    d = [None if x is None else torch.from_numpy(x).cuda() for x in (rp, col, el, vl, vp)]
+    torch.cuda.synchronize()
+    del rp, col, el, vl, vp
+    log(f"[batched] union on device in {time.perf_counter() - t0:.1f}s")
+
+    holder = {}
+
+    def make(cand):
+        b = kb.Batch(*d, off, kmax=k, tuning=kb.tuning(**cand), graphs=True)
+        holder["outs"] = holder.get("outs") or b.alloc_outputs(k)
+        return b
+
+    def run(b):
+        return b.refine(k, out=holder["outs"])
+
+    t0 = time.perf_counter()
+    best, report = tune.autotune(make, run, key="batch|" + tune.degree_signature(d[0].cpu().numpy()), reps=1,
+                                 cache_path=args.tune_cache)
+    log(f"[batched] autotune {time.perf_counter() - t0:.1f}s: best {best}; {report['ms']}")
+    t0 = time.perf_counter()
+    b = kb.Batch(*d, off, kmax=k, tuning=kb.tuning(**best), graphs=True)
+    torch.cuda.synchronize()
+    create_ms = (time.perf_counter() - t0) * 1e3
+    outs = holder["outs"]
+    for _ in range(2):
+        _, counts = b.refine(k, out=outs)
+    reps = args.batch_steps
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        _, counts = b.refine(k, out=outs)
+    torch.cuda.synchronize()
+    batched_s = (time.perf_counter() - t0) / reps
+    packed = [o.clone() for o in outs]
+    b.close()
+    del b, holder, d, outs
+    torch.cuda.empty_cache()
+    log(f"[batched] batched: {batched_s * 1e3:.1f} ms per k={k} pass, create {create_ms:.0f} ms")
+
+    # per-graph plain calls: one context per graph, created before timing
+    t0 = time.perf_counter()
+    refs = [kb.refiner_for(g, kmax=k) for g in graphs]
+    gouts = [r.alloc_outputs(k) for r in refs]
+    torch.cuda.synchronize()
+    log(f"[batched] {len(refs)} per-graph contexts in {time.perf_counter() - t0:.1f}s")
+    for r, o in zip(refs, gouts):
+        r.refine(k, out=o)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pg_counts = None
+    for _ in range(reps):
+        pg_counts = [r.refine(k, out=o)[1] for r, o in zip(refs, gouts)]
+    torch.cuda.synchronize()
+    plain_s = (time.perf_counter() - t0) / reps
+    same = pg_counts == counts
+    for gi in range(0, len(graphs), max(1, len(graphs) // 64)):
+        for i in range(k):
+            if not torch.equal(gouts[gi][i], packed[i][int(off[gi]):int(off[gi + 1])]):
+                same = False
+    for r in refs:
+        r.close()
+    del refs, gouts, packed
+    torch.cuda.empty_cache()
+    log(f"[batched] per-graph plain: {plain_s * 1e3:.1f} ms per pass; identical results: {same}")
+    return {"workload": f"batch_{len(graphs)}_graphs_m1k-2M_k10", "graphs": len(graphs), "m_total": m_total,
+            "k": k, "value": m_total * k / batched_s, "unit": "edge-iterations/s",
+            "ms_per_pass": batched_s * 1e3, "per_graph_plain": {"value": m_total * k / plain_s,
+                                                                 "ms_per_pass": plain_s * 1e3},
+            "speedup_vs_per_graph": plain_s / batched_s, "identical_to_per_graph": bool(same),
+            "tuning": best, "autotune_ms": report["ms"], "create_ms": round(create_ms, 1),
+            "recipe": "graph g: m_g log-uniform 1e3..2e6; even g uniform-random n=max(16,m/8), odd g RMAT "
+                      "(0.57,0.19,0.19,0.05) scale ceil(log2(m/8)); 16 vertex and 32 edge labels uniform"}
+
+
+def run_serve(args, kb, torch):
+    """Poisson arrivals under a 200 GB budget; capacity against one-job-at-a-time."""
+    import random
+    import graphgen
+    from paper_2204_05821_amd import serve
+    t0 = time.perf_counter()
+    pool_h = [graphgen.serving_pool_graph(j) for j in range(args.serve_pool)]
+    pool = [serve.DeviceBackend.pin(g) for g in pool_h]
+    del pool_h
+    pool_m = [g.m for g in pool]
+    log(f"[serve] pool of {len(pool)} graphs ({sum(pool_m)} edges) pinned in {time.perf_counter() - t0:.1f}s")
+    budget = 200 * 10**9
+    rnd = random.Random(11)
+
+    def draw_jobs(count):
+        return [(rnd.randrange(len(pool)), rnd.randint(1, 10)) for _ in range(count)]
+
+    def closed_loop(server_cls, jobs, **kw):
+        be = serve.DeviceBackend(streams=4, keep_outputs=False)
+        srv = server_cls(be, budget, **kw).start()
+        t = time.perf_counter()
+        js = [srv.submit(pool[gi], k) for gi, k in jobs]
+        srv.stop()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t
+        err = [j.error for j in js if j.error is not None]
+        if err:
+            raise err[0]
+        return wall, [j.counts for j in js], srv.stats()
+
+    # warm-up (library load, allocator, first contexts)
+    closed_loop(serve.Server, draw_jobs(16))
+    # capacity: the same job list through both servers
+    jobs = draw_jobs(args.serve_capacity_jobs)
+    ek = sum(pool_m[gi] * k for gi, k in jobs)
+    cont_s, cont_counts, cont_st = closed_loop(serve.Server, jobs)
+    fifo_s, fifo_counts, _ = closed_loop(serve.FifoServer, jobs)
+    log(f"[serve] capacity on {len(jobs)} jobs: continuous {cont_s:.2f}s, one-at-a-time {fifo_s:.2f}s, "
+        f"identical counts {cont_counts == fifo_counts}")
+
+    # open loop: Poisson arrivals at the offered rate
+    be = serve.DeviceBackend(streams=4, keep_outputs=False)
+    srv = serve.Server(be, budget).start()
+    t_end = time.perf_counter() + args.serve_seconds
+    submitted = []
+    nxt = time.perf_counter()
+    while True:
+        nxt += rnd.expovariate(args.serve_rate)
+        if nxt > t_end:
+            break
+        dt = nxt - time.perf_counter()
+        if dt > 0:
+            time.sleep(dt)
+        gi, k = rnd.randrange(len(pool)), rnd.randint(1, 10)
+        submitted.append((srv.submit(pool[gi], k), pool_m[gi]))
+    srv.stop()
+    torch.cuda.synchronize()
+    st = srv.stats()
+    js = [j for j, _ in submitted]
+    first = min(j.arrival for j in js)
+    last = max(j.finished for j in js)
+    ek_open = sum(m * j.k for j, m in submitted)
+    log(f"[serve] Poisson {args.serve_rate}/s for {args.serve_seconds}s: {st}")
+    return {"workload": "serve_poisson200_rmat_m10k-50M_k1-10", "rate_per_s": args.serve_rate,
+            "seconds": args.serve_seconds, "jobs": len(js), "errors": st["errors"] + st["rejected"],
+            "p50_ms": st["p50_s"] * 1e3, "p99_ms": st["p99_s"] * 1e3,
+            "p50_admit_prepare_ms": st["p50_admit_prepare_s"] * 1e3,
+            "jobs_per_s": len(js) / (last - first), "edge_iterations_per_s": ek_open / (last - first),
+            "mean_jobs_per_tick": st["mean_jobs_per_tick"], "units": st["units"],
+            "peak_budget_bytes": st["peak_bytes"], "budget_bytes": budget,
+            "capacity": {"jobs": len(jobs), "continuous_jobs_per_s": len(jobs) / cont_s,
+                         "one_at_a_time_jobs_per_s": len(jobs) / fifo_s,
+                         "continuous_edge_iterations_per_s": ek / cont_s,
+                         "one_at_a_time_edge_iterations_per_s": ek / fifo_s,
+                         "speedup": fifo_s / cont_s, "identical_counts": cont_counts == fifo_counts,
+                         "mean_jobs_per_tick": cont_st["mean_jobs_per_tick"]},
+            "pool": {"graphs": len(pool), "edges": sum(pool_m)},
+            "latency": "arrival to counts on the host and ids on the device, H2D of the CSR included"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--mode", default="all", choices=["all", "plain", "batched", "serve"])
+    ap.add_argument("--workload", default="rmat_s23_m100M_k10", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true", help="skip per-kernel event timing")
+    ap.add_argument("--batch-graphs", type=int, default=4096)
+    ap.add_argument("--batch-steps", type=int, default=3)
+    ap.add_argument("--tune-cache", default=None, help="JSON file for autotuner choices (default: none kept)")
+    ap.add_argument("--serve-pool", type=int, default=64)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-seconds", type=float, default=20.0)
+    ap.add_argument("--serve-capacity-jobs", type=int, default=200)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run the library's streaming copy kernel on this many MiB (bandwidth and counter "
+                         "calibration) and print its rate")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on one GPU; a multi-GPU figure is not produced "
+              "(the sharding design is described in the design notes).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2204_05821_amd as kb
+    torch.cuda.set_device(torch.device("cuda:0"))
+
+    if args.copy_probe_mib:
+        print(json.dumps(copy_probe(kb, torch, args.copy_probe_mib)), flush=True)
+        return
+    res = None
+    if args.mode in ("all", "plain"):
+        res = run_plain(args, kb, torch)
+    if args.mode in ("all", "batched"):
+        bres = run_batched(args, kb, torch)
+        res = bres if res is None else dict(res, batched=bres)
+    if args.mode in ("all", "serve"):
+        sres = run_serve(args, kb, torch)
+        res = sres if res is None else dict(res, served=sres)
     print(json.dumps(res), flush=True)
 
 

@@ -167,6 +167,16 @@ int kbisim_batch_create(const kbisim_graph *u, int64_t num_graphs, const int64_t
  * P_{i+1}.  Synchronises once at the end.                                   */
 int kbisim_batch_refine(kbisim_batch *b, int k, int32_t *const *out_ids, int64_t *out_counts);
 
+/* Single steps of a batch, for schedulers that advance many batches and
+ * contexts one step at a time.  Step i (0 <= i < kmax, issued in order
+ * 0, 1, 2, ...) writes the per-graph ids of P_{i+1} into out_ids (device
+ * int32 [n], union order); the batch keeps P_i itself.  _async only
+ * enqueues; _result synchronises, settles any unresolved hash collision of
+ * the step and writes out_counts (HOST int64 [num_graphs]): graph g's
+ * block count in P_{i+1}.                                                   */
+int kbisim_batch_step_async(kbisim_batch *b, int i, int32_t *out_ids);
+int kbisim_batch_step_result(kbisim_batch *b, int i, int32_t *out_ids, int64_t *out_counts);
+
 /* The context that runs the batch (for kbisim_use_graphs, profiling and
  * schedule statistics).  It is owned by the batch.                         */
 int kbisim_batch_context(kbisim_batch *b, kbisim_ctx **ctx);
@@ -211,6 +221,20 @@ int kbisim_schedule_info(kbisim_ctx *c, int64_t *info);
  * library's streaming copy kernel, enqueued on `stream`.  Used to measure
  * achievable HBM bandwidth and to calibrate hardware byte counters.        */
 int kbisim_copy_probe(void *dst, const void *src, size_t bytes, void *stream);
+
+/* ---- single steps (for schedulers that interleave many contexts) --------- */
+
+/* Enqueue step i (0 <= i < kmax): P_{i+1} from prev into out (device int32
+ * [n]) on the context's stream, without synchronising.  Steps of one context
+ * must be issued in order i = 0, 1, 2, ... with prev = P_0 (NULL) for i = 0
+ * and prev = the previous step's out afterwards; out must not alias prev.
+ * The count stays on the device until kbisim_step_result.                   */
+int kbisim_step_async(kbisim_ctx *c, int i, const int32_t *prev, int32_t *out);
+
+/* Finish step i (same i, prev, out): synchronises the stream, recomputes the
+ * step with host-driven collision peeling if its in-loop round left a
+ * collision unsettled, and returns the block count of P_{i+1} in *count.   */
+int kbisim_step_result(kbisim_ctx *c, int i, const int32_t *prev, int32_t *out, int64_t *count);
 
 /* Release the context (host memory only; the workspace stays the caller's). */
 int kbisim_destroy(kbisim_ctx *c);

@@ -71,10 +71,14 @@ def _lib():
     lib.kbisim_create_tuned.argtypes = [ctypes.POINTER(_Graph), i32, ctypes.POINTER(Tuning), vp, sz, vp,
                                         ctypes.POINTER(vp)]
     lib.kbisim_use_graphs.argtypes = [vp, i32]
+    lib.kbisim_step_async.argtypes = [vp, i32, vp, vp]
+    lib.kbisim_step_result.argtypes = [vp, i32, vp, vp, ctypes.POINTER(i64)]
     lib.kbisim_batch_workspace_bytes.argtypes = [ctypes.POINTER(_Graph), i64, i32, ctypes.POINTER(sz)]
     lib.kbisim_batch_create.argtypes = [ctypes.POINTER(_Graph), i64, vp, i32, ctypes.POINTER(Tuning), vp, sz, vp,
                                         ctypes.POINTER(vp)]
     lib.kbisim_batch_refine.argtypes = [vp, i32, ctypes.POINTER(vp), vp]
+    lib.kbisim_batch_step_async.argtypes = [vp, i32, vp]
+    lib.kbisim_batch_step_result.argtypes = [vp, i32, vp, vp]
     lib.kbisim_batch_context.argtypes = [vp, ctypes.POINTER(vp)]
     lib.kbisim_batch_destroy.argtypes = [vp]
     lib.kbisim_initial.argtypes = [vp, vp, ctypes.POINTER(i64)]
@@ -93,7 +97,8 @@ def _lib():
     for f in ("kbisim_workspace_bytes", "kbisim_create", "kbisim_initial", "kbisim_refine", "kbisim_refine_from",
               "kbisim_destroy", "kbisim_profile_enable", "kbisim_profile_read", "kbisim_schedule_info",
               "kbisim_copy_probe", "kbisim_create_tuned", "kbisim_use_graphs", "kbisim_batch_workspace_bytes",
-              "kbisim_batch_create", "kbisim_batch_refine", "kbisim_batch_context", "kbisim_batch_destroy"):
+              "kbisim_batch_create", "kbisim_batch_refine", "kbisim_batch_context", "kbisim_batch_destroy",
+              "kbisim_step_async", "kbisim_step_result", "kbisim_batch_step_async", "kbisim_batch_step_result"):
         getattr(lib, f).restype = i32
     _LIB = lib
     return lib
@@ -233,6 +238,20 @@ class Refiner:
     def alloc_outputs(self, k: int) -> List[torch.Tensor]:
         return [torch.empty(self.n, dtype=torch.int32, device=self.device) for _ in range(k)]
 
+    def step_async(self, i: int, prev: Optional[torch.Tensor], out: torch.Tensor) -> None:
+        """Enqueue step i (P_{i+1} from prev, None = P0) without synchronising."""
+        rc = _lib().kbisim_step_async(self._ctx, i, _ptr(prev), _ptr(out))
+        if rc:
+            raise KbisimError(rc, "kbisim_step_async")
+
+    def step_result(self, i: int, prev: Optional[torch.Tensor], out: torch.Tensor) -> int:
+        """Finish step i (synchronises the context's stream); the block count of P_{i+1}."""
+        cnt = ctypes.c_int64(0)
+        rc = _lib().kbisim_step_result(self._ctx, i, _ptr(prev), _ptr(out), ctypes.byref(cnt))
+        if rc:
+            raise KbisimError(rc, "kbisim_step_result")
+        return int(cnt.value)
+
     def refine(self, k: int, out: Optional[Sequence[torch.Tensor]] = None,
                start: Optional[torch.Tensor] = None) -> Tuple[List[torch.Tensor], List[int]]:
         """P_1..P_k (or P_{i+1}.. from ``start`` = P_i) and their block counts."""
@@ -359,6 +378,20 @@ class Batch:
             raise KbisimError(rc, "kbisim_batch_refine")
         cl = [[int(counts[g * k + i]) for i in range(k)] for g in range(self.num_graphs)]
         return list(out[:k]), cl
+
+    def step_async(self, i: int, out: torch.Tensor) -> None:
+        """Enqueue step i (per-graph ids of P_{i+1} into out) without synchronising."""
+        rc = _lib().kbisim_batch_step_async(self._b, i, _ptr(out))
+        if rc:
+            raise KbisimError(rc, "kbisim_batch_step_async")
+
+    def step_result(self, i: int, out: torch.Tensor) -> List[int]:
+        """Finish step i; per-graph block counts of P_{i+1}."""
+        counts = (ctypes.c_int64 * max(self.num_graphs, 1))()
+        rc = _lib().kbisim_batch_step_result(self._b, i, _ptr(out), counts)
+        if rc:
+            raise KbisimError(rc, "kbisim_batch_step_result")
+        return [int(counts[g]) for g in range(self.num_graphs)]
 
     def profile(self, enable: bool = True) -> None:
         rc = _lib().kbisim_profile_enable(self._ctx, 1 if enable else 0)

@@ -592,13 +592,18 @@ int run_step(kbisim_ctx *c, const Src &src, const Schedule &s, int *out, int64_t
 // Enqueue steps [i0, k) starting from partition `prev` (no host
 // synchronisation unless careful).  In a batch, step i refines into an
 // internal buffer of global ids and writes the caller's per-graph ids and
-// counts.
-int enqueue_steps(kbisim_ctx *c, const int32_t *prev, int i0, int k, int32_t *const *out, bool careful) {
+// counts (graph g's count of step i at bcounts[g * cstride + i]).  scatter:
+// copy prev into the rank-ordered buffer first (false only when the previous
+// step of this context already left it there).
+int enqueue_steps(kbisim_ctx *c, const int32_t *prev, int i0, int k, int32_t *const *out, bool careful,
+                  int cstride, bool scatter = true) {
   const int n = (int)c->g.n;
   const bool batch = c->num_graphs > 0;
   int rc = 0;
-  k_scatter_rank<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, prev, c->rank, c->gpid[i0 & 1]);
-  LAUNCH_CHECK();
+  if (scatter) {
+    k_scatter_rank<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, prev, c->rank, c->gpid[i0 & 1]);
+    LAUNCH_CHECK();
+  }
   for (int i = i0; i < k; ++i) {
     if (careful && (rc = fill_i32(c, c->counters + CNT_STRIDE * i, CNT_STRIDE, 0))) return rc;
     int *dst = batch ? c->ibuf[i & 1] : out[i];
@@ -609,7 +614,7 @@ int enqueue_steps(kbisim_ctx *c, const int32_t *prev, int i0, int k, int32_t *co
       k_rebase<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, c->gid, c->first, dst, out[i]);
       LAUNCH_CHECK();
       k_batch_counts<<<blocks_for(c->num_graphs, 256), 256, 0, c->stream>>>((int)c->num_graphs, c->first, c->next,
-                                                                            dst, &c->dcounts[i], k, i, c->bcounts);
+                                                                            dst, &c->dcounts[i], cstride, i, c->bcounts);
       LAUNCH_CHECK();
     }
     prev = dst;
@@ -645,7 +650,7 @@ int refine_impl(kbisim_ctx *c, const int32_t *start, int k, int32_t *const *out,
       HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
       int rc1 = fill_i32(c, c->counters, (int64_t)CNT_STRIDE * k, 0);
       if (!rc1) rc1 = fill_i32(c, (int *)c->err, 1, 0);
-      if (!rc1) rc1 = enqueue_steps(c, p0, 0, k, out, false);
+      if (!rc1) rc1 = enqueue_steps(c, p0, 0, k, out, false, k);
       hipGraph_t graph = nullptr;
       hipError_t e = hipStreamEndCapture(c->stream, &graph);
       if (rc1) {
@@ -663,7 +668,7 @@ int refine_impl(kbisim_ctx *c, const int32_t *start, int k, int32_t *const *out,
   } else {
     if ((rc = fill_i32(c, c->counters, (int64_t)CNT_STRIDE * k, 0))) return rc;
     if ((rc = fill_i32(c, (int *)c->err, 1, 0))) return rc;
-    if ((rc = enqueue_steps(c, p0, 0, k, out, false))) return rc;
+    if ((rc = enqueue_steps(c, p0, 0, k, out, false, k))) return rc;
   }
   std::vector<int> hc((size_t)CNT_STRIDE * k);
   u32 err = 0;
@@ -680,7 +685,7 @@ int refine_impl(kbisim_ctx *c, const int32_t *start, int k, int32_t *const *out,
     }
   if (first_bad >= 0) {
     const int32_t *prev = first_bad == 0 ? p0 : (batch ? c->ibuf[(first_bad - 1) & 1] : out[first_bad - 1]);
-    if ((rc = enqueue_steps(c, prev, first_bad, k, out, true))) return rc;
+    if ((rc = enqueue_steps(c, prev, first_bad, k, out, true, k))) return rc;
     HIP_TRY(hipMemcpyAsync(&err, c->err, sizeof err, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     prof_collect(c);
@@ -932,6 +937,65 @@ int kbisim_refine_from(kbisim_ctx *c, const int32_t *pid_i, int k, int32_t *cons
   return refine_impl(c, pid_i, k, out_block_ids, out_counts);
 }
 
+// Single steps.  Step i reads P_i (prev, P0 for i = 0; a batch keeps its own
+// global-id copy) and writes P_{i+1} into out; the rank-ordered copy of the
+// partition left by step i-1 is reused, so steps of one context go in order.
+int step_async_impl(kbisim_ctx *c, int i, const int32_t *prev, int32_t *out) {
+  if (!c || i < 0 || i >= c->kmax) return KBISIM_EINVAL;
+  const bool batch = c->num_graphs > 0;
+  if (c->g.n == 0) return KBISIM_OK;
+  if (!out || (!batch && i > 0 && !prev) || (const int32_t *)out == prev) return KBISIM_EINVAL;
+  const int32_t *p = i == 0 ? c->p0 : (batch ? c->ibuf[(i - 1) & 1] : prev);
+  int rc = 0;
+  if (i == 0 && (rc = fill_i32(c, (int *)c->err, 1, 0))) return rc;
+  if ((rc = fill_i32(c, c->counters + CNT_STRIDE * i, CNT_STRIDE, 0))) return rc;
+  std::vector<int32_t *> o((size_t)i + 1, out);  // indexed by step number
+  return enqueue_steps(c, p, i, i + 1, o.data(), false, c->kmax, i == 0);
+}
+
+int step_result_impl(kbisim_ctx *c, int i, const int32_t *prev, int32_t *out) {
+  if (!c || i < 0 || i >= c->kmax) return KBISIM_EINVAL;
+  const bool batch = c->num_graphs > 0;
+  if (c->g.n == 0) return KBISIM_OK;
+  if (!out || (!batch && i > 0 && !prev)) return KBISIM_EINVAL;
+  const int32_t *p = i == 0 ? c->p0 : (batch ? c->ibuf[(i - 1) & 1] : prev);
+  int left = 0;
+  u32 err = 0;
+  HIP_TRY(hipMemcpyAsync(&left, c->counters + CNT_STRIDE * i + 2, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipMemcpyAsync(&err, c->err, sizeof err, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  prof_collect(c);
+  if (err) return KBISIM_EINTERNAL;
+  if (left) {
+    std::vector<int32_t *> o((size_t)i + 1, out);
+    int rc = enqueue_steps(c, p, i, i + 1, o.data(), true, c->kmax, true);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(&err, c->err, sizeof err, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    prof_collect(c);
+    if (err) return KBISIM_EINTERNAL;
+  }
+  return KBISIM_OK;
+}
+
+int kbisim_step_async(kbisim_ctx *c, int i, const int32_t *prev, int32_t *out) {
+  if (!c || c->num_graphs > 0) return KBISIM_EINVAL;
+  return step_async_impl(c, i, prev, out);
+}
+
+int kbisim_step_result(kbisim_ctx *c, int i, const int32_t *prev, int32_t *out, int64_t *count) {
+  if (!c || c->num_graphs > 0 || !count) return KBISIM_EINVAL;
+  int rc = step_result_impl(c, i, prev, out);
+  if (rc) return rc;
+  if (c->g.n == 0) {
+    *count = 0;
+    return KBISIM_OK;
+  }
+  HIP_TRY(hipMemcpyAsync(count, &c->dcounts[i], 8, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return KBISIM_OK;
+}
+
 int kbisim_use_graphs(kbisim_ctx *c, int enable) {
   if (!c) return KBISIM_EINVAL;
   if (enable && c->stream == nullptr) return KBISIM_EINVAL;  // the null stream cannot be captured
@@ -1024,6 +1088,28 @@ int kbisim_batch_create(const kbisim_graph *u, int64_t num_graphs, const int64_t
 int kbisim_batch_refine(kbisim_batch *b, int k, int32_t *const *out_ids, int64_t *out_counts) {
   if (!b) return KBISIM_EINVAL;
   return refine_impl(b->c, nullptr, k, out_ids, out_counts);
+}
+
+int kbisim_batch_step_async(kbisim_batch *b, int i, int32_t *out_ids) {
+  if (!b) return KBISIM_EINVAL;
+  return step_async_impl(b->c, i, nullptr, out_ids);
+}
+
+int kbisim_batch_step_result(kbisim_batch *b, int i, int32_t *out_ids, int64_t *out_counts) {
+  if (!b || !out_counts) return KBISIM_EINVAL;
+  kbisim_ctx *c = b->c;
+  int rc = step_result_impl(c, i, nullptr, out_ids);
+  if (rc) return rc;
+  const int64_t G = c->num_graphs;
+  if (c->g.n == 0) {
+    for (int64_t g = 0; g < G; ++g) out_counts[g] = 0;
+    return KBISIM_OK;
+  }
+  // column i of the [graph][kmax] count table
+  HIP_TRY(hipMemcpy2DAsync(out_counts, sizeof(int64_t), c->bcounts + i, sizeof(int64_t) * (size_t)c->kmax,
+                           sizeof(int64_t), (size_t)G, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return KBISIM_OK;
 }
 
 int kbisim_batch_context(kbisim_batch *b, kbisim_ctx **ctx) {

@@ -164,3 +164,53 @@ def test_every_tuning_gives_identical_results(re, hc, hp):
         for a, b in zip(ids, exp):
             assert np.array_equal(a.cpu().numpy(), b)
         r.close()
+
+
+# ------------------------------------------------------------------ single steps
+
+def _stepwise_batch(graphs, k):
+    kb = _kb()
+    b = kb.batch_for(graphs, kmax=k)
+    outs = b.alloc_outputs(k)
+    counts = []
+    for i in range(k):
+        b.step_async(i, outs[i])
+        counts.append(b.step_result(i, outs[i]))
+    torch.cuda.synchronize()
+    got = [o.cpu().numpy() for o in outs]
+    off = b.vert_off
+    b.close()
+    return got, counts, off
+
+
+@pytest.mark.parametrize("bits", [None, "6"])
+def test_batch_single_steps_equal_reference(bits, monkeypatch):
+    if bits:
+        monkeypatch.setenv("KBISIM_DEBUG_HASH_BITS", bits)
+    graphs = mixed_graphs(seed=5, count=10)
+    got, counts, off = _stepwise_batch(graphs, 6)
+    for gi, g in enumerate(graphs):
+        exp, ec = ref(g, 6)
+        assert [counts[i][gi] for i in range(6)] == ec
+        for i in range(6):
+            assert np.array_equal(got[i][off[gi]:off[gi + 1]], exp[i]), (gi, i)
+
+
+@pytest.mark.parametrize("bits", [None, "5"])
+def test_solo_single_steps_equal_reference(bits, monkeypatch):
+    if bits:
+        monkeypatch.setenv("KBISIM_DEBUG_HASH_BITS", bits)
+    kb = _kb()
+    g = graphgen.tiny(seed=6, n=4000, m=20000)
+    exp, ec = ref(g, 7)
+    r = kb.refiner_for(g, kmax=7)
+    outs = r.alloc_outputs(7)
+    for rep in range(2):
+        counts = []
+        for i in range(7):
+            r.step_async(i, None if i == 0 else outs[i - 1], outs[i])
+            counts.append(r.step_result(i, None if i == 0 else outs[i - 1], outs[i]))
+        assert counts == ec
+        for a, b in zip(outs, exp):
+            assert np.array_equal(a.cpu().numpy(), b)
+    r.close()
