@@ -5,11 +5,13 @@
 //   signature   per vertex v: gather the pairs (edge label, previous block of
 //               target) over v's CSR row, remove duplicates (the signature is a
 //               SET, Def. signature), and fold the distinct pairs and v's own
-//               previous block into a 64-bit key hash.  Degree tiers: a thread
-//               per vertex (deg <= 16, in vertex order), a wave per vertex with
-//               an LDS hash set (deg <= 512), a workgroup per vertex with a
-//               64 KB LDS hash set (deg <= 4096), and hub vertices split over
-//               many workgroups sharing a global hash set.
+//               previous block into a 64-bit key hash.  Degree tiers, fixed at
+//               create time: runs of consecutive low-degree vertices share a
+//               workgroup and an LDS hash set (range tier, at most 1024 or
+//               2048 entries per run), a row of up to 4096 entries gets a
+//               workgroup of its own, and hub rows are split into chunks that
+//               are deduplicated in two passes (chunk, then partition), or,
+//               beyond 4M entries, through a global hash set.
 //   group       every vertex inserts (key hash, v) into an open-addressing
 //               table that keeps the minimum vertex per key; a lookup gives
 //               each vertex its candidate representative.
@@ -244,13 +246,7 @@ __global__ void k_validate_vals(int64_t cnt, const int32_t *__restrict__ vals, i
 }
 
 // ---------------------------------------------------------------- signature tiers
-// Range tier: a workgroup takes a run of consecutive vertices of degree <=
-// RANGE_DMAX holding at most RANGE_EDGES entries and RANGE_VERTS vertices.
-// All entries of the run are gathered at once (8 per thread, loads issued
-// before any dependent work, contiguous addresses), then each pair is
-// inserted into its vertex's region of an LDS hash set (2*deg slots at
-// offset 2*row offset); first insertions add the pair's mix to the vertex's
-// accumulator.  Zero-degree vertices cost one row-offset read.
+// A run of consecutive vertices [v0, v1) handled by one workgroup.
 struct Range {
   int v0, v1;
 };
