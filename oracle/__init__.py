@@ -17,8 +17,10 @@ Three independent references live here:
 * ``splitter.splitter_refine`` — a splitter-based refinement in the style of
   Alg. kaushik-alg, adapted to (edge label, block) splitters.
 
-``stepcheck`` holds property checks used at sizes the plain reference cannot
-reach in test time.
+``check_initial`` / ``check_step`` (``stepcheck.cpp``) check a given
+partition chain against the definition at sizes the plain reference cannot
+reach in test time: canonical ids, and each partition exactly the partition
+by (previous block, signature).
 """
 from __future__ import annotations
 
@@ -34,12 +36,18 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 
+_CHECK_PATH = os.path.join(_HERE, "libstepcheck.so")
+_check_lib = None
+
+
 def build(force: bool = True) -> str:
-    src = os.path.join(_HERE, "oracle.cpp")
-    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(src):
-        tmp = _LIB_PATH + ".tmp"
-        subprocess.check_call(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-Wall", "-o", tmp, src])
-        os.replace(tmp, _LIB_PATH)
+    for src, lib, extra in [("oracle.cpp", _LIB_PATH, []), ("stepcheck.cpp", _CHECK_PATH, ["-fopenmp"])]:
+        src = os.path.join(_HERE, src)
+        if force or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(src):
+            tmp = lib + ".tmp"
+            subprocess.check_call(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-Wall"] + extra +
+                                  ["-o", tmp, src])
+            os.replace(tmp, lib)
     return _LIB_PATH
 
 
@@ -125,3 +133,60 @@ class planted_mistake:
     def __exit__(self, *exc):
         _load().oracle_set_mutation(self.old)
         return False
+
+
+# ---------------------------------------------------------------- property checks
+
+CHECK_CODES = {-1: "ids not numbered by first vertex", -2: "not a refinement of the previous partition",
+               -3: "a block holds two different signatures", -4: "two blocks share one key",
+               -5: "bad input"}
+
+
+def _check():
+    global _check_lib
+    if _check_lib is not None:
+        return _check_lib
+    if not os.path.exists(_CHECK_PATH):
+        build(force=False)
+    lib = ctypes.CDLL(_CHECK_PATH)
+    vp = ctypes.c_void_p
+    lib.stepcheck_threads.argtypes = [ctypes.c_int]
+    lib.stepcheck_threads.restype = ctypes.c_int
+    lib.stepcheck_initial.argtypes = [ctypes.c_int64, vp, vp, vp, vp]
+    lib.stepcheck_initial.restype = ctypes.c_int64
+    lib.stepcheck_step.argtypes = [ctypes.c_int64, vp, vp, vp, vp, vp, vp]
+    lib.stepcheck_step.restype = ctypes.c_int64
+    _check_lib = lib
+    return lib
+
+
+def check_threads(threads: int = 0) -> int:
+    """Set (threads > 0) and return the number of threads the property checks use."""
+    return int(_check().stepcheck_threads(threads))
+
+
+def _raise(code, bad, what):
+    raise AssertionError(f"{what}: {CHECK_CODES.get(code, code)} (vertex {bad})")
+
+
+def check_initial(g, p0) -> int:
+    """Block count of P0 if ``p0`` is the canonical label-set partition, else AssertionError."""
+    lib = _check()
+    bad = np.zeros(1, dtype=np.int64)
+    p0 = _c(p0, np.int32)
+    rc = lib.stepcheck_initial(g.n, _p(_c(g.vlabel_ptr, np.int64)), _p(_c(g.vlabel, np.int32)), _p(p0), _p(bad))
+    if rc < 0:
+        _raise(int(rc), int(bad[0]), "P0")
+    return int(rc)
+
+
+def check_step(g, prev, cur) -> int:
+    """Block count of ``cur`` if it is the canonical refinement step of ``prev``, else AssertionError."""
+    lib = _check()
+    bad = np.zeros(1, dtype=np.int64)
+    prev, cur = _c(prev, np.int32), _c(cur, np.int32)
+    rc = lib.stepcheck_step(g.n, _p(_c(g.row_ptr, np.int64)), _p(_c(g.col, np.int32)), _p(_c(g.elabel, np.int32)),
+                            _p(prev), _p(cur), _p(bad))
+    if rc < 0:
+        _raise(int(rc), int(bad[0]), "step")
+    return int(rc)

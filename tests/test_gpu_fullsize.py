@@ -1,0 +1,119 @@
+"""Full-size parity: the benchmark workloads, in the launch configuration the
+benchmark times, checked against the definition.
+
+At these sizes the plain reference is too slow for every step, so each GPU
+partition is checked by the property checker (canonical ids, and exactly the
+partition by (previous block, signature)); a step whose output equals its
+input has reached the fixpoint, and every later output must then be the
+same array.  Where the plain reference fits in test time (the first step of
+the 100M-edge graph, the smaller graphs of the batch) it is compared element
+by element as well.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _kb():
+    import paper_2204_05821_amd as kb
+    return kb
+
+
+def say(*a):
+    print("[fullsize]", *a, flush=True)
+
+
+def verify_chain(g, host, counts, label, quiet=False):
+    """host = [P0, P1, ..., Pk] (numpy), counts likewise."""
+    assert oracle.check_initial(g, host[0]) == counts[0], label
+    fix = None
+    for i in range(1, len(host)):
+        if fix is not None:
+            assert counts[i] == counts[fix] and np.array_equal(host[i], host[fix]), (label, i)
+            continue
+        assert oracle.check_step(g, host[i - 1], host[i]) == counts[i], (label, i)
+        if not quiet:
+            say(f"{label}: P{i} checked ({counts[i]} blocks)")
+        if np.array_equal(host[i], host[i - 1]):
+            fix = i
+    return fix
+
+
+def gpu_plain(g, k):
+    kb = _kb()
+    r = kb.refiner_for(g, kmax=k)
+    p0, c0 = r.initial()
+    ids, counts = r.refine(k)
+    torch.cuda.synchronize()
+    host = [p0.cpu().numpy()] + [t.cpu().numpy() for t in ids]
+    r.close()
+    del r, ids, p0
+    torch.cuda.empty_cache()
+    return host, [c0] + counts
+
+
+@pytest.mark.timeout(900)
+def test_rmat_100M_k10():
+    oracle.check_threads(16)
+    g = graphgen.rmat(23, 100_000_000, seed=2)
+    say(f"RMAT s23: n={g.n} m={g.m}")
+    host, counts = gpu_plain(g, 10)
+    say("counts", counts)
+    fix = verify_chain(g, host, counts, "rmat_s23")
+    assert fix is not None and fix <= 10
+    ref, rc = oracle.refine(g, 1)
+    assert rc[0] == counts[1]
+    assert np.array_equal(ref[0], host[1])
+    say("P1 equals the plain reference element by element")
+
+
+@pytest.mark.timeout(1200)
+def test_rdf_rmat_1B_k10():
+    oracle.check_threads(16)
+    g = graphgen.rmat_rdf(27, 1_000_000_000, seed=3)
+    say(f"RDF-like RMAT s27: n={g.n} m={g.m}")
+    host, counts = gpu_plain(g, 10)
+    say("counts", counts)
+    verify_chain(g, host, counts, "rdf_s27")
+
+
+@pytest.mark.timeout(900)
+def test_batch_4096_sampled():
+    """The 4,096-graph batch as the benchmark runs it (captured loop, autotuned shape space);
+    every 16th graph checked by properties, the smallest 64 against the plain reference."""
+    kb = _kb()
+    oracle.check_threads(16)
+    k = 10
+    sizes = graphgen.batch_sizes(4096)
+    graphs = [graphgen.batch_graph(i, m) for i, m in enumerate(sizes)]
+    say(f"batch: {len(graphs)} graphs, {sum(sizes)} edges")
+    b = kb.batch_for(graphs, kmax=k, tuning=kb.tuning(1024, 2048, 2048), graphs_mode=True)
+    outs, counts = b.refine(k)
+    outs, counts = b.refine(k, out=outs)          # a replay of the captured loop
+    torch.cuda.synchronize()
+    off = b.vert_off
+    packed = [o.cpu().numpy() for o in outs]
+    b.close()
+    del b, outs
+    torch.cuda.empty_cache()
+    for gi in range(0, len(graphs), 16):
+        g = graphs[gi]
+        p0, c0 = oracle.initial(g)          # the chain's input; the batch keeps its own P0 inside
+        host = [p0] + [p[off[gi]:off[gi + 1]] for p in packed]
+        verify_chain(g, host, [c0] + counts[gi], f"batch{gi}", quiet=True)
+    say("every 16th graph checked")
+    smallest = sorted(range(len(graphs)), key=lambda i: sizes[i])[:64]
+    for gi in smallest:
+        ref, rc = oracle.refine(graphs[gi], k)
+        assert rc == counts[gi]
+        for i in range(k):
+            assert np.array_equal(packed[i][off[gi]:off[gi + 1]], ref[i]), (gi, i)
+    say("smallest 64 graphs equal the plain reference")
