@@ -78,7 +78,7 @@ def algorithmic_bytes(kernel: str, tiers, n: int, m: int) -> float:
     t = tiers
     if kernel == "k_sig_range":
         return 12.0 * t["range"]["entries"] + 12.0 * t["range"]["vertices"]
-    if kernel == "k_sig_block":
+    if kernel == "k_sig_row":
         return 12.0 * t["workgroup"]["entries"] + 12.0 * t["workgroup"]["vertices"]
     if kernel == "k_hub_stage":
         return 12.0 * (t["hub"]["entries"] + t["hub_global"]["entries"])
@@ -161,8 +161,24 @@ def run_plain(args, kb, torch):
     dev = torch.device("cuda:0")
     rp, col, el, vl, vp = kb.to_device(g, dev)
     torch.cuda.synchronize()
+    best, tune_report = None, None
+    if not args.no_autotune:
+        from paper_2204_05821_amd import tune
+        holder = {}
+
+        def make(cand):
+            rr = kb.Refiner(rp, col, el, vl, vp, kmax=k, tuning=kb.tuning(**cand))
+            holder["outs"] = holder.get("outs") or rr.alloc_outputs(k)
+            return rr
+
+        t0 = time.perf_counter()
+        best, tune_report = tune.autotune(make, lambda rr: rr.refine(k, out=holder["outs"]),
+                                          key="plain|" + tune.degree_signature(g.row_ptr), reps=2,
+                                          cache_path=args.tune_cache)
+        del holder
+        log(f"[bench] autotune {time.perf_counter() - t0:.1f}s: best {best}; {tune_report['ms']}")
     t0 = time.perf_counter()
-    r = kb.Refiner(rp, col, el, vl, vp, kmax=k)
+    r = kb.Refiner(rp, col, el, vl, vp, kmax=k, tuning=kb.tuning(**best) if best else None)
     torch.cuda.synchronize()
     create_ms = (time.perf_counter() - t0) * 1e3
     tiers = r.schedule_info()
@@ -173,7 +189,8 @@ def run_plain(args, kb, torch):
         log(f"[bench] warmup {i + 1}/{args.warmup} counts {counts}")
     stream = r.stream
     if not args.no_profile:
-        r.profile(True)
+        # inside the timed region only the signature kernels carry events
+        r.profile(True, kinds=["k_sig_range", "k_sig_row"])
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
@@ -192,16 +209,21 @@ def run_plain(args, kb, torch):
     kernels = {}
     roofline = None
     if not args.no_profile:
+        timed = {name: v for name, v in r.profile_read().items() if v[1]}
+        # per-kernel breakdown from a separate pass with every launch bracketed (not the timed region)
+        r.profile(True)
+        for _ in range(max(1, min(args.steps, 5))):
+            r.refine(k, out=outs)
         prof = r.profile_read()
         r.profile(False)
         total = sum(v[0] for v in prof.values())
         for name, (ms, cnt) in prof.items():
             if cnt:
                 kernels[name] = {"ms_per_launch": ms / cnt, "launches": cnt, "share": ms / total if total else 0}
-        dom = max((kk for kk in kernels if algorithmic_bytes(kk, tiers, g.n, g.m) > 0),
-                  key=lambda kk: kernels[kk]["ms_per_launch"] * kernels[kk]["launches"])
+        dom = max((kk for kk in timed if algorithmic_bytes(kk, tiers, g.n, g.m) > 0),
+                  key=lambda kk: timed[kk][0])
         ab = algorithmic_bytes(dom, tiers, g.n, g.m)
-        avg = kernels[dom]["ms_per_launch"]
+        avg = timed[dom][0] / timed[dom][1]
         achieved = ab / (avg / 1e3) / 1e9
         roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -241,6 +263,8 @@ def run_plain(args, kb, torch):
                      "frac_of_peak": round(step_gbs / HBM_PEAK_GBS, 4)},
         "counts": counts,
         "create_ms": round(create_ms, 1),
+        "tuning": best,
+        "autotune_ms": tune_report["ms"] if tune_report else None,
         "kernels": kernels,
         "tiers": tiers,
     }
@@ -422,6 +446,7 @@ def main():
     ap.add_argument("--workload", default="rmat_s23_m100M_k10", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip per-kernel event timing")
+    ap.add_argument("--no-autotune", action="store_true", help="plain form: default launch shapes, no search")
     ap.add_argument("--batch-graphs", type=int, default=4096)
     ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--tune-cache", default=None, help="JSON file for autotuner choices (default: none kept)")

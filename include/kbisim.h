@@ -87,12 +87,16 @@ typedef struct kbisim_ctx kbisim_ctx;
  * not depend on them; only the work split does.
  *   range_edges      CSR entries per range workgroup: 1024 or 2048 (default)
  *   hub_chunk        entries per hub staging workgroup: 2048 or 4096 (default)
- *   hub_part_target  expected entries per hub partition: 1024 or 2048 (default) */
+ *   hub_part_target  expected entries per hub partition: 1024 or 2048 (default)
+ *   key_bits         width of pair keys in LDS hash sets: 32 (default; used
+ *                    when every (edge label, block id) pair fits in 31 bits,
+ *                    else 64) or 64 (always)                                  */
 typedef struct {
   int range_edges;
   int hub_chunk;
   int hub_part_target;
-  int reserved[5];
+  int key_bits;
+  int reserved[4];
 } kbisim_tuning;
 
 /* Workspace bytes needed by kbisim_create for a graph of g->n vertices,
@@ -187,7 +191,7 @@ int kbisim_batch_destroy(kbisim_batch *b);
 
 /* Kernel kinds reported by the per-kernel profiler. */
 #define KBISIM_K_SIG_RANGE 0   /* signatures of runs of low-degree vertices        */
-#define KBISIM_K_SIG_BLOCK 1   /* signatures, one workgroup per mid-degree vertex  */
+#define KBISIM_K_SIG_BLOCK 1   /* signatures, one workgroup per row (1k-8k entries) */
 #define KBISIM_K_HUB_STAGE 2   /* hub rows: chunk dedupe and partitioned staging   */
 #define KBISIM_K_HUB_REDUCE 3  /* hub rows: per-partition dedupe and sums          */
 #define KBISIM_K_HUB_FINAL 4   /* hub key hashes (and very large hubs)             */
@@ -203,6 +207,11 @@ int kbisim_batch_destroy(kbisim_batch *b);
  * every launch is bracketed by HIP events on the context's stream and the
  * elapsed times are summed per kernel kind.  Enabling resets the sums.      */
 int kbisim_profile_enable(kbisim_ctx *c, int enable);
+
+/* Restrict timing to the kernel kinds whose bits are set in `kinds` (bit i =
+ * kind i; all kinds by default), so a timed run pays for events only around
+ * the kernels of interest.                                                 */
+int kbisim_profile_select(kbisim_ctx *c, uint32_t kinds);
 
 /* Sums since kbisim_profile_enable: ms[KBISIM_NKERNELS] milliseconds and
  * launches[KBISIM_NKERNELS] launch counts (host arrays; either may be NULL).
@@ -227,7 +236,9 @@ int kbisim_copy_probe(void *dst, const void *src, size_t bytes, void *stream);
 /* Enqueue step i (0 <= i < kmax): P_{i+1} from prev into out (device int32
  * [n]) on the context's stream, without synchronising.  Steps of one context
  * must be issued in order i = 0, 1, 2, ... with prev = P_0 (NULL) for i = 0
- * and prev = the previous step's out afterwards; out must not alias prev.
+ * and prev = the previous step's out afterwards, and no other refine call on
+ * the context in between (later steps reuse state of step 0); out must not
+ * alias prev.
  * The count stays on the device until kbisim_step_result.                   */
 int kbisim_step_async(kbisim_ctx *c, int i, const int32_t *prev, int32_t *out);
 

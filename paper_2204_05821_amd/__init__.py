@@ -44,15 +44,15 @@ class _Graph(ctypes.Structure):
 class Tuning(ctypes.Structure):
     """Launch-shape parameters (0 = default); results never depend on them."""
     _fields_ = [("range_edges", ctypes.c_int), ("hub_chunk", ctypes.c_int), ("hub_part_target", ctypes.c_int),
-                ("reserved", ctypes.c_int * 5)]
+                ("key_bits", ctypes.c_int), ("reserved", ctypes.c_int * 4)]
 
     def as_dict(self):
         return {"range_edges": self.range_edges, "hub_chunk": self.hub_chunk,
-                "hub_part_target": self.hub_part_target}
+                "hub_part_target": self.hub_part_target, "key_bits": self.key_bits}
 
 
-def tuning(range_edges: int = 0, hub_chunk: int = 0, hub_part_target: int = 0) -> Tuning:
-    return Tuning(range_edges, hub_chunk, hub_part_target)
+def tuning(range_edges: int = 0, hub_chunk: int = 0, hub_part_target: int = 0, key_bits: int = 0) -> Tuning:
+    return Tuning(range_edges, hub_chunk, hub_part_target, key_bits)
 
 
 _LIB = None
@@ -77,6 +77,8 @@ def _lib():
     lib.kbisim_batch_create.argtypes = [ctypes.POINTER(_Graph), i64, vp, i32, ctypes.POINTER(Tuning), vp, sz, vp,
                                         ctypes.POINTER(vp)]
     lib.kbisim_batch_refine.argtypes = [vp, i32, ctypes.POINTER(vp), vp]
+    lib.kbisim_profile_select.argtypes = [vp, ctypes.c_uint32]
+    lib.kbisim_profile_select.restype = i32
     lib.kbisim_batch_step_async.argtypes = [vp, i32, vp]
     lib.kbisim_batch_step_result.argtypes = [vp, i32, vp, vp]
     lib.kbisim_batch_context.argtypes = [vp, ctypes.POINTER(vp)]
@@ -211,8 +213,14 @@ class Refiner:
             raise KbisimError(rc, "kbisim_initial")
         return out, int(cnt.value)
 
-    def profile(self, enable: bool = True) -> None:
-        """Start (and reset) or stop per-kernel event timing of later refine calls."""
+    def profile(self, enable: bool = True, kinds: Optional[Sequence[str]] = None) -> None:
+        """Start (and reset) or stop per-kernel event timing of later refine calls;
+        ``kinds`` limits the timing to these kernel names (default: all)."""
+        names = kernel_names()
+        mask = 0xFFFFFFFF if kinds is None else sum(1 << names.index(k) for k in kinds)
+        rc = _lib().kbisim_profile_select(self._ctx, mask)
+        if rc:
+            raise KbisimError(rc, "kbisim_profile_select")
         rc = _lib().kbisim_profile_enable(self._ctx, 1 if enable else 0)
         if rc:
             raise KbisimError(rc, "kbisim_profile_enable")

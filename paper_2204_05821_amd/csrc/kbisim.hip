@@ -18,6 +18,7 @@
 #include <cstring>
 #include <map>
 #include <new>
+#include <type_traits>
 #include <utility>
 #include <vector>
 
@@ -128,9 +129,11 @@ Plan make_plan(int64_t n, int64_t m, int64_t nl, int kmax, int64_t num_graphs) {
 struct Schedule {
   int nranges = 0;  // multi-vertex ranges (at most range_edges entries)
   int nbig = 0;     // single-row ranges of range_edges < deg <= RANGE_DMAX
+  int nrow8 = 0;    // single-row ranges of RANGE_DMAX < deg <= ROW_MAX (after the nbig ones)
   int nhub = 0, hub_off = 0;
   int nchunks = 0, nparts = 0, ngchunks = 0;
   int64_t gset_begin = 0, gset_end = 0;  // global hash sets of very large hubs
+  int64_t nonempty = 0;                   // rows with at least one entry
   int64_t info[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // vertices, entries per tier
 };
 
@@ -138,6 +141,7 @@ struct Tuning {
   int range_edges = RANGE_EDGES;
   int hub_chunk = HUB_CHUNK;
   int hub_part_target = HUB_PART_TARGET;
+  int key_bits = 0;  // LDS set keys: 0 = narrow (32-bit) where pairs fit, 64 = always 64-bit
 };
 
 struct GraphKey {
@@ -170,6 +174,10 @@ struct kbisim_ctx {
   HubGChunk *gchunks;
   Schedule sched;  // graph rows
   u64 hmask = ~0ULL;
+  u64 tmask_steps = 0;   // grouping-table mask of refinement steps (sized by vertices with edges)
+  u32 prof_mask = ~0u;   // kernel kinds timed by the profiler
+  bool narrow = false;  // 32-bit LDS keys: (edge label << pb) | block fits in 31 bits
+  u32 pb = 31;
   int64_t p0_count = 0;
   // batches
   int64_t num_graphs = 0;
@@ -227,7 +235,7 @@ struct ProfScope {
   int kind;
   size_t start = (size_t)-1;
   ProfScope(kbisim_ctx *c_, int kind_) : c(c_), kind(kind_) {
-    if (!c->prof) return;
+    if (!c->prof || !((c->prof_mask >> kind) & 1u)) return;
     hipEvent_t e = prof_event(c);
     if (!e) return;
     start = c->ev_used - 1;
@@ -311,7 +319,7 @@ int build_schedule(kbisim_ctx *c, const int64_t *ptr, Schedule &s) {
     HIP_TRY(hipStreamSynchronize(c->stream));
   }
   auto deg = [&](int64_t v) -> int64_t { return ptr ? rp[(size_t)v + 1] - rp[(size_t)v] : 1; };
-  std::vector<Range> ranges, big_ranges;
+  std::vector<Range> ranges, big_ranges, row8_ranges;
   std::vector<int> hubs;
   int64_t cur0 = -1, cur_e = 0;
   auto close = [&](int64_t v_end) {
@@ -321,9 +329,17 @@ int build_schedule(kbisim_ctx *c, const int64_t *ptr, Schedule &s) {
   };
   for (int64_t v = 0; v < n; ++v) {
     const int64_t d = deg(v);
-    if (d > RANGE_DMAX) {
+    s.nonempty += d > 0;
+    if (d > ROW_MAX) {
       close(v);
       hubs.push_back((int)v);
+      continue;
+    }
+    if (d > RANGE_DMAX) {
+      close(v);
+      row8_ranges.push_back(Range{(int)v, (int)v + 1});
+      s.info[2] += 1;
+      s.info[3] += d;
       continue;
     }
     if (d > t.range_edges) {
@@ -342,7 +358,9 @@ int build_schedule(kbisim_ctx *c, const int64_t *ptr, Schedule &s) {
   close(n);
   s.nranges = (int)ranges.size();
   s.nbig = (int)big_ranges.size();
+  s.nrow8 = (int)row8_ranges.size();
   ranges.insert(ranges.end(), big_ranges.begin(), big_ranges.end());
+  ranges.insert(ranges.end(), row8_ranges.begin(), row8_ranges.end());
   // hubs: staged (partitioned) unless very large or out of offset space
   std::vector<HubChunk> chunks;
   std::vector<HubPart> parts;
@@ -476,25 +494,70 @@ int peel_round(kbisim_ctx *c, const Src &src, int *in_cnt, int *in_list, int *ou
   return 0;
 }
 
+// Refinement steps group only vertices with edges (the rest go by previous
+// block alone), so their table span is sized by that count; P0 uses it all.
 template <class Src>
-int launch_ranges(kbisim_ctx *c, const Src &src, const Schedule &s) {
-  const u64 tmask = c->plan.tslots - 1;
+u64 table_mask(const kbisim_ctx *c) {
+  if constexpr (std::is_same<Src, GraphSrc>::value) return c->tmask_steps;
+  return c->plan.tslots - 1;
+}
+
+template <class Src, class K>
+int launch_ranges_k(kbisim_ctx *c, const Src &src, const Schedule &s, int zfresh) {
+  const u64 tmask = table_mask<Src>(c);
   if (s.nranges) {
     ProfScope ps(c, KBISIM_K_SIG_RANGE);
     if (c->tune.range_edges == 1024)
-      k_sig_range<Src, 1024><<<(unsigned)s.nranges, 256, 0, c->stream>>>(src, c->ranges, c->H, c->DC, c->table, tmask,
-                                                                         c->dep, c->hmask, c->zrep);
+      k_sig_range<Src, 1024, K><<<(unsigned)s.nranges, 256, 0, c->stream>>>(src, c->ranges, c->H, c->DC, c->table,
+                                                                            tmask, c->dep, c->hmask, c->zrep, zfresh);
     else
-      k_sig_range<Src, 2048><<<(unsigned)s.nranges, 256, 0, c->stream>>>(src, c->ranges, c->H, c->DC, c->table, tmask,
-                                                                         c->dep, c->hmask, c->zrep);
+      k_sig_range<Src, 2048, K><<<(unsigned)s.nranges, 256, 0, c->stream>>>(src, c->ranges, c->H, c->DC, c->table,
+                                                                            tmask, c->dep, c->hmask, c->zrep, zfresh);
     LAUNCH_CHECK();
   }
-  if (s.nbig) {
+  if (s.nbig || s.nrow8) {
     ProfScope ps(c, KBISIM_K_SIG_BLOCK);
-    k_sig_range<Src, RANGE_DMAX><<<(unsigned)s.nbig, 256, 0, c->stream>>>(src, c->ranges + s.nranges, c->H, c->DC,
-                                                                          c->table, tmask, c->dep, c->hmask, c->zrep);
+    if (s.nbig) {
+      k_sig_row<Src, RANGE_DMAX, 512, K><<<(unsigned)s.nbig, 512, 0, c->stream>>>(
+          src, c->ranges + s.nranges, c->H, c->DC, c->table, tmask, c->dep, c->hmask, c->zrep);
+      LAUNCH_CHECK();
+    }
+    if (s.nrow8) {
+      k_sig_row<Src, ROW_MAX, 1024, K><<<(unsigned)s.nrow8, 1024, 0, c->stream>>>(
+          src, c->ranges + s.nranges + s.nbig, c->H, c->DC, c->table, tmask, c->dep, c->hmask, c->zrep);
+      LAUNCH_CHECK();
+    }
+  }
+  return 0;
+}
+
+template <class Src>
+int launch_ranges(kbisim_ctx *c, const Src &src, const Schedule &s, int zfresh) {
+  if constexpr (std::is_same<Src, GraphSrc>::value) {
+    if (c->narrow) return launch_ranges_k<Src, u32>(c, src, s, zfresh);
+  }
+  return launch_ranges_k<Src, u64>(c, src, s, zfresh);
+}
+
+// Staged hub rows: chunk dedupe and partitioned staging, then per-partition
+// dedupe and sums.  K: width of the staged keys.
+template <class Src, class K>
+int launch_hub_staged(kbisim_ctx *c, const Src &src, const Schedule &s, const int *hubs) {
+  K *stage = reinterpret_cast<K *>(c->hubsets);
+  {
+    ProfScope ps(c, KBISIM_K_HUB_STAGE);
+    if (c->tune.hub_chunk == 2048)
+      k_hub_stage<Src, 2048, K><<<(unsigned)s.nchunks, 256, 0, c->stream>>>(src, c->chunks, hubs, stage, c->poff,
+                                                                            c->err);
+    else
+      k_hub_stage<Src, 4096, K><<<(unsigned)s.nchunks, 256, 0, c->stream>>>(src, c->chunks, hubs, stage, c->poff,
+                                                                            c->err);
     LAUNCH_CHECK();
   }
+  ProfScope ps(c, KBISIM_K_HUB_REDUCE);
+  k_hub_reduce<Src, K><<<(unsigned)s.nparts, 256, 0, c->stream>>>(src, c->parts, c->chunks, stage, c->poff, c->hacc,
+                                                                  c->hcnt, c->err);
+  LAUNCH_CHECK();
   return 0;
 }
 
@@ -502,32 +565,27 @@ int launch_ranges(kbisim_ctx *c, const Src &src, const Schedule &s) {
 // into *count_dev.  cnt: CNT_STRIDE zeroed device counters for this step.
 // careful: settle every collision with host-driven peeling rounds.
 // gpid_next: where to write the new partition in rank order (NULL: not needed).
+// zfresh: group vertices with an empty signature afresh (the first step of a
+// call); otherwise their representatives from that step are kept, since two
+// such vertices share a block after a step exactly when they did before it.
 template <class Src>
 int run_step(kbisim_ctx *c, const Src &src, const Schedule &s, int *out, int64_t *count_dev, int *cnt,
-             bool careful, int *gpid_next) {
+             bool careful, int *gpid_next, bool zfresh) {
   const int n = (int)c->g.n;
   if (n == 0) return 0;
-  const u64 tmask = c->plan.tslots - 1;
+  const u64 tmask = table_mask<Src>(c);
   int rc = advance(c, ADV_TABLE | ADV_CTABLE | ADV_ZERO | (s.ngchunks ? ADV_HUB : 0u), s);
   if (rc) return rc;
-  if ((rc = launch_ranges(c, src, s))) return rc;
+  if ((rc = launch_ranges(c, src, s, zfresh ? 1 : 0))) return rc;
   if (s.nhub) {
     const int *hubs = c->lists + s.hub_off;
     if (s.nchunks) {
-      {
-        ProfScope ps(c, KBISIM_K_HUB_STAGE);
-        if (c->tune.hub_chunk == 2048)
-          k_hub_stage<Src, 2048><<<(unsigned)s.nchunks, 256, 0, c->stream>>>(src, c->chunks, hubs, c->hubsets, c->poff,
-                                                                             c->err);
-        else
-          k_hub_stage<Src, 4096><<<(unsigned)s.nchunks, 256, 0, c->stream>>>(src, c->chunks, hubs, c->hubsets, c->poff,
-                                                                             c->err);
-        LAUNCH_CHECK();
+      if constexpr (std::is_same<Src, GraphSrc>::value) {
+        rc = c->narrow ? launch_hub_staged<Src, u32>(c, src, s, hubs) : launch_hub_staged<Src, u64>(c, src, s, hubs);
+      } else {
+        rc = launch_hub_staged<Src, u64>(c, src, s, hubs);
       }
-      ProfScope ps(c, KBISIM_K_HUB_REDUCE);
-      k_hub_reduce<Src><<<(unsigned)s.nparts, 256, 0, c->stream>>>(c->parts, c->chunks, c->hubsets, c->poff, c->hacc,
-                                                                   c->hcnt, c->err);
-      LAUNCH_CHECK();
+      if (rc) return rc;
     }
     if (s.ngchunks) {
       ProfScope ps(c, KBISIM_K_HUB_STAGE);
@@ -543,7 +601,8 @@ int run_step(kbisim_ctx *c, const Src &src, const Schedule &s, int *out, int64_t
   {
     ProfScope ps(c, KBISIM_K_LOOKUP);
     k_lookup<Src><<<blocks_for(n, 256), 256, 0, c->stream>>>(src, n, c->H, c->DC, c->table, tmask, c->dep, c->rep,
-                                                             &cnt[0], c->vlist, &cnt[1], c->clA, c->err, c->zrep);
+                                                             &cnt[0], c->vlist, &cnt[1], c->clA, c->err, c->zrep,
+                                                             zfresh ? 1 : 0);
     LAUNCH_CHECK();
   }
   {
@@ -607,8 +666,9 @@ int enqueue_steps(kbisim_ctx *c, const int32_t *prev, int i0, int k, int32_t *co
   for (int i = i0; i < k; ++i) {
     if (careful && (rc = fill_i32(c, c->counters + CNT_STRIDE * i, CNT_STRIDE, 0))) return rc;
     int *dst = batch ? c->ibuf[i & 1] : out[i];
-    GraphSrc src{c->g.row_ptr, c->gcol, c->g.elabel, c->gpid[i & 1], prev};
-    rc = run_step(c, src, c->sched, dst, &c->dcounts[i], c->counters + CNT_STRIDE * i, careful, c->gpid[(i + 1) & 1]);
+    GraphSrc src{c->g.row_ptr, c->gcol, c->g.elabel, c->gpid[i & 1], prev, c->pb};
+    rc = run_step(c, src, c->sched, dst, &c->dcounts[i], c->counters + CNT_STRIDE * i, careful, c->gpid[(i + 1) & 1],
+                  i == 0);
     if (rc) return rc;
     if (batch) {
       k_rebase<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, c->gid, c->first, dst, out[i]);
@@ -723,6 +783,10 @@ int read_tuning(const kbisim_tuning *t, Tuning &out) {
     if (t->hub_part_target != 1024 && t->hub_part_target != 2048) return KBISIM_EINVAL;
     out.hub_part_target = t->hub_part_target;
   }
+  if (t->key_bits) {
+    if (t->key_bits != 32 && t->key_bits != 64) return KBISIM_EINVAL;
+    out.key_bits = t->key_bits;
+  }
   return 0;
 }
 
@@ -830,6 +894,31 @@ int create_impl(const kbisim_graph *g, int kmax, const kbisim_tuning *tuning, vo
   if ((rc = read_err(c, &err))) return fail(rc);
   if (err) return fail(KBISIM_EGRAPH);
 
+  // Pairs keep block ids modulo 2^pb, pb = bit width of the largest graph's
+  // vertex count (the block ids of one graph form an interval no longer than
+  // that).  Keys inside LDS sets are (edge label << pb) | reduced block, in
+  // 31 bits, when the labels allow.
+  {
+    int64_t gmax = n;
+    if (num_graphs > 0) {
+      gmax = 0;
+      for (int64_t i = 0; i < num_graphs; ++i) gmax = std::max<int64_t>(gmax, vert_off[i + 1] - vert_off[i]);
+    }
+    u32 max_label = 0;
+    if (g->elabel && m > 0) {
+      k_max_i32<<<(unsigned)std::min<int64_t>(blocks_for(m, 256), 4096), 256, 0, c->stream>>>(m, g->elabel, c->err + 2);
+      if (hipGetLastError() != hipSuccess) return fail(KBISIM_EHIP);
+      if (hipMemcpyAsync(&max_label, c->err + 2, sizeof(u32), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+          hipStreamSynchronize(c->stream) != hipSuccess)
+        return fail(KBISIM_EHIP);
+    }
+    u32 pb = 1, lb = 0;
+    while (pb < 31 && (int64_t(1) << pb) < gmax) ++pb;
+    while (lb < 32 && (max_label >> lb) != 0) ++lb;
+    c->pb = pb;
+    c->narrow = c->tune.key_bits != 64 && pb + lb <= 31;
+  }
+
   if (num_graphs > 0) {
     // graph of every vertex; first vertex of the next non-empty graph
     std::vector<int64_t> nxt((size_t)num_graphs, -1);
@@ -870,7 +959,7 @@ int create_impl(const kbisim_graph *g, int kmax, const kbisim_tuning *tuning, vo
     int *cnt = c->counters + CNT_STRIDE * (plan.ncounter_steps - 2);
     if ((rc = fill_i32(c, cnt, CNT_STRIDE, 0))) return fail(rc);
     int64_t *dcount = c->dcounts + (plan.ncounter_steps - 2);
-    if ((rc = run_step(c, src, ls, c->p0, dcount, cnt, true, nullptr))) return fail(rc);
+    if ((rc = run_step(c, src, ls, c->p0, dcount, cnt, true, nullptr, true))) return fail(rc);
     if (hipMemcpyAsync(&c->p0_count, dcount, 8, hipMemcpyDeviceToHost, c->stream) != hipSuccess)
       return fail(KBISIM_EHIP);
     if ((rc = read_err(c, &err))) return fail(rc);
@@ -880,6 +969,7 @@ int create_impl(const kbisim_graph *g, int kmax, const kbisim_tuning *tuning, vo
   if ((rc = build_rank(c))) return fail(rc);
   // Static schedule of the graph rows.
   if ((rc = build_schedule(c, g->row_ptr, c->sched))) return fail(rc);
+  c->tmask_steps = std::min<u64>(pow2_at_least(2 * (uint64_t)std::max<int64_t>(c->sched.nonempty, 1)), plan.tslots) - 1;
   *out = c;
   return KBISIM_OK;
 }
@@ -1024,6 +1114,12 @@ int kbisim_profile_enable(kbisim_ctx *c, int enable) {
   return KBISIM_OK;
 }
 
+int kbisim_profile_select(kbisim_ctx *c, uint32_t kinds) {
+  if (!c) return KBISIM_EINVAL;
+  c->prof_mask = kinds;
+  return KBISIM_OK;
+}
+
 int kbisim_profile_read(kbisim_ctx *c, double *ms, int64_t *launches) {
   if (!c) return KBISIM_EINVAL;
   HIP_TRY(hipStreamSynchronize(c->stream));
@@ -1036,7 +1132,7 @@ int kbisim_profile_read(kbisim_ctx *c, double *ms, int64_t *launches) {
 }
 
 const char *kbisim_kernel_name(int kind) {
-  static const char *names[KBISIM_NKERNELS] = {"k_sig_range", "k_sig_block", "k_hub_stage", "k_hub_reduce",
+  static const char *names[KBISIM_NKERNELS] = {"k_sig_range", "k_sig_row", "k_hub_stage", "k_hub_reduce",
                                                "k_hub_final", "k_lookup",    "k_verify",    "k_res_*",
                                                "k_scan",      "k_assign",    "k_fill_*"};
   return (kind >= 0 && kind < KBISIM_NKERNELS) ? names[kind] : nullptr;

@@ -43,8 +43,9 @@ constexpr int WAVE = 64;
 constexpr int SMALL_MAX = 16;        // inline exact check limit (thread per vertex)
 constexpr int RANGE_EDGES = 2048;    // CSR entries per multi-vertex range workgroup
 constexpr int RANGE_VERTS = 256;     // vertices per range workgroup
-constexpr int RANGE_DMAX = 4096;     // rows above RANGE_EDGES get a range of their own; above this, hubs
-constexpr int BLOCK_MAX = RANGE_DMAX;
+constexpr int RANGE_DMAX = 4096;     // rows above RANGE_EDGES get a workgroup of 512 threads
+constexpr int ROW_MAX = 8192;        // rows above RANGE_DMAX get one of 1024 threads; above this, hubs
+constexpr int BLOCK_MAX = ROW_MAX;
 constexpr int BLOCK_SLOTS = 8192;    // LDS set slots for exact checks (64 KB)
 constexpr int HUB_CHUNK = 4096;      // default entries per hub staging workgroup (16 per thread)
 constexpr int HUB_PMAX = 1024;       // partitions per hub at most
@@ -118,13 +119,26 @@ struct GraphSrc {
   const int32_t *pid;     // previous partition in vertex order
   __device__ inline int64_t begin(int v) const { return row_ptr[v]; }
   __device__ inline int64_t end(int v) const { return row_ptr[v + 1]; }
+  // A pair keeps the target's block id modulo 2^pb.  The targets of one row
+  // lie in one graph, whose block ids form an interval of at most 2^pb ids
+  // (pb covers the largest graph; a single graph: all ids), so the reduction
+  // is one-to-one within a row, and every kernel reduces the same way.
+  u32 pb;
+  __device__ inline u32 pmask() const { return pb >= 31 ? 0x7FFFFFFFu : (1u << pb) - 1u; }
   __device__ inline u64 pair(int64_t e) const {
     // streamed arrays are read non-temporally so they do not evict the
     // gather targets from the L2
     const u32 l = elabel ? (u32)__builtin_nontemporal_load(&elabel[e]) : 0u;
-    return ((u64)l << 31) | (u64)(u32)gpid[__builtin_nontemporal_load(&gcol[e])];
+    return ((u64)l << 31) | (u64)((u32)gpid[__builtin_nontemporal_load(&gcol[e])] & pmask());
   }
   __device__ inline u32 own(int v) const { return (u32)pid[v]; }
+  // Narrow form of a pair, used inside LDS sets when every edge label and
+  // reduced block id fit together in 31 bits: (label << pb) | block.
+  __device__ inline u32 key32(int64_t e) const {
+    const u32 l = elabel ? (u32)__builtin_nontemporal_load(&elabel[e]) : 0u;
+    return (l << pb) | ((u32)gpid[__builtin_nontemporal_load(&gcol[e])] & pmask());
+  }
+  __device__ inline u64 wide(u32 q) const { return ((u64)(q >> pb) << 31) | (u64)(q & pmask()); }
 };
 
 struct LabelSrc {
@@ -135,6 +149,31 @@ struct LabelSrc {
   __device__ inline int64_t end(int v) const { return ptr ? ptr[v + 1] : (int64_t)v + 1; }
   __device__ inline u64 pair(int64_t e) const { return (u64)(u32)lab[e]; }
   __device__ inline u32 own(int v) const { return gid ? (u32)gid[v] : 0u; }
+};
+
+// LDS set keys: the 64-bit pair itself, or the narrow 32-bit form.
+template <class K>
+struct Keys;
+template <>
+struct Keys<u64> {
+  static constexpr u64 EMPTY = EMPTY64;
+  template <class Src>
+  __device__ static inline u64 load(const Src &s, int64_t e) { return s.pair(e); }
+  template <class Src>
+  __device__ static inline u64 wide(const Src &, u64 p) { return p; }
+  __device__ static inline u32 hash(u64 p) { return set_hash(p); }
+};
+template <>
+struct Keys<u32> {
+  static constexpr u32 EMPTY = 0xFFFFFFFFu;
+  template <class Src>
+  __device__ static inline u32 load(const Src &s, int64_t e) { return s.key32(e); }
+  template <class Src>
+  __device__ static inline u64 wide(const Src &s, u32 q) { return s.wide(q); }
+  __device__ static inline u32 hash(u32 q) {
+    const u32 h = q * 0x9E3779B1u;
+    return h ^ (h >> 15);
+  }
 };
 
 // ---------------------------------------------------------------- wave helpers
@@ -225,6 +264,25 @@ __device__ inline void key_insert(u64 *table, u64 tmask, u64 *zrep, u64 h, u32 d
   else table_insert(table, tmask, h, v, epoch);
 }
 
+// zero_insert for the lanes with pred set, one atomic per distinct block in
+// the wave (device-wide atomics on one address serialise, and empty
+// signatures share few blocks).  Must be reached by the whole wave.
+__device__ inline void zero_insert_wave(u64 *zrep, bool pred, u32 own, u32 v, u32 zep) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  u64 pending = __ballot(pred);
+  while (pending) {
+    const int leader = __ffsll((long long)pending) - 1;
+    const u32 lo = __shfl(own, leader, WAVE);
+    const bool mine = pred && own == lo;
+    u32 mv = mine ? v : 0xFFFFFFFFu;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) mv = min(mv, (u32)__shfl_xor(mv, o, WAVE));
+    if (lane == leader) zero_insert(zrep, lo, mv, zep);
+    pending &= ~__ballot(mine);
+    pred = pred && !mine;
+  }
+}
+
 // ---------------------------------------------------------------- validation
 __global__ void k_validate_rows(int64_t n, int64_t m, const int64_t *__restrict__ ptr, u32 *err, u32 bit) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -236,6 +294,16 @@ __global__ void k_validate_rows(int64_t n, int64_t m, const int64_t *__restrict_
   if (i < n && ptr[i + 1] < a) bad = true;
   if (a < 0 || a > m) bad = true;
   if (bad) atomicOr(err, bit);
+}
+
+// Largest value of a non-negative array (atomicMax into *out, which starts at 0).
+__global__ void k_max_i32(int64_t cnt, const int32_t *__restrict__ vals, u32 *out) {
+  u32 mx = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x)
+    mx = max(mx, (u32)vals[i]);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) mx = max(mx, (u32)__shfl_xor(mx, o, WAVE));
+  if ((threadIdx.x & (WAVE - 1)) == 0 && mx) atomicMax(out, mx);
 }
 
 __global__ void k_validate_vals(int64_t cnt, const int32_t *__restrict__ vals, int64_t upper, u32 *err, u32 bit) {
@@ -253,6 +321,8 @@ struct Range {
 
 __device__ inline u64 scale_to(u32 a, u64 n) { return __umul64hi(((u64)a) << 32, n); }
 
+// Sum over the workgroup; the result is valid in thread 0.  sh_acc and
+// sh_cnt hold one slot per wave.
 __device__ inline void block_reduce_2(u64 &acc, u32 &cnt, u64 *sh_acc, u32 *sh_cnt) {
   acc = wave_sum_u64(acc);
   cnt = wave_sum_u32(cnt);
@@ -272,13 +342,14 @@ __device__ inline void block_reduce_2(u64 &acc, u32 &cnt, u64 *sh_acc, u32 *sh_c
 // consecutive entries on consecutive lanes), then inserted into their
 // vertex's region of an LDS hash set (2*deg slots at offset 2*row offset);
 // per-vertex sums are formed from the set afterwards.
-template <class Src, int EMAX>
+template <class Src, int EMAX, class K = u64>
 __global__ void __launch_bounds__(256) k_sig_range(Src src, const Range *__restrict__ ranges, u64 *__restrict__ H,
                                                    u32 *__restrict__ DC, u64 *table, u64 tmask,
-                                                   const u32 *__restrict__ dep, u64 hmask, u64 *zrep) {
+                                                   const u32 *__restrict__ dep, u64 hmask, u64 *zrep, int zfresh) {
+  typedef Keys<K> KO;
   constexpr int U = EMAX / 256;
   const u32 epoch = dep[EP_TABLE], zep = dep[EP_ZERO];
-  __shared__ u64 set[2 * EMAX];
+  __shared__ K set[2 * EMAX];
   __shared__ u64 acc[RANGE_VERTS];
   __shared__ u32 cnt[RANGE_VERTS];
   __shared__ int roff[RANGE_VERTS + 1];
@@ -300,17 +371,17 @@ __global__ void __launch_bounds__(256) k_sig_range(Src src, const Range *__restr
     for (int i = t; i < EMAX; i += 256) owner[i] = 0;
   __syncthreads();
   const int E = roff[V];
-  for (int i = t; i < 2 * E; i += 256) set[i] = EMPTY64;
+  for (int i = t; i < 2 * E; i += 256) set[i] = KO::EMPTY;
   // the row start of every non-empty vertex marks its index; a max-scan then
   // gives the owner of every entry
   if (!single)
     for (int i = t; i < V; i += 256)
       if (roff[i + 1] > roff[i]) owner[roff[i]] = (unsigned char)i;
-  u64 pr[U];
+  K pr[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     const int j = t + u * 256;
-    pr[u] = j < E ? src.pair(eb + j) : EMPTY64;
+    pr[u] = j < E ? KO::load(src, eb + j) : KO::EMPTY;
   }
   __syncthreads();
   if (!single) {
@@ -344,18 +415,18 @@ __global__ void __launch_bounds__(256) k_sig_range(Src src, const Range *__restr
     const u32 sz = 2u * (u32)E;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const u64 p = pr[u];
-      if (p == EMPTY64) continue;
-      u32 sl = (u32)scale_to(set_hash(p), sz);
+      const K p = pr[u];
+      if (p == KO::EMPTY) continue;
+      u32 sl = (u32)scale_to(KO::hash(p), sz);
       while (true) {
-        const u64 old = atomicCAS(&set[sl], EMPTY64, p);
-        if (old == EMPTY64) { a += mix_pair(p); ++c; break; }
+        const K old = atomicCAS(&set[sl], KO::EMPTY, p);
+        if (old == KO::EMPTY) { a += mix_pair(KO::wide(src, p)); ++c; break; }
         if (old == p) break;
         sl = (sl + 1 == sz) ? 0u : sl + 1;
       }
     }
     block_reduce_2(a, c, sh_acc, sh_cnt);
-    if (t == 0) {
+    if (t == 0 && (c || zfresh)) {
       const int v = rg.v0;
       const u32 own = src.own(v);
       const u64 h = finalize_key(a, c, own) & hmask;
@@ -370,14 +441,14 @@ __global__ void __launch_bounds__(256) k_sig_range(Src src, const Range *__restr
     const int j = t + u * 256;
     if (j < E) {
       const int lo = owner[j];
-      const u64 p = pr[u];
+      const K p = pr[u];
       const int base = 2 * roff[lo];
       const u32 sz = 2u * (u32)(roff[lo + 1] - roff[lo]);
-      u32 sl = (u32)scale_to(set_hash(p), sz);
+      u32 sl = (u32)scale_to(KO::hash(p), sz);
       while (true) {
-        const u64 old = atomicCAS(&set[base + sl], EMPTY64, p);
-        if (old == EMPTY64) {
-          atomicAdd(&acc[lo], mix_pair(p));
+        const K old = atomicCAS(&set[base + sl], KO::EMPTY, p);
+        if (old == KO::EMPTY) {
+          atomicAdd(&acc[lo], mix_pair(KO::wide(src, p)));
           atomicAdd(&cnt[lo], 1u);
           break;
         }
@@ -387,18 +458,75 @@ __global__ void __launch_bounds__(256) k_sig_range(Src src, const Range *__restr
     }
   }
   __syncthreads();
-  for (int i = t; i < V; i += 256) {
-    const int v = rg.v0 + i;
-    const u32 c = cnt[i];
-    const u32 own = src.own(v);
+  // V <= RANGE_VERTS = blockDim: one vertex per thread.  Vertices with an
+  // empty signature keep their representative from the call's first step
+  // unless zfresh (their classes never change within a call).
+  bool zero = false;
+  u32 own = 0;
+  const int v = rg.v0 + t;
+  if (t < V) {
+    const u32 c = cnt[t];
     if (c) {
-      const u64 h = finalize_key(acc[i], c, own) & hmask;
+      own = src.own(v);
+      const u64 h = finalize_key(acc[t], c, own) & hmask;
       H[v] = h;
       table_insert(table, tmask, h, (u32)v, epoch);
-    } else {
-      zero_insert(zrep, own, (u32)v, zep);
+    } else if (zfresh) {
+      own = src.own(v);
+      zero = true;
     }
     DC[v] = c;
+  }
+  zero_insert_wave(zrep, zero, own, (u32)v, zep);
+}
+
+// Row tier: one workgroup of NT threads per row of RANGE_EDGES < deg <= EMAX
+// entries.  All entries are gathered at once (EMAX / NT per thread), then
+// inserted into an LDS hash set of 2 * deg slots; first insertions add to
+// thread-local sums, reduced over the workgroup at the end.
+template <class Src, int EMAX, int NT, class K = u64>
+__global__ void __launch_bounds__(NT) k_sig_row(Src src, const Range *__restrict__ rows, u64 *__restrict__ H,
+                                                u32 *__restrict__ DC, u64 *table, u64 tmask,
+                                                const u32 *__restrict__ dep, u64 hmask, u64 *zrep) {
+  typedef Keys<K> KO;
+  constexpr int U = EMAX / NT;
+  __shared__ K set[2 * EMAX];
+  __shared__ u64 sh_acc[NT / WAVE];
+  __shared__ u32 sh_cnt[NT / WAVE];
+  const int t = threadIdx.x;
+  const int v = rows[blockIdx.x].v0;
+  const int64_t eb = src.begin(v);
+  const int E = (int)(src.end(v) - eb);
+  for (int i = t; i < 2 * E; i += NT) set[i] = KO::EMPTY;
+  K pr[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int j = t + u * NT;
+    pr[u] = j < E ? KO::load(src, eb + j) : KO::EMPTY;
+  }
+  __syncthreads();
+  u64 a = 0;
+  u32 c = 0;
+  const u32 sz = 2u * (u32)E;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const K p = pr[u];
+    if (p == KO::EMPTY) continue;
+    u32 sl = (u32)scale_to(KO::hash(p), sz);
+    while (true) {
+      const K old = atomicCAS(&set[sl], KO::EMPTY, p);
+      if (old == KO::EMPTY) { a += mix_pair(KO::wide(src, p)); ++c; break; }
+      if (old == p) break;
+      sl = (sl + 1 == sz) ? 0u : sl + 1;
+    }
+  }
+  block_reduce_2(a, c, sh_acc, sh_cnt);
+  if (t == 0) {
+    const u32 own = src.own(v);
+    const u64 h = finalize_key(a, c, own) & hmask;
+    H[v] = h;
+    DC[v] = c;
+    key_insert(table, tmask, zrep, h, c, own, (u32)v, dep[EP_TABLE], dep[EP_ZERO]);
   }
 }
 
@@ -426,37 +554,38 @@ struct HubPart {
   int nchunks;
 };
 
-template <class Src, int CHUNK>
+template <class Src, int CHUNK, class K = u64>
 __global__ void __launch_bounds__(256) k_hub_stage(Src src, const HubChunk *__restrict__ chunks,
-                                                   const int *__restrict__ hubs, u64 *__restrict__ stage,
+                                                   const int *__restrict__ hubs, K *__restrict__ stage,
                                                    int *__restrict__ poff, u32 *err) {
+  typedef Keys<K> KO;
   constexpr int HUB_U = CHUNK / 256;
-  __shared__ u64 set[2 * CHUNK];
+  __shared__ K set[2 * CHUNK];
   __shared__ int hist[HUB_PMAX + 1];
   __shared__ int wtot[4];
   const HubChunk c = chunks[blockIdx.x];
   const int P = c.parts;
   const int64_t row = src.begin(hubs[c.hub]);
   const int E = (int)(c.e - c.b);
-  for (int i = threadIdx.x; i < 2 * CHUNK; i += 256) set[i] = EMPTY64;
+  for (int i = threadIdx.x; i < 2 * CHUNK; i += 256) set[i] = KO::EMPTY;
   for (int i = threadIdx.x; i <= P; i += 256) hist[i] = 0;
-  u64 pr[HUB_U];
+  K pr[HUB_U];
 #pragma unroll
   for (int u = 0; u < HUB_U; ++u) {
     const int j = threadIdx.x + u * 256;
-    pr[u] = j < E ? src.pair(row + c.b + j) : EMPTY64;
+    pr[u] = j < E ? KO::load(src, row + c.b + j) : KO::EMPTY;
   }
   __syncthreads();
   int rank[HUB_U];
 #pragma unroll
   for (int u = 0; u < HUB_U; ++u) {
     rank[u] = -1;
-    const u64 p = pr[u];
-    if (p == EMPTY64) continue;
-    u32 sl = set_hash(p) & (2 * CHUNK - 1);
+    const K p = pr[u];
+    if (p == KO::EMPTY) continue;
+    u32 sl = KO::hash(p) & (2 * CHUNK - 1);
     while (true) {
-      const u64 old = atomicCAS(&set[sl], EMPTY64, p);
-      if (old == EMPTY64) {
+      const K old = atomicCAS(&set[sl], KO::EMPTY, p);
+      if (old == KO::EMPTY) {
         rank[u] = atomicAdd(&hist[part_hash(p) & (P - 1)], 1);
         break;
       }
@@ -501,17 +630,19 @@ __global__ void __launch_bounds__(256) k_hub_stage(Src src, const HubChunk *__re
 #pragma unroll
   for (int u = 0; u < HUB_U; ++u) {
     if (rank[u] >= 0) {
-      const u64 p = pr[u];
+      const K p = pr[u];
       stage[c.stage + hist[part_hash(p) & (P - 1)] + rank[u]] = p;
     }
   }
 }
 
-template <class Src>
-__global__ void __launch_bounds__(256) k_hub_reduce(const HubPart *__restrict__ parts, const HubChunk *__restrict__ chunks,
-                                                    const u64 *__restrict__ stage, const int *__restrict__ poff,
+template <class Src, class K = u64>
+__global__ void __launch_bounds__(256) k_hub_reduce(Src src, const HubPart *__restrict__ parts,
+                                                    const HubChunk *__restrict__ chunks,
+                                                    const K *__restrict__ stage, const int *__restrict__ poff,
                                                     u64 *hub_acc, u32 *hub_cnt, u32 *err) {
-  __shared__ u64 set[HUB_PSLOTS];
+  typedef Keys<K> KO;
+  __shared__ K set[HUB_PSLOTS];
   __shared__ int64_t sbase[HUB_PMAX]; // per chunk: staging position of this partition's segment
   __shared__ int pre[HUB_PMAX + 1];    // exclusive prefix of segment lengths
   __shared__ int wtot[4];
@@ -519,7 +650,7 @@ __global__ void __launch_bounds__(256) k_hub_reduce(const HubPart *__restrict__ 
   __shared__ u32 sh_cnt[4];
   const HubPart hp = parts[blockIdx.x];
   const int C = hp.nchunks;
-  for (int i = threadIdx.x; i < HUB_PSLOTS; i += 256) set[i] = EMPTY64;
+  for (int i = threadIdx.x; i < HUB_PSLOTS; i += 256) set[i] = KO::EMPTY;
   // segment lengths, then an exclusive scan over the (at most 1024) chunks
   {
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -560,11 +691,11 @@ __global__ void __launch_bounds__(256) k_hub_reduce(const HubPart *__restrict__ 
   u64 acc = 0;
   u32 cnt = 0;
   for (int t0 = 0; t0 < T; t0 += 4 * 256) {
-    u64 pr[4];
+    K pr[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int t = t0 + threadIdx.x + u * 256;
-      pr[u] = EMPTY64;
+      pr[u] = KO::EMPTY;
       if (t < T) {
         int lo = 0, hi = C - 1;
         while (lo < hi) {
@@ -576,13 +707,13 @@ __global__ void __launch_bounds__(256) k_hub_reduce(const HubPart *__restrict__ 
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const u64 p = pr[u];
-      if (p == EMPTY64) continue;
-      u32 sl = set_hash(p) & (HUB_PSLOTS - 1);
+      const K p = pr[u];
+      if (p == KO::EMPTY) continue;
+      u32 sl = KO::hash(p) & (HUB_PSLOTS - 1);
       for (int probes = 0;; ++probes) {
         if (probes >= HUB_PSLOTS) { atomicOr(err, ERR_VERIFY_OVERFLOW); break; }
-        const u64 old = atomicCAS(&set[sl], EMPTY64, p);
-        if (old == EMPTY64) { acc += mix_pair(p); ++cnt; break; }
+        const K old = atomicCAS(&set[sl], KO::EMPTY, p);
+        if (old == KO::EMPTY) { acc += mix_pair(KO::wide(src, p)); ++cnt; break; }
         if (old == p) break;
         sl = (sl + 1) & (HUB_PSLOTS - 1);
       }
@@ -663,69 +794,73 @@ __global__ void k_hub_final(Src src, const int *__restrict__ hubs, int nhub, u64
 
 // ---------------------------------------------------------------- lookup + exact check
 // For each vertex: representative r = minimum vertex stored under its key.
-// r == v: v heads its block.  Otherwise the key of v is compared exactly
-// with r's: the previous block, the number of distinct pairs, and (for small
-// rows, inline) every pair of v must occur in r's row.  Larger rows go to a
-// verification list; mismatches (hash collisions) to the collision list
-// with rep = -1.
+// r == v: v heads its block.  Otherwise v joins r's block once the keys are
+// shown equal exactly: the previous block, the number of distinct pairs and,
+// for rows of at most SMALL_MAX entries, the pair sets here; larger rows go
+// to a verification list (k_verify).  Mismatches (hash collisions) go to the
+// collision list with rep = -1.  Lists are appended with one atomic per
+// wave; they stay short, since device-wide atomics on one counter serialise.
 template <class Src>
 __global__ void __launch_bounds__(256) k_lookup(Src src, int n, const u64 *__restrict__ H,
                                                 const u32 *__restrict__ DC, const u64 *table, u64 tmask,
                                                 const u32 *__restrict__ dep, int *__restrict__ rep, int *vcount,
-                                                int *vlist, int *ccount, int *clist, u32 *err, const u64 *zrep) {
+                                                int *vlist, int *ccount, int *clist, u32 *err, const u64 *zrep,
+                                                int zfresh) {
   const u32 epoch = dep[EP_TABLE], zep = dep[EP_ZERO];
-  __shared__ u64 buf[SMALL_MAX * 256];
-  const int t = threadIdx.x;
-  const int v = blockIdx.x * 256 + t;
+  const int v = blockIdx.x * 256 + threadIdx.x;
   bool to_verify = false, collided = false;
-  const u32 dcv0 = v < n ? DC[v] : 0u;
-  if (v < n && dcv0 == 0) {
-    // empty signature: exact grouping by previous block
-    const u64 z = zrep[src.own(v)];
-    if ((u32)(z >> 32) != ~zep) {
-      atomicOr(err, ERR_LOOKUP_MISS);
-      rep[v] = v;
+  if (v < n) {
+    const u32 dcv = DC[v];
+    if (dcv == 0) {
+      // empty signature: exact grouping by previous block (without zfresh the
+      // representative is kept from the call's first step)
+      if (zfresh) {
+        const u64 z = zrep[src.own(v)];
+        if ((u32)(z >> 32) != ~zep) {
+          atomicOr(err, ERR_LOOKUP_MISS);
+          rep[v] = v;
+        } else {
+          rep[v] = (int)(u32)z;
+        }
+      }
     } else {
-      rep[v] = (int)(u32)z;
-    }
-  } else if (v < n) {
-    const int r = table_lookup(table, tmask, H[v], epoch);
-    if (r < 0) {
-      atomicOr(err, ERR_LOOKUP_MISS);
-      rep[v] = v;
-    } else if (r == v) {
-      rep[v] = v;
-    } else {
-      const u32 dcv = DC[v];
-      bool ok;
-      if (src.own(v) != src.own(r) || dcv != DC[r]) {
-        ok = false;
-      } else if (dcv == 0) {
-        ok = true;
+      const int r = table_lookup(table, tmask, H[v], epoch);
+      if (r < 0) {
+        atomicOr(err, ERR_LOOKUP_MISS);
+        rep[v] = v;
+      } else if (r == v) {
+        rep[v] = v;
+      } else if (src.own(v) != src.own(r) || dcv != DC[r]) {
+        rep[v] = -1;
+        collided = true;
       } else {
         const int64_t bv = src.begin(v), ev = src.end(v);
         const int64_t br = src.begin(r), er = src.end(r);
         if (ev - bv <= SMALL_MAX && er - br <= SMALL_MAX) {
-          int nr = 0;
-          for (int64_t i = br; i < er; ++i) buf[(nr++) * 256 + t] = src.pair(i);
-          ok = true;
-          for (int64_t i = bv; i < ev && ok; ++i) {
-            const u64 p = src.pair(i);
+          // small rows: r's pairs in registers (static indexing), every pair
+          // of v must occur among them (equal distinct counts were checked,
+          // so inclusion is equality)
+          u64 rp[SMALL_MAX];
+#pragma unroll
+          for (int j = 0; j < SMALL_MAX; ++j) rp[j] = br + j < er ? src.pair(br + j) : EMPTY64;
+          bool ok = true;
+          for (int64_t j = bv; j < ev && ok; ++j) {
+            const u64 p = src.pair(j);
             bool found = false;
-            for (int j = 0; j < nr; ++j)
-              if (buf[j * 256 + t] == p) { found = true; break; }
+#pragma unroll
+            for (int q = 0; q < SMALL_MAX; ++q) found |= rp[q] == p;
             ok = found;
           }
+          if (ok) {
+            rep[v] = r;
+          } else {
+            rep[v] = -1;
+            collided = true;
+          }
         } else {
+          rep[v] = r;  // confirmed or rejected by k_verify
           to_verify = true;
-          ok = true;
         }
-      }
-      if (ok) {
-        rep[v] = r;
-      } else {
-        rep[v] = -1;
-        collided = true;
       }
     }
   }

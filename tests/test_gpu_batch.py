@@ -152,13 +152,14 @@ def test_graph_replay_with_collision_fallback(monkeypatch):
 
 # ------------------------------------------------------------------ tunings
 
-@pytest.mark.parametrize("re,hc,hp", list(itertools.product([1024, 2048], [2048, 4096], [1024, 2048])))
-def test_every_tuning_gives_identical_results(re, hc, hp):
+@pytest.mark.parametrize("re,hc,hp,kbits", list(itertools.product([1024, 2048], [2048, 4096], [1024, 2048],
+                                                                   [0, 64])))
+def test_every_tuning_gives_identical_results(re, hc, hp, kbits):
     kb = _kb()
     from tests.test_gpu_parity import tier_graph
     for g in [graphgen.rmat(14, 250_000, seed=5), tier_graph(seed=9)]:
         exp, ec = ref(g, 4)
-        r = kb.Refiner(*kb.to_device(g), kmax=4, tuning=kb.tuning(re, hc, hp))
+        r = kb.Refiner(*kb.to_device(g), kmax=4, tuning=kb.tuning(re, hc, hp, kbits))
         ids, counts = r.refine(4)
         assert counts == ec
         for a, b in zip(ids, exp):

@@ -141,6 +141,44 @@ def test_degree_tiers_many_labels():
     assert_same(tier_graph(seed=4, labels=200, shared_targets=3000), 5, "tiers-many")
 
 
+# ------------------------------------------------------------------ key width
+
+def assert_same_tuned(g, k, tune, label):
+    kb = _kb()
+    print(f"[parity] {label} n={g.n} m={g.m} k={k} tuning={tune.as_dict()}", flush=True)
+    exp, ec = ref_all(g, k)
+    r = kb.Refiner(*kb.to_device(g), kmax=k, tuning=tune)
+    ids, counts = r.refine(k)
+    assert counts == ec[1:], label
+    for i, (a, b) in enumerate(zip(ids, exp[1:])):
+        assert np.array_equal(a.cpu().numpy(), b), (label, i + 1)
+    r.close()
+
+
+@pytest.mark.parametrize("kbits", [0, 64])
+def test_key_width_forced_and_automatic(kbits):
+    """32-bit LDS keys are used where (edge label, block) fits in 31 bits; 64-bit keys always work."""
+    kb = _kb()
+    for g in [graphgen.rmat(14, 200_000, seed=2), tier_graph(seed=6), graphgen.rmat_rdf(12, 60_000, seed=8),
+              graphgen.deep(seed=9, n=20_000, avg_degree=1.5)]:
+        assert_same_tuned(g, 6, kb.tuning(key_bits=kbits), f"keys{kbits}-{g.name}")
+
+
+@pytest.mark.parametrize("label_max", [(1 << 11) - 1, 1 << 11])
+def test_key_width_boundary(label_max):
+    """n = 2^20 gives 20 bits of block id; labels up to 2^11 - 1 fill 31 bits exactly (narrow keys),
+    one more label bit needs 64-bit keys."""
+    kb = _kb()
+    rng = np.random.default_rng(label_max)
+    n, m = 1 << 20, 3_000_000
+    src = rng.integers(0, n, size=m)
+    dst = rng.integers(0, n // 64, size=m)           # few targets: many equal pairs to merge
+    lab = rng.integers(label_max - 3, label_max + 1, size=m)
+    vl = rng.integers(0, 3, size=n)
+    g = graphgen.from_edges(n, src, dst, lab, vl, name=f"bound{label_max}")
+    assert_same_tuned(g, 4, kb.tuning(), f"boundary-{label_max}")
+
+
 # ------------------------------------------------------------------ hash collisions
 
 @pytest.mark.parametrize("bits", [0, 3, 8])
