@@ -41,7 +41,7 @@ typedef uint32_t u32;
 constexpr u64 EMPTY64 = ~0ULL;
 constexpr int WAVE = 64;
 constexpr int SMALL_MAX = 16;        // inline exact check limit (thread per vertex)
-constexpr int RANGE_EDGES = 2048;    // CSR entries per multi-vertex range workgroup
+constexpr int RANGE_EDGES = 1024;    // CSR entries per multi-vertex range workgroup (default)
 constexpr int RANGE_VERTS = 256;     // vertices per range workgroup
 constexpr int RANGE_DMAX = 4096;     // rows above RANGE_EDGES get a workgroup of 512 threads
 constexpr int ROW_MAX = 8192;        // rows above RANGE_DMAX get one of 1024 threads; above this, hubs
@@ -336,12 +336,12 @@ __device__ inline void block_reduce_2(u64 &acc, u32 &cnt, u64 *sh_acc, u32 *sh_c
 }
 
 // Range tier: a workgroup takes a run of consecutive vertices holding at most
-// EMAX entries and RANGE_VERTS vertices (rows of more than RANGE_EDGES entries
-// form a range of their own, EMAX = 2 * RANGE_EDGES).  All entries are
-// gathered at once (EMAX/256 per thread, loads issued before dependent work,
-// consecutive entries on consecutive lanes), then inserted into their
-// vertex's region of an LDS hash set (2*deg slots at offset 2*row offset);
-// per-vertex sums are formed from the set afterwards.
+// EMAX entries (the range capacity, 1024 or 2048) and RANGE_VERTS vertices;
+// longer rows go to the row tier.  All entries are gathered at once (EMAX/256
+// per thread, loads issued before dependent work, consecutive entries on
+// consecutive lanes), then inserted into their vertex's region of an LDS hash
+// set (2*deg slots at offset 2*row offset); the first insertion of a pair
+// adds its mix to the vertex's sum.
 template <class Src, int EMAX, class K = u64>
 __global__ void __launch_bounds__(256) k_sig_range(Src src, const Range *__restrict__ ranges, u64 *__restrict__ H,
                                                    u32 *__restrict__ DC, u64 *table, u64 tmask,
@@ -480,8 +480,8 @@ __global__ void __launch_bounds__(256) k_sig_range(Src src, const Range *__restr
   zero_insert_wave(zrep, zero, own, (u32)v, zep);
 }
 
-// Row tier: one workgroup of NT threads per row of RANGE_EDGES < deg <= EMAX
-// entries.  All entries are gathered at once (EMAX / NT per thread), then
+// Row tier: one workgroup of NT threads per row of more entries than the
+// range capacity and at most EMAX.  All entries are gathered at once (EMAX / NT per thread), then
 // inserted into an LDS hash set of 2 * deg slots; first insertions add to
 // thread-local sums, reduced over the workgroup at the end.
 template <class Src, int EMAX, int NT, class K = u64>
