@@ -447,14 +447,44 @@ __global__ void __launch_bounds__(256) k_sig_range(Src src, const Range *__restr
       u32 sl = (u32)scale_to(KO::hash(p), sz);
       while (true) {
         const K old = atomicCAS(&set[base + sl], KO::EMPTY, p);
-        if (old == KO::EMPTY) {
-          atomicAdd(&acc[lo], mix_pair(KO::wide(src, p)));
-          atomicAdd(&cnt[lo], 1u);
-          break;
-        }
-        if (old == p) break;
+        if (old == KO::EMPTY || old == p) break;
         sl = (sl + 1 == sz) ? 0u : sl + 1;
       }
+    }
+  }
+  __syncthreads();
+  // Sums from the set: thread t reads the 2U consecutive slots from 2Ut on;
+  // slot s lies in the region of vertex owner[s / 2].  Runs of one vertex are
+  // summed in registers and added to the vertex once per run, so the shared
+  // accumulators see a few atomics per vertex instead of one per pair.
+  {
+    u64 a = 0;
+    u32 c = 0;
+    int cur = -1;
+#pragma unroll
+    for (int q = 0; q < 2 * U; ++q) {
+      const int sidx = 2 * U * t + q;
+      if (sidx < 2 * E) {
+        const int lo = owner[sidx >> 1];
+        if (lo != cur) {
+          if (c) {
+            atomicAdd(&acc[cur], a);
+            atomicAdd(&cnt[cur], c);
+          }
+          cur = lo;
+          a = 0;
+          c = 0;
+        }
+        const K p = set[sidx];
+        if (p != KO::EMPTY) {
+          a += mix_pair(KO::wide(src, p));
+          ++c;
+        }
+      }
+    }
+    if (c) {
+      atomicAdd(&acc[cur], a);
+      atomicAdd(&cnt[cur], c);
     }
   }
   __syncthreads();
