@@ -187,6 +187,25 @@ int kbisim_batch_context(kbisim_batch *b, kbisim_ctx **ctx);
 
 int kbisim_batch_destroy(kbisim_batch *b);
 
+/* ---- graph preparation -------------------------------------------------- */
+
+/* Backward refinement (Def. inverse-schema-element; the backward models of
+ * Sec. "Bisimulation Variants", e.g. Kaushik's vertex-labelled backward
+ * bisimulation) is forward refinement of the transposed graph.
+ * kbisim_transpose writes the transpose of (row_ptr, col, elabel): row w of
+ * the output lists every entry (v, l, w) of the input as (l, v).
+ *   out_row_ptr  device int64 [n+1]
+ *   out_col      device int32 [m]
+ *   out_elabel   device int32 [m] or NULL (zeros when elabel is NULL)
+ *   workspace    device, kbisim_transpose_workspace_bytes(n, m) bytes
+ * The order of entries inside an output row is unspecified; refinement does
+ * not depend on it.  Validates the input first; synchronises `stream`.
+ * Errors: EINVAL, ERANGE, ENOSPACE, EGRAPH (invalid input), EHIP.           */
+int kbisim_transpose_workspace_bytes(int64_t n, int64_t m, size_t *bytes);
+int kbisim_transpose(int64_t n, int64_t m, const int64_t *row_ptr, const int32_t *col, const int32_t *elabel,
+                     int64_t *out_row_ptr, int32_t *out_col, int32_t *out_elabel, void *workspace, size_t ws_bytes,
+                     void *stream);
+
 /* ---- tracing and measurement -------------------------------------------- */
 
 /* Kernel kinds reported by the per-kernel profiler. */

@@ -77,6 +77,10 @@ def _lib():
     lib.kbisim_batch_create.argtypes = [ctypes.POINTER(_Graph), i64, vp, i32, ctypes.POINTER(Tuning), vp, sz, vp,
                                         ctypes.POINTER(vp)]
     lib.kbisim_batch_refine.argtypes = [vp, i32, ctypes.POINTER(vp), vp]
+    lib.kbisim_transpose_workspace_bytes.argtypes = [i64, i64, ctypes.POINTER(sz)]
+    lib.kbisim_transpose_workspace_bytes.restype = i32
+    lib.kbisim_transpose.argtypes = [i64, i64, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    lib.kbisim_transpose.restype = i32
     lib.kbisim_profile_select.argtypes = [vp, ctypes.c_uint32]
     lib.kbisim_profile_select.restype = i32
     lib.kbisim_batch_step_async.argtypes = [vp, i32, vp]
@@ -297,6 +301,35 @@ def to_device(g, device="cuda"):
     def t(a):
         return None if a is None else torch.from_numpy(a).to(device)
     return t(g.row_ptr), t(g.col), t(g.elabel), t(g.vlabel), t(g.vlabel_ptr)
+
+
+def transpose(row_ptr: torch.Tensor, col: torch.Tensor, elabel: Optional[torch.Tensor] = None,
+              stream=None) -> Tuple[torch.Tensor, torch.Tensor, Optional[torch.Tensor]]:
+    """Transposed CSR on the device (backward refinement = forward refinement of the transpose).
+
+    Returns (row_ptr, col, elabel) device tensors; elabel is None when the input has none.
+    """
+    lib = _lib()
+    dev = row_ptr.device
+    row_ptr = _check(row_ptr, torch.int64, "row_ptr", dev)
+    col = _check(col, torch.int32, "col", dev)
+    elabel = _check(elabel, torch.int32, "elabel", dev)
+    n, m = int(row_ptr.numel()) - 1, int(col.numel())
+    nbytes = ctypes.c_size_t(0)
+    rc = lib.kbisim_transpose_workspace_bytes(n, m, ctypes.byref(nbytes))
+    if rc:
+        raise KbisimError(rc, "kbisim_transpose_workspace_bytes")
+    with torch.cuda.device(dev):
+        ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=dev)
+        out_rp = torch.empty(n + 1, dtype=torch.int64, device=dev)
+        out_col = torch.empty(max(m, 0), dtype=torch.int32, device=dev)
+        out_el = torch.empty(max(m, 0), dtype=torch.int32, device=dev) if elabel is not None else None
+        torch.cuda.current_stream().synchronize()
+        rc = lib.kbisim_transpose(n, m, _ptr(row_ptr), _ptr(col), _ptr(elabel), _ptr(out_rp), _ptr(out_col),
+                                  _ptr(out_el), _ptr(ws), int(nbytes.value), _stream_handle(stream))
+    if rc:
+        raise KbisimError(rc, "kbisim_transpose")
+    return out_rp, out_col, out_el
 
 
 def refiner_for(g, kmax: int = 10, device="cuda") -> Refiner:

@@ -1220,6 +1220,80 @@ int kbisim_batch_destroy(kbisim_batch *b) {
   return KBISIM_OK;
 }
 
+namespace {
+struct TransposePlan {
+  size_t off_cnt, off_tiles, off_cursor, total;
+  int64_t ntiles;
+};
+TransposePlan transpose_plan(int64_t n) {
+  TransposePlan p{};
+  size_t at = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = at;
+    at = align_up(at + std::max<size_t>(bytes, 1));
+    return o;
+  };
+  p.ntiles = (std::max<int64_t>(n, 1) + SCAN_TILE - 1) / SCAN_TILE;
+  p.off_cnt = take(4 * (size_t)std::max<int64_t>(n, 1));
+  p.off_tiles = take(8 * (size_t)p.ntiles);
+  p.off_cursor = take(8 * (size_t)std::max<int64_t>(n, 1));
+  p.total = at;
+  return p;
+}
+}  // namespace
+
+int kbisim_transpose_workspace_bytes(int64_t n, int64_t m, size_t *bytes) {
+  if (!bytes || n < 0 || m < 0) return KBISIM_EINVAL;
+  if (n >= (int64_t(1) << 31)) return KBISIM_ERANGE;
+  *bytes = transpose_plan(n).total;
+  return KBISIM_OK;
+}
+
+int kbisim_transpose(int64_t n, int64_t m, const int64_t *row_ptr, const int32_t *col, const int32_t *elabel,
+                     int64_t *out_row_ptr, int32_t *out_col, int32_t *out_elabel, void *workspace, size_t ws_bytes,
+                     void *stream) {
+  if (n < 0 || m < 0 || !row_ptr || !out_row_ptr || (m > 0 && (!col || !out_col))) return KBISIM_EINVAL;
+  if (n >= (int64_t(1) << 31)) return KBISIM_ERANGE;
+  const TransposePlan p = transpose_plan(n);
+  if (!workspace || ws_bytes < p.total) return KBISIM_ENOSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  char *w = (char *)workspace;
+  int *cnt = (int *)(w + p.off_cnt);
+  int64_t *tiles = (int64_t *)(w + p.off_tiles);
+  unsigned long long *cursor = (unsigned long long *)(w + p.off_cursor);
+  u32 *err = (u32 *)(w + p.off_tiles);  // scratch word, reused by the scan afterwards
+  if (n == 0) {
+    if (m > 0) return KBISIM_EGRAPH;
+    k_fill_u64<<<1, 64, 0, s>>>((u64 *)out_row_ptr, 1, 0);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s));
+    return KBISIM_OK;
+  }
+  // validate the input (row offsets monotone from 0 to m, targets in range)
+  k_fill_i32<<<1, 64, 0, s>>>((int *)err, 1, 0);
+  k_validate_rows<<<blocks_for(n + 1, 256), 256, 0, s>>>(n, m, row_ptr, err, ERR_GRAPH_ROWPTR);
+  if (m > 0) {
+    k_validate_vals<<<blocks_for(m, 256), 256, 0, s>>>(m, col, n, err, ERR_GRAPH_COL);
+    if (elabel) k_validate_vals<<<blocks_for(m, 256), 256, 0, s>>>(m, elabel, -1, err, ERR_GRAPH_ELABEL);
+  }
+  HIP_TRY(hipGetLastError());
+  u32 bad = 0;
+  HIP_TRY(hipMemcpyAsync(&bad, err, sizeof bad, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (bad) return KBISIM_EGRAPH;
+  k_fill_i32<<<blocks_for(n, 256), 256, 0, s>>>(cnt, n, 0);
+  if (m > 0) k_indegree<<<(unsigned)std::min<int64_t>(blocks_for(m, 256), 65536), 256, 0, s>>>(m, col, cnt);
+  k_sum_tiles64<<<(unsigned)p.ntiles, 256, 0, s>>>(n, cnt, tiles);
+  k_scan_tiles64<<<1, 256, 0, s>>>(p.ntiles, tiles);
+  k_write_ptr64<<<(unsigned)p.ntiles, 256, 0, s>>>(n, cnt, tiles, out_row_ptr, cursor);
+  if (m > 0)
+    k_transpose_scatter<<<(unsigned)std::min<int64_t>(blocks_for(n * WAVE, 256), 65536), 256, 0, s>>>(
+        n, row_ptr, col, elabel, cursor, out_col, out_elabel);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(s));
+  return KBISIM_OK;
+}
+
 const char *kbisim_strerror(int code) {
   switch (code) {
     case KBISIM_OK: return "ok";

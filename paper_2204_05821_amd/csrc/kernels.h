@@ -1175,6 +1175,105 @@ __global__ void k_assign(int n, const int *__restrict__ rep, int *out, const int
 
 // In-degree histogram, target renumbering and rank-order scatter (create time
 // and the start of each call).
+// ---------------------------------------------------------------- transpose
+// Backward refinement is forward refinement of the transposed graph
+// (Def. inverse-schema-element).  Transpose = count entries per target,
+// exclusive scan into row offsets, scatter each entry (v, l, w) to row w.
+
+// Exclusive scan of 64-bit values over a 256-thread workgroup.
+__device__ inline int64_t block_exclusive_scan64(int64_t mine, int64_t *sh_w, int64_t *total) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  int64_t x = mine;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int64_t y = __shfl_up(x, o, WAVE);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) sh_w[w] = x;
+  __syncthreads();
+  int64_t base = 0;
+  for (int i = 0; i < w; ++i) base += sh_w[i];
+  *total = sh_w[0] + sh_w[1] + sh_w[2] + sh_w[3];
+  __syncthreads();
+  return base + x - mine;
+}
+
+__global__ void __launch_bounds__(256) k_sum_tiles64(int64_t n, const int *__restrict__ cnt, int64_t *tile_sum) {
+  __shared__ int64_t sh_w[4];
+  const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+  int64_t mine = 0;
+#pragma unroll
+  for (int j = 0; j < SCAN_ITEMS; ++j)
+    if (base + j < n) mine += cnt[base + j];
+  int64_t total;
+  block_exclusive_scan64(mine, sh_w, &total);
+  if (threadIdx.x == 0) tile_sum[blockIdx.x] = total;
+}
+
+// One workgroup of 256 threads: in-place exclusive scan of ntiles sums.
+__global__ void __launch_bounds__(256) k_scan_tiles64(int64_t ntiles, int64_t *tile_sum) {
+  __shared__ int64_t sh_w[4];
+  __shared__ int64_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int64_t b0 = 0; b0 < ntiles; b0 += 256) {
+    const int64_t i = b0 + threadIdx.x;
+    const int64_t mine = i < ntiles ? tile_sum[i] : 0;
+    int64_t total;
+    const int64_t ex = block_exclusive_scan64(mine, sh_w, &total);
+    if (i < ntiles) tile_sum[i] = carry + ex;
+    __syncthreads();
+    if (threadIdx.x == 0) carry += total;
+    __syncthreads();
+  }
+}
+
+// out_ptr[i] = sum of cnt[0..i), out_ptr[n] = total; cursor[i] = out_ptr[i].
+__global__ void __launch_bounds__(256) k_write_ptr64(int64_t n, const int *__restrict__ cnt,
+                                                     const int64_t *__restrict__ tile_pre, int64_t *out_ptr,
+                                                     unsigned long long *cursor) {
+  __shared__ int64_t sh_w[4];
+  const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+  int64_t c[SCAN_ITEMS];
+  int64_t mine = 0;
+#pragma unroll
+  for (int j = 0; j < SCAN_ITEMS; ++j) {
+    c[j] = base + j < n ? cnt[base + j] : 0;
+    mine += c[j];
+  }
+  int64_t total;
+  int64_t off = tile_pre[blockIdx.x] + block_exclusive_scan64(mine, sh_w, &total);
+#pragma unroll
+  for (int j = 0; j < SCAN_ITEMS; ++j) {
+    if (base + j < n) {
+      out_ptr[base + j] = off;
+      cursor[base + j] = (unsigned long long)off;
+    }
+    off += c[j];
+    if (base + j + 1 == n) out_ptr[n] = off;
+  }
+}
+
+// One wave per source row: every entry (v, l, w) takes the next free
+// position of row w.  The order inside a transposed row depends on timing;
+// signatures are sets, so refinement results do not.
+__global__ void __launch_bounds__(256) k_transpose_scatter(int64_t n, const int64_t *__restrict__ row_ptr,
+                                                           const int32_t *__restrict__ col,
+                                                           const int32_t *__restrict__ elabel,
+                                                           unsigned long long *cursor, int32_t *out_col,
+                                                           int32_t *out_elabel) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t v = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; v < n; v += waves) {
+    const int64_t b = row_ptr[v], e = row_ptr[v + 1];
+    for (int64_t i = b + lane; i < e; i += WAVE) {
+      const unsigned long long pos = atomicAdd(&cursor[col[i]], 1ULL);
+      out_col[pos] = (int32_t)v;
+      if (out_elabel) out_elabel[pos] = elabel ? elabel[i] : 0;
+    }
+  }
+}
+
 __global__ void k_indegree(int64_t m, const int *__restrict__ col, int *indeg) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x)
     atomicAdd(&indeg[col[e]], 1);

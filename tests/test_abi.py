@@ -93,3 +93,23 @@ def test_null_context_and_strerror(lib):
         assert lib.kbisim_strerror(code)
     lib.kbisim_destroy.argtypes = [ctypes.c_void_p]
     assert lib.kbisim_destroy(None) == 0
+
+
+def test_transpose_argument_checks_before_touching_the_device(lib):
+    wb = lib.kbisim_transpose_workspace_bytes
+    wb.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p]
+    wb.restype = ctypes.c_int
+    out = ctypes.c_size_t(0)
+    assert wb(100, 50, None) == -1
+    assert wb(-1, 0, ctypes.byref(out)) == -1
+    assert wb(1 << 31, 0, ctypes.byref(out)) == -5
+    assert wb(1000, 5000, ctypes.byref(out)) == 0 and out.value >= 12 * 1000
+    f = lib.kbisim_transpose
+    f.argtypes = [ctypes.c_int64, ctypes.c_int64] + [ctypes.c_void_p] * 7 + [ctypes.c_size_t, ctypes.c_void_p]
+    f.restype = ctypes.c_int
+    fake = ctypes.c_void_p(0x1000)   # never dereferenced: every case fails before a HIP call
+    assert f(1000, 5000, None, fake, None, fake, fake, None, fake, 1 << 30, None) == -1
+    assert f(1000, 5000, fake, None, None, fake, fake, None, fake, 1 << 30, None) == -1
+    assert f(1000, 5000, fake, fake, None, fake, fake, None, None, 1 << 30, None) == -3
+    assert f(1000, 5000, fake, fake, None, fake, fake, None, fake, 8, None) == -3
+    assert f(1 << 31, 5, fake, fake, None, fake, fake, None, fake, 1 << 30, None) == -5
