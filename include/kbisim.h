@@ -123,6 +123,17 @@ int kbisim_create_tuned(const kbisim_graph *g, int kmax, const kbisim_tuning *tu
  * per-kernel profiler is on.                                                */
 int kbisim_use_graphs(kbisim_ctx *c, int enable);
 
+/* Work-efficient mode (enable = 1; 0 = off, the default; -1 = leave as is).
+ * The outputs are the same; the work is not: a vertex alone in its block is
+ * not refined again (a singleton block cannot split), and once a step leaves
+ * the block count unchanged the partition is a fixpoint (a refinement with as
+ * many blocks is the same partition), so the remaining outputs are copies.
+ * Calls synchronise after every step to read its count; graph capture is not
+ * used while the mode is on.  *last_steps (may be NULL) receives the number
+ * of steps the last call computed.  This mode is reported separately from
+ * the full-work figures.                                                    */
+int kbisim_work_efficient(kbisim_ctx *c, int enable, int *last_steps);
+
 /* Copy P_0 into out_ids (device int32 [n]) and its block count into
  * *out_count (host).  Synchronises the stream.                              */
 int kbisim_initial(kbisim_ctx *c, int32_t *out_ids, int64_t *out_count);

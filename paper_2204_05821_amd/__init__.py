@@ -81,6 +81,8 @@ def _lib():
     lib.kbisim_transpose_workspace_bytes.restype = i32
     lib.kbisim_transpose.argtypes = [i64, i64, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     lib.kbisim_transpose.restype = i32
+    lib.kbisim_work_efficient.argtypes = [vp, i32, ctypes.POINTER(i32)]
+    lib.kbisim_work_efficient.restype = i32
     lib.kbisim_profile_select.argtypes = [vp, ctypes.c_uint32]
     lib.kbisim_profile_select.restype = i32
     lib.kbisim_batch_step_async.argtypes = [vp, i32, vp]
@@ -216,6 +218,14 @@ class Refiner:
         if rc:
             raise KbisimError(rc, "kbisim_initial")
         return out, int(cnt.value)
+
+    def work_efficient(self, enable: Optional[bool] = True) -> int:
+        """Turn the work-efficient mode on/off (None: leave it); returns the steps the last call computed."""
+        steps = ctypes.c_int(0)
+        rc = _lib().kbisim_work_efficient(self._ctx, -1 if enable is None else int(bool(enable)), ctypes.byref(steps))
+        if rc:
+            raise KbisimError(rc, "kbisim_work_efficient")
+        return int(steps.value)
 
     def profile(self, enable: bool = True, kinds: Optional[Sequence[str]] = None) -> None:
         """Start (and reset) or stop per-kernel event timing of later refine calls;
@@ -419,6 +429,14 @@ class Batch:
             raise KbisimError(rc, "kbisim_batch_refine")
         cl = [[int(counts[g * k + i]) for i in range(k)] for g in range(self.num_graphs)]
         return list(out[:k]), cl
+
+    def work_efficient(self, enable: Optional[bool] = True) -> int:
+        """Turn the work-efficient mode on/off (None: leave it); returns the steps the last call computed."""
+        steps = ctypes.c_int(0)
+        rc = _lib().kbisim_work_efficient(self._ctx, -1 if enable is None else int(bool(enable)), ctypes.byref(steps))
+        if rc:
+            raise KbisimError(rc, "kbisim_work_efficient")
+        return int(steps.value)
 
     def step_async(self, i: int, out: torch.Tensor) -> None:
         """Enqueue step i (per-graph ids of P_{i+1} into out) without synchronising."""

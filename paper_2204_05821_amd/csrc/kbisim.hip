@@ -52,7 +52,7 @@ struct Plan {
   size_t off_H, off_DC, off_rep, off_p0, off_vlist, off_clA, off_clB, off_ranges, off_lists, off_gcol, off_rank,
       off_gpid, off_zrep;
   size_t off_table, off_ctable, off_hacc, off_hcnt, off_chunks, off_parts, off_gchunks, off_poff;
-  size_t off_status, off_counters, off_dcounts, off_err, off_dep, off_hubsets;
+  size_t off_status, off_counters, off_dcounts, off_err, off_dep, off_hubsets, off_single, off_multi;
   size_t off_gid, off_ibuf, off_first, off_next, off_bcounts;  // batches only
   uint64_t tslots;
   int64_t max_ranges, max_lists, nhub_max, nchunk_max, npart_max, ngchunk_max, npoff_max, ntiles, hubset_slots;
@@ -113,6 +113,8 @@ Plan make_plan(int64_t n, int64_t m, int64_t nl, int kmax, int64_t num_graphs) {
   p.off_err = take(16);
   p.off_dep = take(64);
   p.off_hubsets = take(8 * (size_t)p.hubset_slots);
+  p.off_single = take(2 * N);
+  p.off_multi = take(4 * N);
   if (num_graphs > 0) {
     p.off_gid = take(4 * N);
     p.off_ibuf = take(8 * N);
@@ -175,6 +177,10 @@ struct kbisim_ctx {
   Schedule sched;  // graph rows
   u64 hmask = ~0ULL;
   u64 tmask_steps = 0;   // grouping-table mask of refinement steps (sized by vertices with edges)
+  bool work_eff = false;  // skip singleton blocks, stop at the fixpoint
+  int we_steps = 0;       // steps computed by the last work-efficient call
+  unsigned char *single[2] = {nullptr, nullptr};  // singleton flags of the last two partitions
+  u32 *multi = nullptr;  // stamps of heads that have a non-head member
   u32 prof_mask = ~0u;   // kernel kinds timed by the profiler
   bool narrow = false;  // 32-bit LDS keys: (edge label << pb) | block fits in 31 bits
   u32 pb = 31;
@@ -502,29 +508,44 @@ u64 table_mask(const kbisim_ctx *c) {
   return c->plan.tslots - 1;
 }
 
+template <class Src, class K, bool SKIP>
+int launch_range_kernel(kbisim_ctx *c, const Src &src, const Schedule &s, u64 tmask, int zfresh,
+                        const unsigned char *skip) {
+  ProfScope ps(c, KBISIM_K_SIG_RANGE);
+  if (c->tune.range_edges == 1024)
+    k_sig_range<Src, 1024, K, SKIP><<<(unsigned)s.nranges, 256, 0, c->stream>>>(
+        src, c->ranges, c->H, c->DC, c->table, tmask, c->dep, c->hmask, c->zrep, zfresh, skip);
+  else
+    k_sig_range<Src, 2048, K, SKIP><<<(unsigned)s.nranges, 256, 0, c->stream>>>(
+        src, c->ranges, c->H, c->DC, c->table, tmask, c->dep, c->hmask, c->zrep, zfresh, skip);
+  LAUNCH_CHECK();
+  return 0;
+}
+
+// skip: singleton flags of the previous partition (work-efficient mode), or NULL.
 template <class Src, class K>
-int launch_ranges_k(kbisim_ctx *c, const Src &src, const Schedule &s, int zfresh) {
+int launch_ranges_k(kbisim_ctx *c, const Src &src, const Schedule &s, int zfresh, const unsigned char *skip) {
   const u64 tmask = table_mask<Src>(c);
   if (s.nranges) {
-    ProfScope ps(c, KBISIM_K_SIG_RANGE);
-    if (c->tune.range_edges == 1024)
-      k_sig_range<Src, 1024, K><<<(unsigned)s.nranges, 256, 0, c->stream>>>(src, c->ranges, c->H, c->DC, c->table,
-                                                                            tmask, c->dep, c->hmask, c->zrep, zfresh);
-    else
-      k_sig_range<Src, 2048, K><<<(unsigned)s.nranges, 256, 0, c->stream>>>(src, c->ranges, c->H, c->DC, c->table,
-                                                                            tmask, c->dep, c->hmask, c->zrep, zfresh);
-    LAUNCH_CHECK();
+    int rc = 0;
+    if constexpr (std::is_same<Src, GraphSrc>::value) {
+      rc = skip ? launch_range_kernel<Src, K, true>(c, src, s, tmask, zfresh, skip)
+                : launch_range_kernel<Src, K, false>(c, src, s, tmask, zfresh, nullptr);
+    } else {
+      rc = launch_range_kernel<Src, K, false>(c, src, s, tmask, zfresh, nullptr);
+    }
+    if (rc) return rc;
   }
   if (s.nbig || s.nrow8) {
     ProfScope ps(c, KBISIM_K_SIG_BLOCK);
     if (s.nbig) {
       k_sig_row<Src, RANGE_DMAX, 512, K><<<(unsigned)s.nbig, 512, 0, c->stream>>>(
-          src, c->ranges + s.nranges, c->H, c->DC, c->table, tmask, c->dep, c->hmask, c->zrep);
+          src, c->ranges + s.nranges, c->H, c->DC, c->table, tmask, c->dep, c->hmask, c->zrep, skip);
       LAUNCH_CHECK();
     }
     if (s.nrow8) {
       k_sig_row<Src, ROW_MAX, 1024, K><<<(unsigned)s.nrow8, 1024, 0, c->stream>>>(
-          src, c->ranges + s.nranges + s.nbig, c->H, c->DC, c->table, tmask, c->dep, c->hmask, c->zrep);
+          src, c->ranges + s.nranges + s.nbig, c->H, c->DC, c->table, tmask, c->dep, c->hmask, c->zrep, skip);
       LAUNCH_CHECK();
     }
   }
@@ -532,31 +553,32 @@ int launch_ranges_k(kbisim_ctx *c, const Src &src, const Schedule &s, int zfresh
 }
 
 template <class Src>
-int launch_ranges(kbisim_ctx *c, const Src &src, const Schedule &s, int zfresh) {
+int launch_ranges(kbisim_ctx *c, const Src &src, const Schedule &s, int zfresh, const unsigned char *skip) {
   if constexpr (std::is_same<Src, GraphSrc>::value) {
-    if (c->narrow) return launch_ranges_k<Src, u32>(c, src, s, zfresh);
+    if (c->narrow) return launch_ranges_k<Src, u32>(c, src, s, zfresh, skip);
   }
-  return launch_ranges_k<Src, u64>(c, src, s, zfresh);
+  return launch_ranges_k<Src, u64>(c, src, s, zfresh, skip);
 }
 
 // Staged hub rows: chunk dedupe and partitioned staging, then per-partition
 // dedupe and sums.  K: width of the staged keys.
 template <class Src, class K>
-int launch_hub_staged(kbisim_ctx *c, const Src &src, const Schedule &s, const int *hubs) {
+int launch_hub_staged(kbisim_ctx *c, const Src &src, const Schedule &s, const int *hubs,
+                      const unsigned char *skip) {
   K *stage = reinterpret_cast<K *>(c->hubsets);
   {
     ProfScope ps(c, KBISIM_K_HUB_STAGE);
     if (c->tune.hub_chunk == 2048)
       k_hub_stage<Src, 2048, K><<<(unsigned)s.nchunks, 256, 0, c->stream>>>(src, c->chunks, hubs, stage, c->poff,
-                                                                            c->err);
+                                                                            c->err, skip);
     else
       k_hub_stage<Src, 4096, K><<<(unsigned)s.nchunks, 256, 0, c->stream>>>(src, c->chunks, hubs, stage, c->poff,
-                                                                            c->err);
+                                                                            c->err, skip);
     LAUNCH_CHECK();
   }
   ProfScope ps(c, KBISIM_K_HUB_REDUCE);
   k_hub_reduce<Src, K><<<(unsigned)s.nparts, 256, 0, c->stream>>>(src, c->parts, c->chunks, stage, c->poff, c->hacc,
-                                                                  c->hcnt, c->err);
+                                                                  c->hcnt, c->err, hubs, skip);
   LAUNCH_CHECK();
   return 0;
 }
@@ -568,41 +590,47 @@ int launch_hub_staged(kbisim_ctx *c, const Src &src, const Schedule &s, const in
 // zfresh: group vertices with an empty signature afresh (the first step of a
 // call); otherwise their representatives from that step are kept, since two
 // such vertices share a block after a step exactly when they did before it.
+// skip_in / single_out (work-efficient mode, else NULL): singleton flags of
+// the previous partition (those vertices are not refined: a singleton block
+// cannot split) and of the new one.
 template <class Src>
 int run_step(kbisim_ctx *c, const Src &src, const Schedule &s, int *out, int64_t *count_dev, int *cnt,
-             bool careful, int *gpid_next, bool zfresh) {
+             bool careful, int *gpid_next, bool zfresh, const unsigned char *skip_in = nullptr,
+             unsigned char *single_out = nullptr) {
   const int n = (int)c->g.n;
   if (n == 0) return 0;
   const u64 tmask = table_mask<Src>(c);
   int rc = advance(c, ADV_TABLE | ADV_CTABLE | ADV_ZERO | (s.ngchunks ? ADV_HUB : 0u), s);
   if (rc) return rc;
-  if ((rc = launch_ranges(c, src, s, zfresh ? 1 : 0))) return rc;
+  if ((rc = launch_ranges(c, src, s, zfresh ? 1 : 0, skip_in))) return rc;
   if (s.nhub) {
     const int *hubs = c->lists + s.hub_off;
     if (s.nchunks) {
       if constexpr (std::is_same<Src, GraphSrc>::value) {
-        rc = c->narrow ? launch_hub_staged<Src, u32>(c, src, s, hubs) : launch_hub_staged<Src, u64>(c, src, s, hubs);
+        rc = c->narrow ? launch_hub_staged<Src, u32>(c, src, s, hubs, skip_in)
+                       : launch_hub_staged<Src, u64>(c, src, s, hubs, skip_in);
       } else {
-        rc = launch_hub_staged<Src, u64>(c, src, s, hubs);
+        rc = launch_hub_staged<Src, u64>(c, src, s, hubs, skip_in);
       }
       if (rc) return rc;
     }
     if (s.ngchunks) {
       ProfScope ps(c, KBISIM_K_HUB_STAGE);
       k_sig_hub_global<Src><<<(unsigned)s.ngchunks, 256, 0, c->stream>>>(src, c->gchunks, hubs, c->hubsets, c->hacc,
-                                                                         c->hcnt, c->dep);
+                                                                         c->hcnt, c->dep, skip_in);
       LAUNCH_CHECK();
     }
     ProfScope ps(c, KBISIM_K_HUB_FINAL);
     k_hub_final<Src><<<blocks_for(s.nhub, 256), 256, 0, c->stream>>>(src, hubs, s.nhub, c->hacc, c->hcnt, c->H, c->DC,
-                                                                     c->table, tmask, c->dep, c->hmask, c->zrep);
+                                                                     c->table, tmask, c->dep, c->hmask, c->zrep,
+                                                                     skip_in);
     LAUNCH_CHECK();
   }
   {
     ProfScope ps(c, KBISIM_K_LOOKUP);
     k_lookup<Src><<<blocks_for(n, 256), 256, 0, c->stream>>>(src, n, c->H, c->DC, c->table, tmask, c->dep, c->rep,
                                                              &cnt[0], c->vlist, &cnt[1], c->clA, c->err, c->zrep,
-                                                             zfresh ? 1 : 0);
+                                                             zfresh ? 1 : 0, skip_in);
     LAUNCH_CHECK();
   }
   {
@@ -642,8 +670,13 @@ int run_step(kbisim_ctx *c, const Src &src, const Schedule &s, int *out, int64_t
   }
   {
     ProfScope ps(c, KBISIM_K_ASSIGN);
-    k_assign<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, c->rep, out, gpid_next ? c->rank : nullptr, gpid_next);
+    k_assign<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, c->rep, out, gpid_next ? c->rank : nullptr, gpid_next,
+                                                        single_out ? c->multi : nullptr, c->dep);
     LAUNCH_CHECK();
+    if (single_out) {
+      k_singletons<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, c->rep, c->multi, c->dep, single_out);
+      LAUNCH_CHECK();
+    }
   }
   return 0;
 }
@@ -667,8 +700,11 @@ int enqueue_steps(kbisim_ctx *c, const int32_t *prev, int i0, int k, int32_t *co
     if (careful && (rc = fill_i32(c, c->counters + CNT_STRIDE * i, CNT_STRIDE, 0))) return rc;
     int *dst = batch ? c->ibuf[i & 1] : out[i];
     GraphSrc src{c->g.row_ptr, c->gcol, c->g.elabel, c->gpid[i & 1], prev, c->pb};
+    // work-efficient mode: singletons of P_i (flags of step i-1) are not refined
+    const unsigned char *skip_in = (c->work_eff && i > 0) ? c->single[(i - 1) & 1] : nullptr;
+    unsigned char *single_out = c->work_eff ? c->single[i & 1] : nullptr;
     rc = run_step(c, src, c->sched, dst, &c->dcounts[i], c->counters + CNT_STRIDE * i, careful, c->gpid[(i + 1) & 1],
-                  i == 0);
+                  i == 0, skip_in, single_out);
     if (rc) return rc;
     if (batch) {
       k_rebase<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, c->gid, c->first, dst, out[i]);
@@ -680,6 +716,63 @@ int enqueue_steps(kbisim_ctx *c, const int32_t *prev, int i0, int k, int32_t *co
     prev = dst;
   }
   return 0;
+}
+
+// Work-efficient refinement: singleton blocks are not refined (skip flags
+// from the previous step), and once a step leaves the block count unchanged
+// the partition is a fixpoint (a refinement with as many blocks is the same
+// partition), so the remaining outputs are copies.  Synchronises after every
+// step to read its count.
+int refine_we(kbisim_ctx *c, const int32_t *start, int k, int32_t *const *out, int64_t *counts) {
+  const int n = (int)c->g.n;
+  const bool batch = c->num_graphs > 0;
+  const int32_t *p0 = start ? start : c->p0;
+  int64_t prev_count = start ? -1 : c->p0_count;
+  int rc = 0;
+  if ((rc = fill_i32(c, c->counters, (int64_t)CNT_STRIDE * k, 0))) return rc;
+  if ((rc = fill_i32(c, (int *)c->err, 1, 0))) return rc;
+  int done = k;
+  for (int i = 0; i < k; ++i) {
+    const int32_t *prev = i == 0 ? p0 : (batch ? c->ibuf[(i - 1) & 1] : out[i - 1]);
+    if ((rc = enqueue_steps(c, prev, i, i + 1, out, false, k, i == 0))) return rc;
+    int left = 0;
+    u32 err = 0;
+    int64_t cnt = 0;
+    HIP_TRY(hipMemcpyAsync(&left, c->counters + CNT_STRIDE * i + 2, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(&err, c->err, sizeof err, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(&cnt, &c->dcounts[i], 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    prof_collect(c);
+    if (err) return KBISIM_EINTERNAL;
+    if (left) {
+      if ((rc = enqueue_steps(c, prev, i, i + 1, out, true, k, true))) return rc;
+      HIP_TRY(hipMemcpyAsync(&err, c->err, sizeof err, hipMemcpyDeviceToHost, c->stream));
+      HIP_TRY(hipMemcpyAsync(&cnt, &c->dcounts[i], 8, hipMemcpyDeviceToHost, c->stream));
+      HIP_TRY(hipStreamSynchronize(c->stream));
+      prof_collect(c);
+      if (err) return KBISIM_EINTERNAL;
+    }
+    if (cnt == prev_count) {
+      done = i + 1;
+      break;
+    }
+    prev_count = cnt;
+  }
+  for (int j = done; j < k; ++j)
+    HIP_TRY(hipMemcpyAsync(out[j], out[done - 1], 4 * (size_t)n, hipMemcpyDeviceToDevice, c->stream));
+  if (batch) {
+    const int64_t G = c->num_graphs;
+    HIP_TRY(hipMemcpyAsync(counts, c->bcounts, 8 * (size_t)(G * k), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    for (int64_t g = 0; g < G; ++g)
+      for (int j = done; j < k; ++j) counts[g * k + j] = counts[g * k + done - 1];
+  } else {
+    HIP_TRY(hipMemcpyAsync(counts, c->dcounts, 8 * (size_t)done, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    for (int j = done; j < k; ++j) counts[j] = counts[done - 1];
+  }
+  c->we_steps = done;
+  return KBISIM_OK;
 }
 
 int refine_impl(kbisim_ctx *c, const int32_t *start, int k, int32_t *const *out, int64_t *counts) {
@@ -696,6 +789,7 @@ int refine_impl(kbisim_ctx *c, const int32_t *start, int k, int32_t *const *out,
     for (int64_t i = 0; i < ncounts; ++i) counts[i] = 0;
     return KBISIM_OK;
   }
+  if (c->work_eff) return refine_we(c, start, k, out, counts);
   const int32_t *p0 = start ? start : c->p0;
   int rc = 0;
   const bool graphed = c->use_graphs && !c->prof;
@@ -852,6 +946,9 @@ int create_impl(const kbisim_graph *g, int kmax, const kbisim_tuning *tuning, vo
   c->err = (u32 *)(w + plan.off_err);
   c->dep = (u32 *)(w + plan.off_dep);
   c->hubsets = (u64 *)(w + plan.off_hubsets);
+  c->single[0] = (unsigned char *)(w + plan.off_single);
+  c->single[1] = c->single[0] + std::max<int64_t>(n, 1);
+  c->multi = (u32 *)(w + plan.off_multi);
   if (num_graphs > 0) {
     c->num_graphs = num_graphs;
     c->gid = (int *)(w + plan.off_gid);
@@ -945,6 +1042,7 @@ int create_impl(const kbisim_graph *g, int kmax, const kbisim_tuning *tuning, vo
   if ((rc = fill_u64(c, c->table, (int64_t)plan.tslots, 0))) return fail(rc);
   if ((rc = fill_u64(c, c->ctable, (int64_t)plan.tslots, 0))) return fail(rc);
   if ((rc = fill_u64(c, c->zrep, std::max<int64_t>(n, 1), ~0ULL))) return fail(rc);
+  if ((rc = fill_i32(c, (int *)c->multi, std::max<int64_t>(n, 1), 0))) return fail(rc);
 
   // P0: blocks of equal vertex label sets, numbered by first vertex; in a
   // batch the graph id joins the key, so no block spans two graphs.
@@ -1083,6 +1181,13 @@ int kbisim_step_result(kbisim_ctx *c, int i, const int32_t *prev, int32_t *out, 
   }
   HIP_TRY(hipMemcpyAsync(count, &c->dcounts[i], 8, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
+  return KBISIM_OK;
+}
+
+int kbisim_work_efficient(kbisim_ctx *c, int enable, int *last_steps) {
+  if (!c) return KBISIM_EINVAL;
+  if (last_steps) *last_steps = c->we_steps;
+  if (enable >= 0) c->work_eff = enable != 0;
   return KBISIM_OK;
 }
 

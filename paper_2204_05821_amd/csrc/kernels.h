@@ -321,6 +321,25 @@ struct Range {
 
 __device__ inline u64 scale_to(u32 a, u64 n) { return __umul64hi(((u64)a) << 32, n); }
 
+// Exclusive block scan (256 threads) of one u32 per thread; returns the
+// thread's prefix and writes the block total to *total.
+__device__ inline u32 block_exclusive_scan(u32 mine, u32 *sh_w, u32 *total) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  u32 x = mine;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const u32 y = __shfl_up(x, o, WAVE);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) sh_w[w] = x;
+  __syncthreads();
+  u32 base = 0;
+  for (int i = 0; i < w; ++i) base += sh_w[i];
+  *total = sh_w[0] + sh_w[1] + sh_w[2] + sh_w[3];
+  __syncthreads();
+  return base + x - mine;
+}
+
 // Sum over the workgroup; the result is valid in thread 0.  sh_acc and
 // sh_cnt hold one slot per wave.
 __device__ inline void block_reduce_2(u64 &acc, u32 &cnt, u64 *sh_acc, u32 *sh_cnt) {
@@ -340,19 +359,23 @@ __device__ inline void block_reduce_2(u64 &acc, u32 &cnt, u64 *sh_acc, u32 *sh_c
 // longer rows go to the row tier.  All entries are gathered at once (EMAX/256
 // per thread, loads issued before dependent work, consecutive entries on
 // consecutive lanes), then inserted into their vertex's region of an LDS hash
-// set (2*deg slots at offset 2*row offset); the first insertion of a pair
-// adds its mix to the vertex's sum.
-template <class Src, int EMAX, class K = u64>
+// set (2*deg slots at offset 2*row offset); sums are formed from the set.
+// SKIP (work-efficient mode): rows of vertices flagged in skip[] (singleton
+// blocks, which cannot split) are left out; the remaining rows are packed,
+// so their entries are gathered only after the owner scan.
+template <class Src, int EMAX, class K = u64, bool SKIP = false>
 __global__ void __launch_bounds__(256) k_sig_range(Src src, const Range *__restrict__ ranges, u64 *__restrict__ H,
                                                    u32 *__restrict__ DC, u64 *table, u64 tmask,
-                                                   const u32 *__restrict__ dep, u64 hmask, u64 *zrep, int zfresh) {
+                                                   const u32 *__restrict__ dep, u64 hmask, u64 *zrep, int zfresh,
+                                                   const unsigned char *__restrict__ skip) {
   typedef Keys<K> KO;
   constexpr int U = EMAX / 256;
   const u32 epoch = dep[EP_TABLE], zep = dep[EP_ZERO];
   __shared__ K set[2 * EMAX];
   __shared__ u64 acc[RANGE_VERTS];
   __shared__ u32 cnt[RANGE_VERTS];
-  __shared__ int roff[RANGE_VERTS + 1];
+  __shared__ int roff[RANGE_VERTS + 1];  // CSR row offsets, relative to the range
+  __shared__ int coff[SKIP ? RANGE_VERTS + 1 : 1];  // packed offsets (skipped rows empty)
   __shared__ unsigned char owner[EMAX];
   __shared__ u32 wmax[4];
   __shared__ u64 sh_acc[4];
@@ -370,18 +393,32 @@ __global__ void __launch_bounds__(256) k_sig_range(Src src, const Range *__restr
   if (!single)
     for (int i = t; i < EMAX; i += 256) owner[i] = 0;
   __syncthreads();
-  const int E = roff[V];
+  const int *off = roff;  // offsets that place entries and set regions
+  bool skipped = false;   // this thread's vertex (t < V) is left out
+  if constexpr (SKIP) {
+    skipped = t < V && skip[rg.v0 + t];
+    const u32 d = (t < V && !skipped) ? (u32)(roff[t + 1] - roff[t]) : 0u;
+    u32 total;
+    const u32 ex = block_exclusive_scan(d, wmax, &total);
+    if (t < V) coff[t] = (int)ex;
+    if (t == 0) coff[V] = (int)total;
+    __syncthreads();
+    off = coff;
+  }
+  const int E = off[V];
   for (int i = t; i < 2 * E; i += 256) set[i] = KO::EMPTY;
   // the row start of every non-empty vertex marks its index; a max-scan then
   // gives the owner of every entry
   if (!single)
     for (int i = t; i < V; i += 256)
-      if (roff[i + 1] > roff[i]) owner[roff[i]] = (unsigned char)i;
+      if (off[i + 1] > off[i]) owner[off[i]] = (unsigned char)i;
   K pr[U];
+  if constexpr (!SKIP) {
 #pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const int j = t + u * 256;
-    pr[u] = j < E ? KO::load(src, eb + j) : KO::EMPTY;
+    for (int u = 0; u < U; ++u) {
+      const int j = t + u * 256;
+      pr[u] = j < E ? KO::load(src, eb + j) : KO::EMPTY;
+    }
   }
   __syncthreads();
   if (!single) {
@@ -408,6 +445,19 @@ __global__ void __launch_bounds__(256) k_sig_range(Src src, const Range *__restr
     }
     __syncthreads();
   }
+  if constexpr (SKIP) {
+    // packed entry j of row lo sits at CSR offset roff[lo] + (j - coff[lo])
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int j = t + u * 256;
+      K p = KO::EMPTY;
+      if (j < E) {
+        const int lo = single ? 0 : owner[j];
+        p = KO::load(src, eb + roff[lo] + (j - coff[lo]));
+      }
+      pr[u] = p;
+    }
+  }
   if (single) {
     // one row: thread-local sums, one block reduction
     u64 a = 0;
@@ -426,7 +476,9 @@ __global__ void __launch_bounds__(256) k_sig_range(Src src, const Range *__restr
       }
     }
     block_reduce_2(a, c, sh_acc, sh_cnt);
-    if (t == 0 && (c || zfresh)) {
+    bool out = t == 0 && (c || zfresh);
+    if constexpr (SKIP) out = out && !skip[rg.v0];
+    if (out) {
       const int v = rg.v0;
       const u32 own = src.own(v);
       const u64 h = finalize_key(a, c, own) & hmask;
@@ -442,8 +494,8 @@ __global__ void __launch_bounds__(256) k_sig_range(Src src, const Range *__restr
     if (j < E) {
       const int lo = owner[j];
       const K p = pr[u];
-      const int base = 2 * roff[lo];
-      const u32 sz = 2u * (u32)(roff[lo + 1] - roff[lo]);
+      const int base = 2 * off[lo];
+      const u32 sz = 2u * (u32)(off[lo + 1] - off[lo]);
       u32 sl = (u32)scale_to(KO::hash(p), sz);
       while (true) {
         const K old = atomicCAS(&set[base + sl], KO::EMPTY, p);
@@ -494,7 +546,7 @@ __global__ void __launch_bounds__(256) k_sig_range(Src src, const Range *__restr
   bool zero = false;
   u32 own = 0;
   const int v = rg.v0 + t;
-  if (t < V) {
+  if (t < V && !skipped) {
     const u32 c = cnt[t];
     if (c) {
       own = src.own(v);
@@ -517,7 +569,8 @@ __global__ void __launch_bounds__(256) k_sig_range(Src src, const Range *__restr
 template <class Src, int EMAX, int NT, class K = u64>
 __global__ void __launch_bounds__(NT) k_sig_row(Src src, const Range *__restrict__ rows, u64 *__restrict__ H,
                                                 u32 *__restrict__ DC, u64 *table, u64 tmask,
-                                                const u32 *__restrict__ dep, u64 hmask, u64 *zrep) {
+                                                const u32 *__restrict__ dep, u64 hmask, u64 *zrep,
+                                                const unsigned char *__restrict__ skip) {
   typedef Keys<K> KO;
   constexpr int U = EMAX / NT;
   __shared__ K set[2 * EMAX];
@@ -525,6 +578,7 @@ __global__ void __launch_bounds__(NT) k_sig_row(Src src, const Range *__restrict
   __shared__ u32 sh_cnt[NT / WAVE];
   const int t = threadIdx.x;
   const int v = rows[blockIdx.x].v0;
+  if (skip && skip[v]) return;  // singleton block (work-efficient mode)
   const int64_t eb = src.begin(v);
   const int E = (int)(src.end(v) - eb);
   for (int i = t; i < 2 * E; i += NT) set[i] = KO::EMPTY;
@@ -587,13 +641,15 @@ struct HubPart {
 template <class Src, int CHUNK, class K = u64>
 __global__ void __launch_bounds__(256) k_hub_stage(Src src, const HubChunk *__restrict__ chunks,
                                                    const int *__restrict__ hubs, K *__restrict__ stage,
-                                                   int *__restrict__ poff, u32 *err) {
+                                                   int *__restrict__ poff, u32 *err,
+                                                   const unsigned char *__restrict__ skip) {
   typedef Keys<K> KO;
   constexpr int HUB_U = CHUNK / 256;
   __shared__ K set[2 * CHUNK];
   __shared__ int hist[HUB_PMAX + 1];
   __shared__ int wtot[4];
   const HubChunk c = chunks[blockIdx.x];
+  if (skip && skip[hubs[c.hub]]) return;  // singleton block (work-efficient mode)
   const int P = c.parts;
   const int64_t row = src.begin(hubs[c.hub]);
   const int E = (int)(c.e - c.b);
@@ -670,7 +726,8 @@ template <class Src, class K = u64>
 __global__ void __launch_bounds__(256) k_hub_reduce(Src src, const HubPart *__restrict__ parts,
                                                     const HubChunk *__restrict__ chunks,
                                                     const K *__restrict__ stage, const int *__restrict__ poff,
-                                                    u64 *hub_acc, u32 *hub_cnt, u32 *err) {
+                                                    u64 *hub_acc, u32 *hub_cnt, u32 *err, const int *__restrict__ hubs,
+                                                    const unsigned char *__restrict__ skip) {
   typedef Keys<K> KO;
   __shared__ K set[HUB_PSLOTS];
   __shared__ int64_t sbase[HUB_PMAX]; // per chunk: staging position of this partition's segment
@@ -679,6 +736,7 @@ __global__ void __launch_bounds__(256) k_hub_reduce(Src src, const HubPart *__re
   __shared__ u64 sh_acc[4];
   __shared__ u32 sh_cnt[4];
   const HubPart hp = parts[blockIdx.x];
+  if (skip && skip[hubs[hp.hub]]) return;  // singleton block (work-efficient mode)
   const int C = hp.nchunks;
   for (int i = threadIdx.x; i < HUB_PSLOTS; i += 256) set[i] = KO::EMPTY;
   // segment lengths, then an exclusive scan over the (at most 1024) chunks
@@ -770,11 +828,13 @@ struct HubGChunk {
 template <class Src>
 __global__ void __launch_bounds__(256) k_sig_hub_global(Src src, const HubGChunk *__restrict__ chunks,
                                                         const int *__restrict__ hubs, u64 *sets, u64 *hub_acc,
-                                                        u32 *hub_cnt, const u32 *__restrict__ dep) {
+                                                        u32 *hub_cnt, const u32 *__restrict__ dep,
+                                                        const unsigned char *__restrict__ skip) {
   const u32 hepoch = dep[EP_HUB];
   __shared__ u64 sh_acc[4];
   __shared__ u32 sh_cnt[4];
   const HubGChunk c = chunks[blockIdx.x];
+  if (skip && skip[hubs[c.hub]]) return;  // singleton block (work-efficient mode)
   u64 *set = sets + c.set_off;
   const u64 size = (u64)c.set_size;
   const int64_t row = src.begin(hubs[c.hub]);
@@ -806,7 +866,8 @@ __global__ void __launch_bounds__(256) k_sig_hub_global(Src src, const HubGChunk
 template <class Src>
 __global__ void k_hub_final(Src src, const int *__restrict__ hubs, int nhub, u64 *hub_acc, u32 *hub_cnt,
                             u64 *__restrict__ H, u32 *__restrict__ DC, u64 *table, u64 tmask,
-                            const u32 *__restrict__ dep, u64 hmask, u64 *zrep) {
+                            const u32 *__restrict__ dep, u64 hmask, u64 *zrep,
+                            const unsigned char *__restrict__ skip) {
   const u32 epoch = dep[EP_TABLE], zep = dep[EP_ZERO];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nhub) return;
@@ -815,6 +876,7 @@ __global__ void k_hub_final(Src src, const int *__restrict__ hubs, int nhub, u64
   const u32 cnt = hub_cnt[i];
   hub_acc[i] = 0;
   hub_cnt[i] = 0;
+  if (skip && skip[v]) return;  // singleton block (work-efficient mode)
   const u32 own = src.own(v);
   const u64 h = finalize_key(acc, cnt, own) & hmask;
   H[v] = h;
@@ -835,11 +897,13 @@ __global__ void __launch_bounds__(256) k_lookup(Src src, int n, const u64 *__res
                                                 const u32 *__restrict__ DC, const u64 *table, u64 tmask,
                                                 const u32 *__restrict__ dep, int *__restrict__ rep, int *vcount,
                                                 int *vlist, int *ccount, int *clist, u32 *err, const u64 *zrep,
-                                                int zfresh) {
+                                                int zfresh, const unsigned char *__restrict__ skip) {
   const u32 epoch = dep[EP_TABLE], zep = dep[EP_ZERO];
   const int v = blockIdx.x * 256 + threadIdx.x;
   bool to_verify = false, collided = false;
-  if (v < n) {
+  if (v < n && skip && skip[v]) {
+    rep[v] = v;  // a singleton block stays a singleton
+  } else if (v < n) {
     const u32 dcv = DC[v];
     if (dcv == 0) {
       // empty signature: exact grouping by previous block (without zfresh the
@@ -1065,24 +1129,6 @@ __device__ inline u32 tile_flags(int n, const int *__restrict__ rep, int64_t bas
   return bits;
 }
 
-// Exclusive block scan (256 threads) of one u32 per thread; returns the
-// thread's prefix and writes the block total to *total.
-__device__ inline u32 block_exclusive_scan(u32 mine, u32 *sh_w, u32 *total) {
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  u32 x = mine;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const u32 y = __shfl_up(x, o, WAVE);
-    if (lane >= o) x += y;
-  }
-  if (lane == 63) sh_w[w] = x;
-  __syncthreads();
-  u32 base = 0;
-  for (int i = 0; i < w; ++i) base += sh_w[i];
-  *total = sh_w[0] + sh_w[1] + sh_w[2] + sh_w[3];
-  __syncthreads();
-  return base + x - mine;
-}
 
 __global__ void __launch_bounds__(256) k_tile_count(int n, const int *__restrict__ rep, u32 *__restrict__ tile_sum) {
   __shared__ u32 sh_w[4];
@@ -1160,8 +1206,10 @@ __global__ void __launch_bounds__(256) k_scan_write(int n, const int *__restrict
 
 // Every non-head copies its representative's id (written by k_scan_write),
 // and the new partition is also written in rank order for the next gather.
+// Work-efficient mode (multi != NULL): every non-head marks its head with the
+// step's stamp, so a head left unmarked is a singleton block (k_singletons).
 __global__ void k_assign(int n, const int *__restrict__ rep, int *out, const int *__restrict__ rank,
-                         int *__restrict__ gpid_next) {
+                         int *__restrict__ gpid_next, u32 *multi, const u32 *__restrict__ dep) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
   const int r = rep[v];
@@ -1169,8 +1217,18 @@ __global__ void k_assign(int n, const int *__restrict__ rep, int *out, const int
   if (r != v) {
     val = r >= 0 ? out[r] : -1;
     out[v] = val;
+    if (multi && r >= 0) multi[r] = dep[EP_ZERO];
   }
   if (rank) gpid_next[rank[v]] = val;
+}
+
+// single[v] = 1 iff v is alone in its block of the partition just computed.
+// A singleton block never splits, so the next step can skip its vertex.
+__global__ void k_singletons(int n, const int *__restrict__ rep, const u32 *__restrict__ multi,
+                             const u32 *__restrict__ dep, unsigned char *single) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  single[v] = (rep[v] == v && multi[v] != dep[EP_ZERO]) ? 1 : 0;
 }
 
 // In-degree histogram, target renumbering and rank-order scatter (create time
