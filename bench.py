@@ -246,7 +246,16 @@ def run_plain(args, kb, torch):
     we_steps = r.work_efficient(None)
     we_same = we_counts == counts and all(torch.equal(a, b) for a, b in zip(outs, full))
     r.work_efficient(False)
-    del full
+    # Summary graph of the chain's last step: source blocks P_k, target blocks P_{k-1}.
+    r.quotient(full[k - 1], full[k - 2])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    qs, ql, qd = r.quotient(full[k - 1], full[k - 2])
+    torch.cuda.synchronize()
+    summary = {"ms": (time.perf_counter() - t0) * 1e3, "edges": int(qs.numel()), "blocks": counts[k - 1],
+               "note": "distinct (P_k block, label, P_(k-1) block) triples, sorted; device radix sort"}
+    log(f"[bench] summary graph: {summary['edges']} edges over {summary['blocks']} blocks in {summary['ms']:.2f} ms")
+    del full, qs, ql, qd
     log(f"[bench] work-efficient: {we_ms:.3f} ms per call, {we_steps} steps computed, identical {we_same}")
     work_efficient = {"ms_per_call": we_ms, "steps_computed": we_steps,
                       "equivalent_edge_iterations_per_s": g.m * k / (we_ms / 1e3),
@@ -284,6 +293,7 @@ def run_plain(args, kb, torch):
                      "frac_of_peak": round(step_gbs / HBM_PEAK_GBS, 4)},
         "counts": counts,
         "work_efficient": work_efficient,
+        "summary_graph": summary,
         "create_ms": round(create_ms, 1),
         "tuning": best,
         "autotune_ms": tune_report["ms"] if tune_report else None,

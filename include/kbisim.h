@@ -217,6 +217,26 @@ int kbisim_transpose(int64_t n, int64_t m, const int64_t *row_ptr, const int32_t
                      int64_t *out_row_ptr, int32_t *out_col, int32_t *out_elabel, void *workspace, size_t ws_bytes,
                      void *stream);
 
+/* ---- summary graph -------------------------------------------------------- */
+
+/* The summary (quotient) graph of a refinement chain (Sec. "Graph Summaries
+ * for Bisimulation"): one vertex per block of src_pid, and an edge (B, l, C)
+ * for every distinct (src_pid[v], elabel[e], dst_pid[w]) over the entries
+ * e = (v, w) of the context's graph (label 0 without edge labels).  The
+ * paper connects B to C by label l when all vertices of B have an l-edge
+ * into C; with src_pid = P_k and dst_pid = P_{k-1} of one chain the members
+ * of a block share their (label, target block) sets, so this union is that
+ * graph.  The distinct triples are written sorted by (source block, label,
+ * target block) to out_src, out_label, out_dst (device int32 [m] each) and
+ * their number to *out_count (host).  src_pid, dst_pid: device int32 [n] with
+ * values in [0, n).  workspace: kbisim_quotient_workspace_bytes bytes.
+ * Synchronises the context's stream.  Errors: EINVAL (null, batch context,
+ * ids out of range), ENOSPACE, ERANGE (the source-block, label and
+ * target-block fields need more than 64 bits), EHIP.                       */
+int kbisim_quotient_workspace_bytes(kbisim_ctx *c, size_t *bytes);
+int kbisim_quotient(kbisim_ctx *c, const int32_t *src_pid, const int32_t *dst_pid, int32_t *out_src,
+                    int32_t *out_label, int32_t *out_dst, int64_t *out_count, void *workspace, size_t ws_bytes);
+
 /* ---- tracing and measurement -------------------------------------------- */
 
 /* Kernel kinds reported by the per-kernel profiler. */

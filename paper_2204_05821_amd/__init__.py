@@ -81,6 +81,10 @@ def _lib():
     lib.kbisim_transpose_workspace_bytes.restype = i32
     lib.kbisim_transpose.argtypes = [i64, i64, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     lib.kbisim_transpose.restype = i32
+    lib.kbisim_quotient_workspace_bytes.argtypes = [vp, ctypes.POINTER(sz)]
+    lib.kbisim_quotient_workspace_bytes.restype = i32
+    lib.kbisim_quotient.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.POINTER(i64), vp, sz]
+    lib.kbisim_quotient.restype = i32
     lib.kbisim_work_efficient.argtypes = [vp, i32, ctypes.POINTER(i32)]
     lib.kbisim_work_efficient.restype = i32
     lib.kbisim_profile_select.argtypes = [vp, ctypes.c_uint32]
@@ -226,6 +230,32 @@ class Refiner:
         if rc:
             raise KbisimError(rc, "kbisim_work_efficient")
         return int(steps.value)
+
+    def quotient(self, src_pid: torch.Tensor, dst_pid: torch.Tensor):
+        """Summary graph: distinct (source block, label, target block) triples, sorted.
+
+        With src_pid = P_k and dst_pid = P_{k-1} this is the summary graph of the
+        k-bisimulation.  Returns three device int32 tensors of equal length.
+        """
+        _check(src_pid, torch.int32, "src_pid", self.device)
+        _check(dst_pid, torch.int32, "dst_pid", self.device)
+        lib = _lib()
+        nbytes = ctypes.c_size_t(0)
+        rc = lib.kbisim_quotient_workspace_bytes(self._ctx, ctypes.byref(nbytes))
+        if rc:
+            raise KbisimError(rc, "kbisim_quotient_workspace_bytes")
+        with torch.cuda.device(self.device):
+            ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+            cap = max(self.m, 1)
+            out = [torch.empty(cap, dtype=torch.int32, device=self.device) for _ in range(3)]
+            cnt = ctypes.c_int64(0)
+            torch.cuda.current_stream().synchronize()
+            rc = lib.kbisim_quotient(self._ctx, _ptr(src_pid), _ptr(dst_pid), _ptr(out[0]), _ptr(out[1]),
+                                     _ptr(out[2]), ctypes.byref(cnt), _ptr(ws), int(nbytes.value))
+        if rc:
+            raise KbisimError(rc, "kbisim_quotient")
+        c = int(cnt.value)
+        return out[0][:c], out[1][:c], out[2][:c]
 
     def profile(self, enable: bool = True, kinds: Optional[Sequence[str]] = None) -> None:
         """Start (and reset) or stop per-kernel event timing of later refine calls;

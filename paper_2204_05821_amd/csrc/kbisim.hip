@@ -184,6 +184,7 @@ struct kbisim_ctx {
   u32 prof_mask = ~0u;   // kernel kinds timed by the profiler
   bool narrow = false;  // 32-bit LDS keys: (edge label << pb) | block fits in 31 bits
   u32 pb = 31;
+  u32 max_label = 0;    // largest edge label (0 without labels)
   int64_t p0_count = 0;
   // batches
   int64_t num_graphs = 0;
@@ -1013,6 +1014,7 @@ int create_impl(const kbisim_graph *g, int kmax, const kbisim_tuning *tuning, vo
     while (pb < 31 && (int64_t(1) << pb) < gmax) ++pb;
     while (lb < 32 && (max_label >> lb) != 0) ++lb;
     c->pb = pb;
+    c->max_label = max_label;
     c->narrow = c->tune.key_bits != 64 && pb + lb <= 31;
   }
 
@@ -1395,6 +1397,116 @@ int kbisim_transpose(int64_t n, int64_t m, const int64_t *row_ptr, const int32_t
     k_transpose_scatter<<<(unsigned)std::min<int64_t>(blocks_for(n * WAVE, 256), 65536), 256, 0, s>>>(
         n, row_ptr, col, elabel, cursor, out_col, out_elabel);
   HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(s));
+  return KBISIM_OK;
+}
+
+namespace {
+struct QuotientPlan {
+  size_t off_a, off_b, off_hist, off_offs, off_tiles, off_flag, off_pos, off_word, total;
+  int64_t rtiles, hist_n, htiles, mtiles;
+};
+QuotientPlan quotient_plan(int64_t m) {
+  QuotientPlan p{};
+  size_t at = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = at;
+    at = align_up(at + std::max<size_t>(bytes, 1));
+    return o;
+  };
+  const int64_t M = std::max<int64_t>(m, 1);
+  p.rtiles = (M + RADIX_TILE - 1) / RADIX_TILE;
+  p.hist_n = 256 * p.rtiles;
+  p.htiles = (p.hist_n + SCAN_TILE - 1) / SCAN_TILE;
+  p.mtiles = (M + SCAN_TILE - 1) / SCAN_TILE;
+  p.off_a = take(8 * (size_t)M);
+  p.off_b = take(8 * (size_t)M);
+  p.off_hist = take(4 * (size_t)p.hist_n);
+  p.off_offs = take(8 * (size_t)(p.hist_n + 1));
+  p.off_tiles = take(8 * (size_t)std::max(p.htiles, p.mtiles));
+  p.off_flag = take(4 * (size_t)M);
+  p.off_pos = take(8 * (size_t)(M + 1));
+  p.off_word = take(16);
+  p.total = at;
+  return p;
+}
+
+int bit_width(uint64_t x) {
+  int b = 0;
+  while (b < 64 && (x >> b) != 0) ++b;
+  return b;
+}
+
+// Exclusive scan of cnt[0..len) into out[0..len] (64-bit), on `s`.
+int scan64(hipStream_t s, int64_t len, const int *cnt, int64_t *tiles, int64_t *out) {
+  const int64_t nt = (len + SCAN_TILE - 1) / SCAN_TILE;
+  k_sum_tiles64<<<(unsigned)nt, 256, 0, s>>>(len, cnt, tiles);
+  k_scan_tiles64<<<1, 256, 0, s>>>(nt, tiles);
+  k_write_ptr64<<<(unsigned)nt, 256, 0, s>>>(len, cnt, tiles, out, nullptr);
+  HIP_TRY(hipGetLastError());
+  return 0;
+}
+}  // namespace
+
+int kbisim_quotient_workspace_bytes(kbisim_ctx *c, size_t *bytes) {
+  if (!c || !bytes || c->num_graphs > 0) return KBISIM_EINVAL;
+  *bytes = quotient_plan(c->g.m).total;
+  return KBISIM_OK;
+}
+
+int kbisim_quotient(kbisim_ctx *c, const int32_t *src_pid, const int32_t *dst_pid, int32_t *out_src,
+                    int32_t *out_label, int32_t *out_dst, int64_t *out_count, void *workspace, size_t ws_bytes) {
+  if (!c || c->num_graphs > 0 || !src_pid || !dst_pid || !out_count) return KBISIM_EINVAL;
+  const int64_t n = c->g.n, m = c->g.m;
+  *out_count = 0;
+  if (m == 0) return KBISIM_OK;
+  if (!out_src || !out_label || !out_dst) return KBISIM_EINVAL;
+  const QuotientPlan p = quotient_plan(m);
+  if (!workspace || ws_bytes < p.total) return KBISIM_ENOSPACE;
+  hipStream_t s = c->stream;
+  char *w = (char *)workspace;
+  u64 *ka = (u64 *)(w + p.off_a), *kb = (u64 *)(w + p.off_b);
+  int *hist = (int *)(w + p.off_hist);
+  int64_t *offs = (int64_t *)(w + p.off_offs), *tiles = (int64_t *)(w + p.off_tiles);
+  int *flag = (int *)(w + p.off_flag);
+  int64_t *pos = (int64_t *)(w + p.off_pos);
+  u32 *word = (u32 *)(w + p.off_word);  // [0] error bits, [1] max source id, [2] max target id
+  int rc = 0;
+  // both partitions must hold ids in [0, n)
+  k_fill_i32<<<1, 64, 0, s>>>((int *)word, 4, 0);
+  k_validate_vals<<<blocks_for(n, 256), 256, 0, s>>>(n, src_pid, n, word, ERR_BAD_PID);
+  k_validate_vals<<<blocks_for(n, 256), 256, 0, s>>>(n, dst_pid, n, word, ERR_BAD_PID);
+  k_max_i32<<<(unsigned)std::min<int64_t>(blocks_for(n, 256), 4096), 256, 0, s>>>(n, src_pid, word + 1);
+  k_max_i32<<<(unsigned)std::min<int64_t>(blocks_for(n, 256), 4096), 256, 0, s>>>(n, dst_pid, word + 2);
+  HIP_TRY(hipGetLastError());
+  u32 hw[3] = {0, 0, 0};
+  HIP_TRY(hipMemcpyAsync(hw, word, sizeof hw, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (hw[0]) return KBISIM_EINVAL;
+  QKey q;
+  q.db = (u32)std::max(1, bit_width(hw[2]));
+  q.lb = c->g.elabel ? (u32)bit_width(c->max_label) : 0u;
+  const int sbits = std::max(1, bit_width(hw[1]));
+  const int total_bits = sbits + (int)q.lb + (int)q.db;
+  if (total_bits > 64) return KBISIM_ERANGE;
+  k_quotient_keys<<<(unsigned)std::min<int64_t>(blocks_for(n * WAVE, 256), 65536), 256, 0, s>>>(
+      n, c->g.row_ptr, c->g.col, c->g.elabel, src_pid, dst_pid, q, ka);
+  HIP_TRY(hipGetLastError());
+  for (int shift = 0; shift < total_bits; shift += 8) {
+    k_radix_hist<<<(unsigned)p.rtiles, 256, 0, s>>>(m, ka, shift, p.rtiles, hist);
+    HIP_TRY(hipGetLastError());
+    if ((rc = scan64(s, p.hist_n, hist, tiles, offs))) return rc;
+    k_radix_scatter<<<(unsigned)p.rtiles, 256, 0, s>>>(m, ka, shift, p.rtiles, offs, kb);
+    HIP_TRY(hipGetLastError());
+    std::swap(ka, kb);
+  }
+  k_run_starts<<<(unsigned)std::min<int64_t>(blocks_for(m, 256), 65536), 256, 0, s>>>(m, ka, flag);
+  HIP_TRY(hipGetLastError());
+  if ((rc = scan64(s, m, flag, tiles, pos))) return rc;
+  k_quotient_write<<<(unsigned)std::min<int64_t>(blocks_for(m, 256), 65536), 256, 0, s>>>(m, ka, flag, pos, q, out_src,
+                                                                                          out_label, out_dst);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(out_count, pos + m, 8, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   return KBISIM_OK;
 }

@@ -1286,7 +1286,7 @@ __global__ void __launch_bounds__(256) k_scan_tiles64(int64_t ntiles, int64_t *t
   }
 }
 
-// out_ptr[i] = sum of cnt[0..i), out_ptr[n] = total; cursor[i] = out_ptr[i].
+// out_ptr[i] = sum of cnt[0..i), out_ptr[n] = total; cursor[i] = out_ptr[i] (cursor may be NULL).
 __global__ void __launch_bounds__(256) k_write_ptr64(int64_t n, const int *__restrict__ cnt,
                                                      const int64_t *__restrict__ tile_pre, int64_t *out_ptr,
                                                      unsigned long long *cursor) {
@@ -1305,7 +1305,7 @@ __global__ void __launch_bounds__(256) k_write_ptr64(int64_t n, const int *__res
   for (int j = 0; j < SCAN_ITEMS; ++j) {
     if (base + j < n) {
       out_ptr[base + j] = off;
-      cursor[base + j] = (unsigned long long)off;
+      if (cursor) cursor[base + j] = (unsigned long long)off;
     }
     off += c[j];
     if (base + j + 1 == n) out_ptr[n] = off;
@@ -1387,6 +1387,114 @@ __global__ void k_batch_counts(int G, const int64_t *__restrict__ first, const i
     c = end - base;
   }
   counts[(int64_t)g * k + i] = c;
+}
+
+// ---------------------------------------------------------------- summary graph
+// The summary (quotient) graph of a refinement chain has one vertex per block
+// of P_k and an edge (B, l, C) when the members of B have an l-edge into block
+// C of P_{k-1} (Sec. "Graph Summaries for Bisimulation": connected when all
+// represented vertices have such an edge; members of one P_k block share
+// their (label, P_{k-1} block) sets, so "all" and "some" coincide).  Built by
+// packing each CSR entry into one 64-bit key (source block, label, target
+// block), sorting the keys (LSD radix, 8-bit digits) and keeping the first of
+// every run of equal keys.
+
+struct QKey {
+  u32 lb, db;  // bits of the label and target-block fields
+};
+
+__global__ void k_quotient_keys(int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+                                const int32_t *__restrict__ elabel, const int32_t *__restrict__ src_pid,
+                                const int32_t *__restrict__ dst_pid, QKey q, u64 *keys) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t v = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; v < n; v += waves) {
+    const u64 sb = (u64)(u32)src_pid[v] << (q.lb + q.db);
+    const int64_t b = row_ptr[v], e = row_ptr[v + 1];
+    for (int64_t i = b + lane; i < e; i += WAVE) {
+      const u64 l = elabel ? (u64)(u32)elabel[i] : 0ULL;
+      keys[i] = sb | (l << q.db) | (u64)(u32)dst_pid[col[i]];
+    }
+  }
+}
+
+constexpr int RADIX_ITEMS = 16;                  // keys per thread per tile
+constexpr int RADIX_TILE = 256 * RADIX_ITEMS;    // keys per tile
+
+// Digit histogram of each tile: hist[digit * ntiles + tile].
+__global__ void __launch_bounds__(256) k_radix_hist(int64_t m, const u64 *__restrict__ keys, int shift, int64_t ntiles,
+                                                    int *__restrict__ hist) {
+  __shared__ int h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * RADIX_TILE;
+#pragma unroll
+  for (int j = 0; j < RADIX_ITEMS; ++j) {
+    const int64_t i = base + j * 256 + threadIdx.x;
+    if (i < m) atomicAdd(&h[(keys[i] >> shift) & 255], 1);
+  }
+  __syncthreads();
+  hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
+}
+
+// Stable scatter of a tile: keys are ranked chunk by chunk (256 keys, in
+// index order); inside a chunk, lanes with equal digits are found with one
+// ballot per digit bit, and waves are ordered through per-digit counts.
+__global__ void __launch_bounds__(256) k_radix_scatter(int64_t m, const u64 *__restrict__ keys, int shift,
+                                                       int64_t ntiles, const int64_t *__restrict__ offs,
+                                                       u64 *__restrict__ out) {
+  __shared__ int64_t base[256];     // next output position per digit
+  __shared__ int wcnt[4][256];      // per-wave digit counts of the current chunk
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  base[t] = offs[(int64_t)t * ntiles + blockIdx.x];
+  const int64_t tile0 = (int64_t)blockIdx.x * RADIX_TILE;
+  const u64 lt = (1ULL << lane) - 1ULL;
+  for (int j = 0; j < RADIX_ITEMS; ++j) {
+    for (int q = 0; q < 4; ++q) wcnt[q][t] = 0;
+    __syncthreads();
+    const int64_t i = tile0 + j * 256 + t;
+    const bool valid = i < m;
+    const u64 key = valid ? keys[i] : 0ULL;
+    const u32 d = (u32)(key >> shift) & 255u;
+    u64 peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const u64 ones = __ballot(valid && ((d >> b) & 1u));
+      peers &= ((d >> b) & 1u) ? ones : ~ones;
+    }
+    const int rank = __popcll(peers & lt);
+    if (valid && rank == 0) wcnt[w][d] = __popcll(peers);
+    __syncthreads();
+    if (valid) {
+      int before = 0;
+      for (int q = 0; q < w; ++q) before += wcnt[q][d];
+      out[base[d] + before + rank] = key;
+    }
+    __syncthreads();
+    // advance the per-digit bases by this chunk's counts
+    base[t] += wcnt[0][t] + wcnt[1][t] + wcnt[2][t] + wcnt[3][t];
+    __syncthreads();
+  }
+}
+
+// flag[i] = 1 where a run of equal keys starts.
+__global__ void k_run_starts(int64_t m, const u64 *__restrict__ keys, int *__restrict__ flag) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
+    flag[i] = (i == 0 || keys[i] != keys[i - 1]) ? 1 : 0;
+}
+
+// Unpack the run starts into (source block, label, target block) at their rank.
+__global__ void k_quotient_write(int64_t m, const u64 *__restrict__ keys, const int *__restrict__ flag,
+                                 const int64_t *__restrict__ pos, QKey q, int32_t *out_src, int32_t *out_lab,
+                                 int32_t *out_dst) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+    if (!flag[i]) continue;
+    const u64 k = keys[i];
+    const int64_t o = pos[i];
+    out_dst[o] = (int32_t)(k & ((1ULL << q.db) - 1ULL));
+    out_lab[o] = q.lb ? (int32_t)((k >> q.db) & ((1ULL << q.lb) - 1ULL)) : 0;
+    out_src[o] = (int32_t)(k >> (q.db + q.lb));
+  }
 }
 
 // ---------------------------------------------------------------- epochs
