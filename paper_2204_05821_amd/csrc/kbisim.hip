@@ -18,6 +18,7 @@
 #include <cstring>
 #include <map>
 #include <new>
+#include <thread>
 #include <type_traits>
 #include <utility>
 #include <vector>
@@ -39,11 +40,12 @@ constexpr int CLEAR_GRID = 2048;
 constexpr int MIN_RANGE_EDGES = 1024;  // smallest tunable range capacity
 constexpr int MIN_HUB_CHUNK = 2048;    // smallest tunable hub chunk
 constexpr int MAX_GRAPH_CACHE = 8;
+constexpr int SCHED_CHUNKS = 16;  // the schedule is built over this many vertex chunks in parallel
 
 inline size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
 uint64_t pow2_at_least(uint64_t x) {
-  uint64_t p = 64;
+  uint64_t p = 512;
   while (p < x) p <<= 1;
   return p;
 }
@@ -76,7 +78,7 @@ Plan make_plan(int64_t n, int64_t m, int64_t nl, int kmax, int64_t num_graphs) {
   // "next" once), when full of vertices, or at the end; rows above the
   // capacity form ranges of their own.  Bounds use the smallest capacity.
   p.max_ranges = big / (RANGE_DMAX + 1) + 2 * big / (MIN_RANGE_EDGES + 1) + 2 * big / MIN_RANGE_EDGES +
-                 (int64_t)N / RANGE_VERTS + 8;
+                 (int64_t)N / RANGE_VERTS + 8 + SCHED_CHUNKS;
   p.max_lists = big / (RANGE_DMAX + 1) + 8;
   p.nhub_max = big / (BLOCK_MAX + 1) + 1;
   p.nchunk_max = big / MIN_HUB_CHUNK + p.nhub_max + 1;
@@ -325,44 +327,81 @@ int build_schedule(kbisim_ctx *c, const int64_t *ptr, Schedule &s) {
     HIP_TRY(hipMemcpyAsync(rp.data(), ptr, 8 * (size_t)(n + 1), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
   }
-  auto deg = [&](int64_t v) -> int64_t { return ptr ? rp[(size_t)v + 1] - rp[(size_t)v] : 1; };
+  // Degree tiers.  Rows are packed greedily into ranges of consecutive
+  // vertices; the vertex sequence is cut into SCHED_CHUNKS fixed chunks that
+  // are packed in parallel (a range never crosses a chunk boundary), so the
+  // schedule is the same on every machine.
+  struct Part {
+    std::vector<Range> ranges, big, row8;
+    std::vector<int> hubs;
+    int64_t info[4] = {0, 0, 0, 0};
+    int64_t nonempty = 0;
+  };
+  std::vector<Part> parts_((size_t)SCHED_CHUNKS);
+  auto pack = [&](int ci) {
+    Part &P = parts_[(size_t)ci];
+    const int64_t v_begin = n * ci / SCHED_CHUNKS, v_end = n * (ci + 1) / SCHED_CHUNKS;
+    if (!ptr) {
+      // one label per vertex: every row has one item, ranges of RANGE_VERTS vertices
+      for (int64_t v0 = v_begin; v0 < v_end; v0 += RANGE_VERTS)
+        P.ranges.push_back(Range{(int)v0, (int)std::min<int64_t>(v_end, v0 + RANGE_VERTS)});
+      P.info[0] = P.info[1] = P.nonempty = v_end - v_begin;
+      return;
+    }
+    int64_t cur0 = -1, cur_e = 0;
+    auto close = [&](int64_t vend) {
+      if (cur0 >= 0) P.ranges.push_back(Range{(int)cur0, (int)vend});
+      cur0 = -1;
+      cur_e = 0;
+    };
+    for (int64_t v = v_begin; v < v_end; ++v) {
+      const int64_t d = rp[(size_t)v + 1] - rp[(size_t)v];
+      P.nonempty += d > 0;
+      if (d > ROW_MAX) {
+        close(v);
+        P.hubs.push_back((int)v);
+        continue;
+      }
+      if (d > RANGE_DMAX) {
+        close(v);
+        P.row8.push_back(Range{(int)v, (int)v + 1});
+        P.info[2] += 1;
+        P.info[3] += d;
+        continue;
+      }
+      if (d > t.range_edges) {
+        close(v);
+        P.big.push_back(Range{(int)v, (int)v + 1});
+        P.info[2] += 1;
+        P.info[3] += d;
+        continue;
+      }
+      if (cur0 >= 0 && (cur_e + d > t.range_edges || v - cur0 == RANGE_VERTS)) close(v);
+      if (cur0 < 0) cur0 = v;
+      cur_e += d;
+      P.info[0] += 1;
+      P.info[1] += d;
+    }
+    close(v_end);
+  };
+  if (n >= (int64_t)1 << 16) {
+    std::vector<std::thread> th;
+    for (int ci = 0; ci < SCHED_CHUNKS; ++ci) th.emplace_back(pack, ci);
+    for (auto &x : th) x.join();
+  } else {
+    for (int ci = 0; ci < SCHED_CHUNKS; ++ci) pack(ci);
+  }
   std::vector<Range> ranges, big_ranges, row8_ranges;
   std::vector<int> hubs;
-  int64_t cur0 = -1, cur_e = 0;
-  auto close = [&](int64_t v_end) {
-    if (cur0 >= 0) ranges.push_back(Range{(int)cur0, (int)v_end});
-    cur0 = -1;
-    cur_e = 0;
-  };
-  for (int64_t v = 0; v < n; ++v) {
-    const int64_t d = deg(v);
-    s.nonempty += d > 0;
-    if (d > ROW_MAX) {
-      close(v);
-      hubs.push_back((int)v);
-      continue;
-    }
-    if (d > RANGE_DMAX) {
-      close(v);
-      row8_ranges.push_back(Range{(int)v, (int)v + 1});
-      s.info[2] += 1;
-      s.info[3] += d;
-      continue;
-    }
-    if (d > t.range_edges) {
-      close(v);
-      big_ranges.push_back(Range{(int)v, (int)v + 1});
-      s.info[2] += 1;
-      s.info[3] += d;
-      continue;
-    }
-    if (cur0 >= 0 && (cur_e + d > t.range_edges || v - cur0 == RANGE_VERTS)) close(v);
-    if (cur0 < 0) cur0 = v;
-    cur_e += d;
-    s.info[0] += 1;
-    s.info[1] += d;
+  for (const Part &P : parts_) {
+    ranges.insert(ranges.end(), P.ranges.begin(), P.ranges.end());
+    big_ranges.insert(big_ranges.end(), P.big.begin(), P.big.end());
+    row8_ranges.insert(row8_ranges.end(), P.row8.begin(), P.row8.end());
+    hubs.insert(hubs.end(), P.hubs.begin(), P.hubs.end());
+    for (int i = 0; i < 4; ++i) s.info[i] += P.info[i];
+    s.nonempty += P.nonempty;
   }
-  close(n);
+  auto deg = [&](int64_t v) -> int64_t { return ptr ? rp[(size_t)v + 1] - rp[(size_t)v] : 1; };
   s.nranges = (int)ranges.size();
   s.nbig = (int)big_ranges.size();
   s.nrow8 = (int)row8_ranges.size();
@@ -459,7 +498,9 @@ int build_schedule(kbisim_ctx *c, const int64_t *ptr, Schedule &s) {
 }
 
 // Rank vertices by decreasing in-degree (ties by vertex id) and renumber the
-// targets of every CSR entry: gcol[e] = rank[col[e]].  Synchronises.
+// targets of every CSR entry: gcol[e] = rank[col[e]].  A stable LSD radix
+// sort of (in-degree key, vertex) on the device; the grouping tables serve as
+// scratch, so this runs before they are cleared.  Synchronises.
 int build_rank(kbisim_ctx *c) {
   const int64_t n = c->g.n, m = c->g.m;
   if (n == 0) return 0;
@@ -470,16 +511,29 @@ int build_rank(kbisim_ctx *c) {
     k_indegree<<<(unsigned)std::min<int64_t>(blocks_for(m, 256), 1 << 16), 256, 0, c->stream>>>(m, c->g.col, indeg);
     LAUNCH_CHECK();
   }
-  std::vector<int> deg((size_t)n), rank((size_t)n);
-  HIP_TRY(hipMemcpyAsync(deg.data(), indeg, 4 * (size_t)n, hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(hipStreamSynchronize(c->stream));
-  const int KEYS = 1 << 20;
-  std::vector<int64_t> start((size_t)KEYS + 1, 0);
-  for (int64_t v = 0; v < n; ++v) start[(size_t)(KEYS - 1 - std::min(deg[(size_t)v], KEYS - 1)) + 1]++;
-  for (int k = 0; k < KEYS; ++k) start[(size_t)k + 1] += start[(size_t)k];
-  for (int64_t v = 0; v < n; ++v)
-    rank[(size_t)v] = (int)start[(size_t)(KEYS - 1 - std::min(deg[(size_t)v], KEYS - 1))]++;
-  HIP_TRY(hipMemcpyAsync(c->rank, rank.data(), 4 * (size_t)n, hipMemcpyHostToDevice, c->stream));
+  u64 *ka = c->table, *kb = c->table + n;  // 8 * tslots >= 16 n bytes
+  const int64_t rtiles = (n + RADIX_TILE - 1) / RADIX_TILE, hist_n = 256 * rtiles;
+  int *hist = (int *)c->ctable;
+  int64_t *offs = (int64_t *)(c->ctable) + (hist_n + 1) / 2 + 1;
+  int64_t *tiles = offs + hist_n + 2;
+  if ((size_t)((char *)(tiles + (hist_n + SCAN_TILE - 1) / SCAN_TILE + 1) - (char *)c->ctable) > 8 * c->plan.tslots)
+    return KBISIM_EINTERNAL;
+  k_rank_keys<<<(unsigned)std::min<int64_t>(blocks_for(n, 256), 1 << 16), 256, 0, c->stream>>>(n, indeg, ka);
+  LAUNCH_CHECK();
+  for (int shift = 32; shift < 32 + RANK_KEYBITS; shift += 8) {
+    k_radix_hist<<<(unsigned)rtiles, 256, 0, c->stream>>>(n, ka, shift, rtiles, hist);
+    LAUNCH_CHECK();
+    const int64_t nt = (hist_n + SCAN_TILE - 1) / SCAN_TILE;
+    k_sum_tiles64<<<(unsigned)nt, 256, 0, c->stream>>>(hist_n, hist, tiles);
+    k_scan_tiles64<<<1, 256, 0, c->stream>>>(nt, tiles);
+    k_write_ptr64<<<(unsigned)nt, 256, 0, c->stream>>>(hist_n, hist, tiles, offs, nullptr);
+    LAUNCH_CHECK();
+    k_radix_scatter<<<(unsigned)rtiles, 256, 0, c->stream>>>(n, ka, shift, rtiles, offs, kb);
+    LAUNCH_CHECK();
+    std::swap(ka, kb);
+  }
+  k_rank_from_sorted<<<(unsigned)std::min<int64_t>(blocks_for(n, 256), 1 << 16), 256, 0, c->stream>>>(n, ka, c->rank);
+  LAUNCH_CHECK();
   if (m > 0) {
     k_remap<<<(unsigned)std::min<int64_t>(blocks_for(m, 256), 1 << 16), 256, 0, c->stream>>>(m, c->g.col, c->rank,
                                                                                           c->gcol);
@@ -1040,6 +1094,9 @@ int create_impl(const kbisim_graph *g, int kmax, const kbisim_tuning *tuning, vo
     if (err) return fail(KBISIM_EGRAPH);
   }
 
+  // Gather renumbering: rank vertices by decreasing in-degree (ties by id).
+  // Uses the grouping tables as scratch, before they are cleared below.
+  if ((rc = build_rank(c))) return fail(rc);
   // Fresh state: tables start empty; empty-signature slots start above any entry.
   if ((rc = fill_u64(c, c->table, (int64_t)plan.tslots, 0))) return fail(rc);
   if ((rc = fill_u64(c, c->ctable, (int64_t)plan.tslots, 0))) return fail(rc);
@@ -1065,8 +1122,6 @@ int create_impl(const kbisim_graph *g, int kmax, const kbisim_tuning *tuning, vo
     if ((rc = read_err(c, &err))) return fail(rc);
     if (err) return fail(KBISIM_EINTERNAL);
   }
-  // Gather renumbering: rank vertices by decreasing in-degree (ties by id).
-  if ((rc = build_rank(c))) return fail(rc);
   // Static schedule of the graph rows.
   if ((rc = build_schedule(c, g->row_ptr, c->sched))) return fail(rc);
   c->tmask_steps = std::min<u64>(pow2_at_least(2 * (uint64_t)std::max<int64_t>(c->sched.nonempty, 1)), plan.tslots) - 1;

@@ -1477,6 +1477,22 @@ __global__ void __launch_bounds__(256) k_radix_scatter(int64_t m, const u64 *__r
   }
 }
 
+// In-degree ranking: key[v] = (RANK_KEYMAX - min(indeg, RANK_KEYMAX)) << 32 | v;
+// a stable sort on the high field orders vertices by decreasing in-degree,
+// ties by vertex id.
+constexpr int RANK_KEYBITS = 20;
+constexpr u32 RANK_KEYMAX = (1u << RANK_KEYBITS) - 1u;
+
+__global__ void k_rank_keys(int64_t n, const int *__restrict__ indeg, u64 *keys) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+    keys[v] = ((u64)(RANK_KEYMAX - min((u32)indeg[v], RANK_KEYMAX)) << 32) | (u64)v;
+}
+
+__global__ void k_rank_from_sorted(int64_t n, const u64 *__restrict__ sorted, int *rank) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    rank[(u32)sorted[i]] = (int)i;
+}
+
 // flag[i] = 1 where a run of equal keys starts.
 __global__ void k_run_starts(int64_t m, const u64 *__restrict__ keys, int *__restrict__ flag) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
