@@ -134,6 +134,7 @@ struct Schedule {
   int nranges = 0;  // multi-vertex ranges (at most range_edges entries)
   int nbig = 0;     // single-row ranges of range_edges < deg <= RANGE_DMAX
   int nrow8 = 0;    // single-row ranges of RANGE_DMAX < deg <= ROW_MAX (after the nbig ones)
+  int nrow20 = 0;   // single-row ranges of ROW_MAX < deg <= ROW_MAX_NARROW, 32-bit keys only (after those)
   int nhub = 0, hub_off = 0;
   int nchunks = 0, nparts = 0, ngchunks = 0;
   int64_t gset_begin = 0, gset_end = 0;  // global hash sets of very large hubs
@@ -317,7 +318,8 @@ int hub_parts_for(const Tuning &t, int64_t d) {
 // Build the static schedule of the rows of `ptr` (NULL: every row has one
 // item) on the host: runs of consecutive low-degree vertices, single-row
 // ranges, and hub chunks, partitions and staging areas.  Synchronises.
-int build_schedule(kbisim_ctx *c, const int64_t *ptr, Schedule &s) {
+// row_max: longest row with a workgroup of its own (longer rows are hubs).
+int build_schedule(kbisim_ctx *c, const int64_t *ptr, Schedule &s, int64_t row_max = ROW_MAX) {
   const int64_t n = c->g.n;
   const Tuning &t = c->tune;
   s = Schedule{};
@@ -332,7 +334,7 @@ int build_schedule(kbisim_ctx *c, const int64_t *ptr, Schedule &s) {
   // are packed in parallel (a range never crosses a chunk boundary), so the
   // schedule is the same on every machine.
   struct Part {
-    std::vector<Range> ranges, big, row8;
+    std::vector<Range> ranges, big, row8, row20;
     std::vector<int> hubs;
     int64_t info[4] = {0, 0, 0, 0};
     int64_t nonempty = 0;
@@ -357,9 +359,16 @@ int build_schedule(kbisim_ctx *c, const int64_t *ptr, Schedule &s) {
     for (int64_t v = v_begin; v < v_end; ++v) {
       const int64_t d = rp[(size_t)v + 1] - rp[(size_t)v];
       P.nonempty += d > 0;
-      if (d > ROW_MAX) {
+      if (d > row_max) {
         close(v);
         P.hubs.push_back((int)v);
+        continue;
+      }
+      if (d > ROW_MAX) {
+        close(v);
+        P.row20.push_back(Range{(int)v, (int)v + 1});
+        P.info[2] += 1;
+        P.info[3] += d;
         continue;
       }
       if (d > RANGE_DMAX) {
@@ -391,9 +400,10 @@ int build_schedule(kbisim_ctx *c, const int64_t *ptr, Schedule &s) {
   } else {
     for (int ci = 0; ci < SCHED_CHUNKS; ++ci) pack(ci);
   }
-  std::vector<Range> ranges, big_ranges, row8_ranges;
+  std::vector<Range> ranges, big_ranges, row8_ranges, row20_ranges;
   std::vector<int> hubs;
   for (const Part &P : parts_) {
+    row20_ranges.insert(row20_ranges.end(), P.row20.begin(), P.row20.end());
     ranges.insert(ranges.end(), P.ranges.begin(), P.ranges.end());
     big_ranges.insert(big_ranges.end(), P.big.begin(), P.big.end());
     row8_ranges.insert(row8_ranges.end(), P.row8.begin(), P.row8.end());
@@ -405,8 +415,10 @@ int build_schedule(kbisim_ctx *c, const int64_t *ptr, Schedule &s) {
   s.nranges = (int)ranges.size();
   s.nbig = (int)big_ranges.size();
   s.nrow8 = (int)row8_ranges.size();
+  s.nrow20 = (int)row20_ranges.size();
   ranges.insert(ranges.end(), big_ranges.begin(), big_ranges.end());
   ranges.insert(ranges.end(), row8_ranges.begin(), row8_ranges.end());
+  ranges.insert(ranges.end(), row20_ranges.begin(), row20_ranges.end());
   // hubs: staged (partitioned) unless very large or out of offset space
   std::vector<HubChunk> chunks;
   std::vector<HubPart> parts;
@@ -591,7 +603,7 @@ int launch_ranges_k(kbisim_ctx *c, const Src &src, const Schedule &s, int zfresh
     }
     if (rc) return rc;
   }
-  if (s.nbig || s.nrow8) {
+  if (s.nbig || s.nrow8 || s.nrow20) {
     ProfScope ps(c, KBISIM_K_SIG_BLOCK);
     if (s.nbig) {
       k_sig_row<Src, RANGE_DMAX, 512, K><<<(unsigned)s.nbig, 512, 0, c->stream>>>(
@@ -602,6 +614,14 @@ int launch_ranges_k(kbisim_ctx *c, const Src &src, const Schedule &s, int zfresh
       k_sig_row<Src, ROW_MAX, 1024, K><<<(unsigned)s.nrow8, 1024, 0, c->stream>>>(
           src, c->ranges + s.nranges + s.nbig, c->H, c->DC, c->table, tmask, c->dep, c->hmask, c->zrep, skip);
       LAUNCH_CHECK();
+    }
+    if constexpr (std::is_same<K, u32>::value) {
+      if (s.nrow20) {
+        k_sig_row<Src, ROW_MAX_NARROW, 1024, u32><<<(unsigned)s.nrow20, 1024, 0, c->stream>>>(
+            src, c->ranges + s.nranges + s.nbig + s.nrow8, c->H, c->DC, c->table, tmask, c->dep, c->hmask, c->zrep,
+            skip);
+        LAUNCH_CHECK();
+      }
     }
   }
   return 0;
@@ -1123,7 +1143,7 @@ int create_impl(const kbisim_graph *g, int kmax, const kbisim_tuning *tuning, vo
     if (err) return fail(KBISIM_EINTERNAL);
   }
   // Static schedule of the graph rows.
-  if ((rc = build_schedule(c, g->row_ptr, c->sched))) return fail(rc);
+  if ((rc = build_schedule(c, g->row_ptr, c->sched, c->narrow ? ROW_MAX_NARROW : ROW_MAX))) return fail(rc);
   c->tmask_steps = std::min<u64>(pow2_at_least(2 * (uint64_t)std::max<int64_t>(c->sched.nonempty, 1)), plan.tslots) - 1;
   *out = c;
   return KBISIM_OK;

@@ -45,6 +45,7 @@ constexpr int RANGE_EDGES = 1024;    // CSR entries per multi-vertex range workg
 constexpr int RANGE_VERTS = 256;     // vertices per range workgroup
 constexpr int RANGE_DMAX = 4096;     // rows above RANGE_EDGES get a workgroup of 512 threads
 constexpr int ROW_MAX = 8192;        // rows above RANGE_DMAX get one of 1024 threads; above this, hubs
+constexpr int ROW_MAX_NARROW = 19456;  // with 32-bit keys rows up to this fit one workgroup's LDS (152 KB)
 constexpr int BLOCK_MAX = ROW_MAX;
 constexpr int BLOCK_SLOTS = 8192;    // LDS set slots for exact checks (64 KB)
 constexpr int HUB_CHUNK = 4096;      // default entries per hub staging workgroup (16 per thread)
