@@ -451,13 +451,21 @@ def run_serve(args, kb, torch):
     first = min(j.arrival for j in js)
     last = max(j.finished for j in js)
     ek_open = sum(m * j.k for j, m in submitted)
-    log(f"[serve] Poisson {args.serve_rate}/s for {args.serve_seconds}s: {st}")
+    # where the slowest 1% of jobs spend their time
+    slow = sorted(submitted, key=lambda jm: -jm[0].latency)[:max(1, len(submitted) // 100)]
+    tail = {"jobs": len(slow),
+            "mean_edges": sum(m for _, m in slow) / len(slow),
+            "mean_k": sum(j.k for j, _ in slow) / len(slow),
+            "mean_queue_ms": 1e3 * sum(j.admitted - j.arrival for j, _ in slow) / len(slow),
+            "mean_prepare_ms": 1e3 * sum(j.ready - j.admitted for j, _ in slow) / len(slow),
+            "mean_run_ms": 1e3 * sum(j.finished - j.ready for j, _ in slow) / len(slow)}
+    log(f"[serve] Poisson {args.serve_rate}/s for {args.serve_seconds}s: {st}; slowest 1%: {tail}")
     return {"workload": "serve_poisson200_rmat_m10k-50M_k1-10", "rate_per_s": args.serve_rate,
             "seconds": args.serve_seconds, "jobs": len(js), "errors": st["errors"] + st["rejected"],
             "p50_ms": st["p50_s"] * 1e3, "p99_ms": st["p99_s"] * 1e3,
             "p50_admit_prepare_ms": st["p50_admit_prepare_s"] * 1e3,
             "jobs_per_s": len(js) / (last - first), "edge_iterations_per_s": ek_open / (last - first),
-            "mean_jobs_per_tick": st["mean_jobs_per_tick"], "units": st["units"],
+            "mean_jobs_per_tick": st["mean_jobs_per_tick"], "units": st["units"], "slowest_1pct": tail,
             "peak_budget_bytes": st["peak_bytes"], "budget_bytes": budget,
             "capacity": {"jobs": len(jobs), "continuous_jobs_per_s": len(jobs) / cont_s,
                          "one_at_a_time_jobs_per_s": len(jobs) / fifo_s,
