@@ -393,13 +393,23 @@ int build_schedule(kbisim_ctx *c, const int64_t *ptr, Schedule &s, int64_t row_m
     }
     close(v_end);
   };
+  // Chunks run on threads when there is enough work; a chunk whose thread
+  // cannot be started is packed here (no exception leaves the library).
+  std::vector<std::thread> th;
+  std::vector<char> started((size_t)SCHED_CHUNKS, 0);
   if (n >= (int64_t)1 << 16) {
-    std::vector<std::thread> th;
-    for (int ci = 0; ci < SCHED_CHUNKS; ++ci) th.emplace_back(pack, ci);
-    for (auto &x : th) x.join();
-  } else {
-    for (int ci = 0; ci < SCHED_CHUNKS; ++ci) pack(ci);
+    for (int ci = 0; ci < SCHED_CHUNKS; ++ci) {
+      try {
+        th.emplace_back(pack, ci);
+        started[(size_t)ci] = 1;
+      } catch (...) {
+        break;
+      }
+    }
   }
+  for (int ci = 0; ci < SCHED_CHUNKS; ++ci)
+    if (!started[(size_t)ci]) pack(ci);
+  for (auto &x : th) x.join();
   std::vector<Range> ranges, big_ranges, row8_ranges, row20_ranges;
   std::vector<int> hubs;
   for (const Part &P : parts_) {
@@ -1599,6 +1609,6 @@ const char *kbisim_strerror(int code) {
   }
 }
 
-const char *kbisim_version(void) { return "kbisim 0.2 gfx950"; }
+const char *kbisim_version(void) { return "kbisim 0.3 gfx950"; }
 
 }  // extern "C"
