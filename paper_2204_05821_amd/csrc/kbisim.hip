@@ -188,6 +188,8 @@ struct kbisim_ctx {
   bool narrow = false;  // 32-bit LDS keys: (edge label << pb) | block fits in 31 bits
   u32 pb = 31;
   u32 max_label = 0;    // largest edge label (0 without labels)
+  bool packed = false;  // edge labels packed above the target ranks in gcol
+  u32 rbits = 31;       // bits of the target rank in gcol
   int64_t p0_count = 0;
   // batches
   int64_t num_graphs = 0;
@@ -557,8 +559,8 @@ int build_rank(kbisim_ctx *c) {
   k_rank_from_sorted<<<(unsigned)std::min<int64_t>(blocks_for(n, 256), 1 << 16), 256, 0, c->stream>>>(n, ka, c->rank);
   LAUNCH_CHECK();
   if (m > 0) {
-    k_remap<<<(unsigned)std::min<int64_t>(blocks_for(m, 256), 1 << 16), 256, 0, c->stream>>>(m, c->g.col, c->rank,
-                                                                                          c->gcol);
+    k_remap<<<(unsigned)std::min<int64_t>(blocks_for(m, 256), 1 << 16), 256, 0, c->stream>>>(
+        m, c->g.col, c->rank, c->gcol, c->packed ? c->g.elabel : nullptr, c->rbits);
     LAUNCH_CHECK();
   }
   HIP_TRY(hipStreamSynchronize(c->stream));
@@ -784,7 +786,7 @@ int enqueue_steps(kbisim_ctx *c, const int32_t *prev, int i0, int k, int32_t *co
   for (int i = i0; i < k; ++i) {
     if (careful && (rc = fill_i32(c, c->counters + CNT_STRIDE * i, CNT_STRIDE, 0))) return rc;
     int *dst = batch ? c->ibuf[i & 1] : out[i];
-    GraphSrc src{c->g.row_ptr, c->gcol, c->g.elabel, c->gpid[i & 1], prev, c->pb};
+    GraphSrc src{c->g.row_ptr, c->gcol, c->packed ? nullptr : c->g.elabel, c->gpid[i & 1], prev, c->pb, c->rbits};
     // work-efficient mode: singletons of P_i (flags of step i-1) are not refined
     const unsigned char *skip_in = (c->work_eff && i > 0) ? c->single[(i - 1) & 1] : nullptr;
     unsigned char *single_out = c->work_eff ? c->single[i & 1] : nullptr;
@@ -1099,6 +1101,13 @@ int create_impl(const kbisim_graph *g, int kmax, const kbisim_tuning *tuning, vo
     while (lb < 32 && (max_label >> lb) != 0) ++lb;
     c->pb = pb;
     c->max_label = max_label;
+    // pack (label, rank) into one 32-bit gather index when both fit
+    u32 rb = 1;
+    while (rb < 31 && (int64_t(1) << rb) < n) ++rb;
+    if (g->elabel && rb + lb <= 32) {
+      c->packed = true;
+      c->rbits = rb;
+    }
     c->narrow = c->tune.key_bits != 64 && pb + lb <= 31;
   }
 

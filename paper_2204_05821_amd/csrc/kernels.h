@@ -114,8 +114,8 @@ __device__ inline u64 finalize_key(u64 acc, u32 dc, u32 own) {
 // lines, which roughly halves the cost of the per-entry random gather.
 struct GraphSrc {
   const int64_t *row_ptr;
-  const int32_t *gcol;    // targets renumbered by in-degree rank
-  const int32_t *elabel;  // may be null
+  const int32_t *gcol;    // targets renumbered by in-degree rank (and, packed, their labels)
+  const int32_t *elabel;  // null without labels, or when the labels are packed into gcol
   const int32_t *gpid;    // previous partition in rank order
   const int32_t *pid;     // previous partition in vertex order
   __device__ inline int64_t begin(int v) const { return row_ptr[v]; }
@@ -125,19 +125,30 @@ struct GraphSrc {
   // (pb covers the largest graph; a single graph: all ids), so the reduction
   // is one-to-one within a row, and every kernel reduces the same way.
   u32 pb;
+  // gcol[e] = (label << rbits) | rank when labels are packed (elabel null and
+  // rbits < 31); otherwise rbits = 31 and the label comes from elabel (or is
+  // 0).  Packing halves the streamed bytes per entry.
+  u32 rbits;
   __device__ inline u32 pmask() const { return pb >= 31 ? 0x7FFFFFFFu : (1u << pb) - 1u; }
+  // (label, rank of the target) of entry e; streamed arrays are read
+  // non-temporally so they do not evict the gather targets from the L2
+  __device__ inline void entry(int64_t e, u32 &l, u32 &r) const {
+    const u32 g = (u32)__builtin_nontemporal_load(&gcol[e]);
+    l = elabel ? (u32)__builtin_nontemporal_load(&elabel[e]) : (g >> rbits);
+    r = g & ((1u << rbits) - 1u);
+  }
   __device__ inline u64 pair(int64_t e) const {
-    // streamed arrays are read non-temporally so they do not evict the
-    // gather targets from the L2
-    const u32 l = elabel ? (u32)__builtin_nontemporal_load(&elabel[e]) : 0u;
-    return ((u64)l << 31) | (u64)((u32)gpid[__builtin_nontemporal_load(&gcol[e])] & pmask());
+    u32 l, r;
+    entry(e, l, r);
+    return ((u64)l << 31) | (u64)((u32)gpid[r] & pmask());
   }
   __device__ inline u32 own(int v) const { return (u32)pid[v]; }
   // Narrow form of a pair, used inside LDS sets when every edge label and
   // reduced block id fit together in 31 bits: (label << pb) | block.
   __device__ inline u32 key32(int64_t e) const {
-    const u32 l = elabel ? (u32)__builtin_nontemporal_load(&elabel[e]) : 0u;
-    return (l << pb) | ((u32)gpid[__builtin_nontemporal_load(&gcol[e])] & pmask());
+    u32 l, r;
+    entry(e, l, r);
+    return (l << pb) | ((u32)gpid[r] & pmask());
   }
   __device__ inline u64 wide(u32 q) const { return ((u64)(q >> pb) << 31) | (u64)(q & pmask()); }
 };
@@ -1337,9 +1348,15 @@ __global__ void k_indegree(int64_t m, const int *__restrict__ col, int *indeg) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x)
     atomicAdd(&indeg[col[e]], 1);
 }
-__global__ void k_remap(int64_t m, const int *__restrict__ col, const int *__restrict__ rank, int *__restrict__ gcol) {
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x)
-    gcol[e] = rank[col[e]];
+// gcol[e] = rank[col[e]], with the entry's label in the bits above rbits
+// when elabel is given (packed form).
+__global__ void k_remap(int64_t m, const int *__restrict__ col, const int *__restrict__ rank, int *__restrict__ gcol,
+                        const int *__restrict__ elabel, u32 rbits) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
+    u32 g = (u32)rank[col[e]];
+    if (elabel) g |= (u32)elabel[e] << rbits;
+    gcol[e] = (int)g;
+  }
 }
 __global__ void k_scatter_rank(int n, const int *__restrict__ pid, const int *__restrict__ rank, int *__restrict__ gpid) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;

@@ -313,3 +313,17 @@ def test_invalid_graphs_rejected():
         r.refine(1, start=big)
     assert ei.value.code == kb.EINVAL
     r.close()
+
+
+def test_large_sparse_label_values():
+    """Labels need not be dense: values up to 2^31 - 1 (no packing, 64-bit keys) and a mix of
+    small graphs where labels pack above the target ranks."""
+    rng = np.random.default_rng(17)
+    g = graphgen.rmat(13, 90_000, seed=9)
+    big = np.array([0, 5, 1 << 20, (1 << 31) - 1, 123456789, 77], dtype=np.int64)
+    g.elabel = big[rng.integers(0, len(big), size=g.m)].astype(np.int32)
+    g.vlabel = (big[rng.integers(0, len(big), size=g.n)] // 3).astype(np.int32)
+    assert_same(g, 6, "large-labels")
+    h = graphgen.rmat(13, 90_000, seed=9)
+    h.elabel = (h.elabel * 1000).astype(np.int32)      # 16 label bits + 13 rank bits: packed
+    assert_same(h, 6, "spread-labels")
