@@ -327,3 +327,35 @@ def test_large_sparse_label_values():
     h = graphgen.rmat(13, 90_000, seed=9)
     h.elabel = (h.elabel * 1000).astype(np.int32)      # 16 label bits + 13 rank bits: packed
     assert_same(h, 6, "spread-labels")
+
+
+def giant_hub_graph(seed=23):
+    """Two twin rows of 4.5M entries (same pairs, different order and duplicates), one slightly
+    different, and small rows."""
+    rng = np.random.default_rng(seed)
+    n, d = 60_000, 4_500_000
+    tg = rng.integers(10, 40_000, size=d)
+    lb = rng.integers(0, 5, size=d)
+    perm = rng.permutation(d)
+    src = [np.zeros(d, np.int64), np.ones(d, np.int64), np.full(d, 2, np.int64)]
+    dst = [tg, tg[perm], np.concatenate([tg[:-1], [50_000]])]
+    lab = [lb, lb[perm], lb]
+    m_small = 200_000
+    src.append(rng.integers(3, n, size=m_small))
+    dst.append(rng.integers(0, n, size=m_small))
+    lab.append(rng.integers(0, 5, size=m_small))
+    return graphgen.from_edges(n, np.concatenate(src), np.concatenate(dst), np.concatenate(lab),
+                               rng.integers(0, 2, size=n), name="giant-hubs")
+
+
+def test_giant_hubs_use_the_global_set_path():
+    """Rows above 4M entries take the global-hash-set hub path."""
+    kb = _kb()
+    g = giant_hub_graph()
+    r = kb.refiner_for(g, kmax=1)
+    info = r.schedule_info()
+    r.close()
+    assert info["hub_global"]["vertices"] == 3, info
+    exp, _ = ref_all(g, 3)
+    assert exp[1][0] == exp[1][1] != exp[1][2]
+    assert_same(g, 3, "giant-hubs")

@@ -63,8 +63,9 @@ def test_same_partitions_fewer_steps(make, k):
 
 
 def test_tiers_and_forced_collisions(monkeypatch):
-    from tests.test_gpu_parity import tier_graph
+    from tests.test_gpu_parity import giant_hub_graph, tier_graph
     check(tier_graph(seed=3), 6, "tiers")
+    check(giant_hub_graph(seed=4), 4, "giant-hubs")
     monkeypatch.setenv("KBISIM_DEBUG_HASH_BITS", "6")
     check(tier_graph(seed=5), 5, "tiers-collide")
     check(graphgen.deep(seed=9, n=6000, avg_degree=1.2), 8, "deep-collide")
