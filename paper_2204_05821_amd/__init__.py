@@ -85,6 +85,8 @@ def _lib():
     lib.kbisim_quotient_workspace_bytes.restype = i32
     lib.kbisim_quotient.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.POINTER(i64), vp, sz]
     lib.kbisim_quotient.restype = i32
+    lib.kbisim_gather_probe.argtypes = [vp, vp, i32, ctypes.POINTER(ctypes.c_double)]
+    lib.kbisim_gather_probe.restype = i32
     lib.kbisim_work_efficient.argtypes = [vp, i32, ctypes.POINTER(i32)]
     lib.kbisim_work_efficient.restype = i32
     lib.kbisim_profile_select.argtypes = [vp, ctypes.c_uint32]
@@ -230,6 +232,15 @@ class Refiner:
         if rc:
             raise KbisimError(rc, "kbisim_work_efficient")
         return int(steps.value)
+
+    def gather_probe(self, pid: torch.Tensor, reps: int = 5) -> float:
+        """Milliseconds of one pass of the bare random gather over all entries (the signature bound)."""
+        _check(pid, torch.int32, "pid", self.device)
+        ms = ctypes.c_double(0.0)
+        rc = _lib().kbisim_gather_probe(self._ctx, _ptr(pid), int(reps), ctypes.byref(ms))
+        if rc:
+            raise KbisimError(rc, "kbisim_gather_probe")
+        return float(ms.value)
 
     def quotient(self, src_pid: torch.Tensor, dst_pid: torch.Tensor):
         """Summary graph: distinct (source block, label, target block) triples, sorted.

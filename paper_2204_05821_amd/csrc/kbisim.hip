@@ -1355,6 +1355,40 @@ int kbisim_copy_probe(void *dst, const void *src, size_t bytes, void *stream) {
   return KBISIM_OK;
 }
 
+int kbisim_gather_probe(kbisim_ctx *c, const int32_t *pid, int reps, double *ms) {
+  if (!c || !pid || reps < 1 || !ms) return KBISIM_EINVAL;
+  *ms = 0.0;
+  const int64_t n = c->g.n, m = c->g.m;
+  if (m == 0) return KBISIM_OK;
+  k_scatter_rank<<<blocks_for(n, 256), 256, 0, c->stream>>>((int)n, pid, c->rank, c->gpid[0]);
+  HIP_TRY(hipGetLastError());
+  u32 slots = 1;  // output words: a power of two, at most 1024 and at most n
+  while (slots < 1024 && (int64_t)slots * 2 <= n) slots *= 2;
+  int rc = fill_i32(c, c->vlist, slots, 0);
+  if (rc) return rc;
+  // the probe reads the same gather index and pairs as the signature kernels
+  GraphSrc src{c->g.row_ptr, c->gcol, c->packed ? nullptr : c->g.elabel, c->gpid[0], pid, c->pb, c->rbits};
+  const unsigned grid = (unsigned)std::min<int64_t>((m + 1023) / 1024, 1 << 20);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return KBISIM_EHIP;
+  }
+  k_gather_probe<<<grid, 256, 0, c->stream>>>(src, m, (u32 *)c->vlist, slots - 1);  // warm-up
+  (void)hipEventRecord(e0, c->stream);
+  for (int r = 0; r < reps; ++r) k_gather_probe<<<grid, 256, 0, c->stream>>>(src, m, (u32 *)c->vlist, slots - 1);
+  (void)hipEventRecord(e1, c->stream);
+  hipError_t e = hipStreamSynchronize(c->stream);
+  float t = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return hip_fail(e);
+  *ms = (double)t / reps;
+  return KBISIM_OK;
+}
+
 int kbisim_batch_workspace_bytes(const kbisim_graph *u, int64_t num_graphs, int kmax, size_t *bytes) {
   int rc = check_sizes(u);
   if (rc) return rc;

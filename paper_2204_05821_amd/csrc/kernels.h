@@ -137,18 +137,45 @@ struct GraphSrc {
     l = elabel ? (u32)__builtin_nontemporal_load(&elabel[e]) : (g >> rbits);
     r = g & ((1u << rbits) - 1u);
   }
+  // entry() for first + min(t + u*STRIDE, count - 1), u < U, with the label
+  // branch taken once, so all the streamed words are requested together
+  template <int U, int STRIDE>
+  __device__ inline void entries(int64_t first, int t, int count, u32 (&l)[U], u32 (&r)[U]) const {
+    const u32 rm = (1u << rbits) - 1u;
+    if (elabel) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t e = first + min(t + u * STRIDE, count - 1);
+        r[u] = (u32)__builtin_nontemporal_load(&gcol[e]);
+        l[u] = (u32)__builtin_nontemporal_load(&elabel[e]);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) r[u] &= rm;
+    } else {
+#pragma unroll
+      for (int u = 0; u < U; ++u) r[u] = (u32)__builtin_nontemporal_load(&gcol[first + min(t + u * STRIDE, count - 1)]);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        l[u] = r[u] >> rbits;
+        r[u] &= rm;
+      }
+    }
+  }
+  // the pair of an entry whose (label, rank) entry() has read: one gather
+  __device__ inline u64 pair_of(u32 l, u32 r) const { return ((u64)l << 31) | (u64)((u32)gpid[r] & pmask()); }
   __device__ inline u64 pair(int64_t e) const {
     u32 l, r;
     entry(e, l, r);
-    return ((u64)l << 31) | (u64)((u32)gpid[r] & pmask());
+    return pair_of(l, r);
   }
   __device__ inline u32 own(int v) const { return (u32)pid[v]; }
   // Narrow form of a pair, used inside LDS sets when every edge label and
   // reduced block id fit together in 31 bits: (label << pb) | block.
+  __device__ inline u32 key32_of(u32 l, u32 r) const { return (l << pb) | ((u32)gpid[r] & pmask()); }
   __device__ inline u32 key32(int64_t e) const {
     u32 l, r;
     entry(e, l, r);
-    return (l << pb) | ((u32)gpid[r] & pmask());
+    return key32_of(l, r);
   }
   __device__ inline u64 wide(u32 q) const { return ((u64)(q >> pb) << 31) | (u64)(q & pmask()); }
 };
@@ -160,6 +187,19 @@ struct LabelSrc {
   __device__ inline int64_t begin(int v) const { return ptr ? ptr[v] : (int64_t)v; }
   __device__ inline int64_t end(int v) const { return ptr ? ptr[v + 1] : (int64_t)v + 1; }
   __device__ inline u64 pair(int64_t e) const { return (u64)(u32)lab[e]; }
+  __device__ inline void entry(int64_t e, u32 &l, u32 &r) const {
+    l = (u32)lab[e];
+    r = 0;
+  }
+  template <int U, int STRIDE>
+  __device__ inline void entries(int64_t first, int t, int count, u32 (&l)[U], u32 (&r)[U]) const {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      l[u] = (u32)lab[first + min(t + u * STRIDE, count - 1)];
+      r[u] = 0;
+    }
+  }
+  __device__ inline u64 pair_of(u32 l, u32) const { return (u64)l; }
   __device__ inline u32 own(int v) const { return gid ? (u32)gid[v] : 0u; }
 };
 
@@ -172,6 +212,8 @@ struct Keys<u64> {
   template <class Src>
   __device__ static inline u64 load(const Src &s, int64_t e) { return s.pair(e); }
   template <class Src>
+  __device__ static inline u64 from(const Src &s, u32 l, u32 r) { return s.pair_of(l, r); }
+  template <class Src>
   __device__ static inline u64 wide(const Src &, u64 p) { return p; }
   __device__ static inline u32 hash(u64 p) { return set_hash(p); }
 };
@@ -181,12 +223,31 @@ struct Keys<u32> {
   template <class Src>
   __device__ static inline u32 load(const Src &s, int64_t e) { return s.key32(e); }
   template <class Src>
+  __device__ static inline u32 from(const Src &s, u32 l, u32 r) { return s.key32_of(l, r); }
+  template <class Src>
   __device__ static inline u64 wide(const Src &s, u32 q) { return s.wide(q); }
   __device__ static inline u32 hash(u32 q) {
     const u32 h = q * 0x9E3779B1u;
     return h ^ (h >> 15);
   }
 };
+
+// Load the keys of entries first + j*STRIDE (j = 0..U-1, only those below
+// count are valid; the others become EMPTY).  All streamed words are
+// requested before any gather, and no load sits under a branch, so a wave
+// waits twice in all instead of twice per entry.  Invalid slots re-read the
+// last valid entry (count >= 1 is required).
+template <class K, int U, int STRIDE, class Src>
+__device__ inline void load_keys(const Src &src, int64_t first, int t, int count, K (&out)[U]) {
+  typedef Keys<K> KO;
+  u32 l[U], r[U];
+  src.template entries<U, STRIDE>(first, t, count, l, r);
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const K p = KO::from(src, l[u], r[u]);
+    out[u] = t + u * STRIDE < count ? p : KO::EMPTY;
+  }
+}
 
 // ---------------------------------------------------------------- wave helpers
 __device__ inline u64 wave_sum_u64(u64 x) {
@@ -426,10 +487,11 @@ __global__ void __launch_bounds__(256) k_sig_range(Src src, const Range *__restr
       if (off[i + 1] > off[i]) owner[off[i]] = (unsigned char)i;
   K pr[U];
   if constexpr (!SKIP) {
+    if (E > 0) {
+      load_keys<K, U, 256>(src, eb, t, E, pr);
+    } else {
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int j = t + u * 256;
-      pr[u] = j < E ? KO::load(src, eb + j) : KO::EMPTY;
+      for (int u = 0; u < U; ++u) pr[u] = KO::EMPTY;
     }
   }
   __syncthreads();
@@ -459,15 +521,20 @@ __global__ void __launch_bounds__(256) k_sig_range(Src src, const Range *__restr
   }
   if constexpr (SKIP) {
     // packed entry j of row lo sits at CSR offset roff[lo] + (j - coff[lo])
+    u32 l[U], r[U];
+    if (E > 0) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int j = min(t + u * 256, E - 1);
+        const int lo = single ? 0 : owner[j];
+        src.entry(eb + roff[lo] + (j - coff[lo]), l[u], r[u]);
+      }
+    }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int j = t + u * 256;
       K p = KO::EMPTY;
-      if (j < E) {
-        const int lo = single ? 0 : owner[j];
-        p = KO::load(src, eb + roff[lo] + (j - coff[lo]));
-      }
-      pr[u] = p;
+      if (E > 0) p = KO::from(src, l[u], r[u]);
+      pr[u] = t + u * 256 < E ? p : KO::EMPTY;
     }
   }
   if (single) {
@@ -595,10 +662,11 @@ __global__ void __launch_bounds__(NT) k_sig_row(Src src, const Range *__restrict
   const int E = (int)(src.end(v) - eb);
   for (int i = t; i < 2 * E; i += NT) set[i] = KO::EMPTY;
   K pr[U];
+  if (E > 0) {
+    load_keys<K, U, NT>(src, eb, t, E, pr);
+  } else {
 #pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const int j = t + u * NT;
-    pr[u] = j < E ? KO::load(src, eb + j) : KO::EMPTY;
+    for (int u = 0; u < U; ++u) pr[u] = KO::EMPTY;
   }
   __syncthreads();
   u64 a = 0;
@@ -668,10 +736,11 @@ __global__ void __launch_bounds__(256) k_hub_stage(Src src, const HubChunk *__re
   for (int i = threadIdx.x; i < 2 * CHUNK; i += 256) set[i] = KO::EMPTY;
   for (int i = threadIdx.x; i <= P; i += 256) hist[i] = 0;
   K pr[HUB_U];
+  if (E > 0) {
+    load_keys<K, HUB_U, 256>(src, row + c.b, (int)threadIdx.x, E, pr);
+  } else {
 #pragma unroll
-  for (int u = 0; u < HUB_U; ++u) {
-    const int j = threadIdx.x + u * 256;
-    pr[u] = j < E ? KO::load(src, row + c.b + j) : KO::EMPTY;
+    for (int u = 0; u < HUB_U; ++u) pr[u] = KO::EMPTY;
   }
   __syncthreads();
   int rank[HUB_U];
@@ -1588,6 +1657,25 @@ __global__ void k_copy_i32(int *dst, const int *src, int64_t cnt) {
 __global__ void k_copy16(uint4 *__restrict__ dst, const uint4 *__restrict__ src, int64_t n16) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (int64_t)gridDim.x * blockDim.x)
     dst[i] = src[i];
+}
+
+// Gather probe: every CSR entry reads its target's previous block through the
+// same index and layout the signature kernels use (one streamed word, one
+// random 4-byte gather), and nothing else.  Measures the random-gather rate
+// the signature kernels are bounded by; one value per workgroup is written so
+// the loads cannot be dropped.
+__global__ void __launch_bounds__(256) k_gather_probe(GraphSrc src, int64_t m, u32 *out, u32 omask) {
+  u32 acc = 0;
+  constexpr int U = 4;
+  for (int64_t base = (int64_t)blockIdx.x * 256 * U; base < m; base += (int64_t)gridDim.x * 256 * U) {
+    u32 v[U];
+    const int cnt = (int)min<int64_t>(m - base, 256 * U);
+    load_keys<u32, U, 256>(src, base, (int)threadIdx.x, cnt, v);
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc ^= v[u];
+  }
+  acc = wave_sum_u32(acc);
+  if ((threadIdx.x & (WAVE - 1)) == 0) atomicAdd(&out[blockIdx.x & omask], acc);
 }
 
 // Degrees of the hub list (for host-side chunking at create time).
