@@ -459,6 +459,9 @@ __global__ void __launch_bounds__(256) k_sig_range(Src src, const Range *__restr
   const bool single = V == 1;
   const int64_t eb = src.begin(rg.v0);
   for (int i = t; i <= V; i += 256) roff[i] = (int)(src.begin(rg.v0 + i) - eb);
+  // this thread's vertex (V <= blockDim): its previous block, fetched with
+  // the row offsets so the epilogue does not wait for it
+  const u32 own_t = t < V ? src.own(rg.v0 + t) : 0u;
   for (int i = t; i < V; i += 256) {
     acc[i] = 0;
     cnt[i] = 0;
@@ -559,7 +562,7 @@ __global__ void __launch_bounds__(256) k_sig_range(Src src, const Range *__restr
     if constexpr (SKIP) out = out && !skip[rg.v0];
     if (out) {
       const int v = rg.v0;
-      const u32 own = src.own(v);
+      const u32 own = own_t;
       const u64 h = finalize_key(a, c, own) & hmask;
       H[v] = h;
       DC[v] = c;
@@ -627,13 +630,12 @@ __global__ void __launch_bounds__(256) k_sig_range(Src src, const Range *__restr
   const int v = rg.v0 + t;
   if (t < V && !skipped) {
     const u32 c = cnt[t];
+    own = own_t;
     if (c) {
-      own = src.own(v);
       const u64 h = finalize_key(acc[t], c, own) & hmask;
       H[v] = h;
       table_insert(table, tmask, h, (u32)v, epoch);
     } else if (zfresh) {
-      own = src.own(v);
       zero = true;
     }
     DC[v] = c;
@@ -659,6 +661,7 @@ __global__ void __launch_bounds__(NT) k_sig_row(Src src, const Range *__restrict
   const int v = rows[blockIdx.x].v0;
   if (skip && skip[v]) return;  // singleton block (work-efficient mode)
   const int64_t eb = src.begin(v);
+  const u32 own0 = t == 0 ? src.own(v) : 0u;  // fetched early, used by thread 0 at the end
   const int E = (int)(src.end(v) - eb);
   for (int i = t; i < 2 * E; i += NT) set[i] = KO::EMPTY;
   K pr[U];
@@ -686,11 +689,10 @@ __global__ void __launch_bounds__(NT) k_sig_row(Src src, const Range *__restrict
   }
   block_reduce_2(a, c, sh_acc, sh_cnt);
   if (t == 0) {
-    const u32 own = src.own(v);
-    const u64 h = finalize_key(a, c, own) & hmask;
+    const u64 h = finalize_key(a, c, own0) & hmask;
     H[v] = h;
     DC[v] = c;
-    key_insert(table, tmask, zrep, h, c, own, (u32)v, dep[EP_TABLE], dep[EP_ZERO]);
+    key_insert(table, tmask, zrep, h, c, own0, (u32)v, dep[EP_TABLE], dep[EP_ZERO]);
   }
 }
 
