@@ -231,6 +231,18 @@ def run_plain(args, kb, torch):
                     "algorithmic_bytes_per_launch": ab, "avg_launch_ms": round(avg, 5)}
     b_alg = 12.0 * g.m + 16.0 * g.n
     step_gbs = b_alg * k / (ms_per_step / 1e3) / 1e9
+    # the bare random gather over all entries, for the same partition: the
+    # ceiling the signature kernels work against (one pass = one iteration's gathers)
+    probe_ms = r.gather_probe(outs[k - 1], reps=5)
+    gather = {"ms_per_pass": probe_ms, "entries": g.m, "G_gathers_per_s": g.m / (probe_ms / 1e3) / 1e9,
+              "algorithmic_GBs": 8.0 * g.m / (probe_ms / 1e3) / 1e9}
+    if roofline is not None:
+        sig_ms = sum(kernels[kk]["ms_per_launch"] for kk in ("k_sig_range", "k_sig_row", "k_hub_stage",
+                                                             "k_hub_reduce") if kk in kernels)
+        gather["signature_kernels_ms_per_iteration"] = sig_ms
+        gather["probe_share_of_signature_time"] = probe_ms / sig_ms if sig_ms else None
+    log(f"[bench] gather probe: {probe_ms:.3f} ms per pass over {g.m} entries "
+        f"({gather['G_gathers_per_s']:.1f} G gathers/s)")
 
     # Work-efficient mode (singleton blocks skipped, stop at the fixpoint): reported
     # separately; its outputs must equal the full-work outputs.
@@ -292,6 +304,7 @@ def run_plain(args, kb, torch):
         "step_hbm": {"algorithmic_bytes_per_iteration": b_alg, "achieved_GBs": round(step_gbs, 1),
                      "frac_of_peak": round(step_gbs / HBM_PEAK_GBS, 4)},
         "counts": counts,
+        "gather_probe": gather,
         "work_efficient": work_efficient,
         "summary_graph": summary,
         "create_ms": round(create_ms, 1),

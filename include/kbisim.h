@@ -281,6 +281,14 @@ int kbisim_schedule_info(kbisim_ctx *c, int64_t *info);
  * achievable HBM bandwidth and to calibrate hardware byte counters.        */
 int kbisim_copy_probe(void *dst, const void *src, size_t bytes, void *stream);
 
+/* Time the context's random gather alone: every CSR entry reads the block id
+ * of its target (in pid, device int32 [n]) through the same index and layout
+ * as the signature kernels, and nothing else is done.  *ms (host) receives
+ * the mean time of one pass over all m entries (reps passes after a warm-up).
+ * It bounds what the signature kernels can reach on this graph.  Overwrites
+ * scratch parts of the workspace; synchronises.                             */
+int kbisim_gather_probe(kbisim_ctx *c, const int32_t *pid, int reps, double *ms);
+
 /* ---- single steps (for schedulers that interleave many contexts) --------- */
 
 /* Enqueue step i (0 <= i < kmax): P_{i+1} from prev into out (device int32

@@ -215,3 +215,15 @@ def test_solo_single_steps_equal_reference(bits, monkeypatch):
         for a, b in zip(outs, exp):
             assert np.array_equal(a.cpu().numpy(), b)
     r.close()
+
+
+def test_gather_probe_runs_on_small_and_empty_graphs():
+    kb = _kb()
+    for g in [graphgen.from_edges(3, [0, 1], [1, 2]), graphgen.tiny(seed=2, n=500, m=3000),
+              graphgen.from_edges(5, [], [])]:
+        r = kb.refiner_for(g, kmax=1)
+        ids, _ = r.refine(1)
+        assert r.gather_probe(ids[0], reps=2) >= 0.0
+        ids2, _ = r.refine(1)                      # the context still refines correctly afterwards
+        assert torch.equal(ids[0], ids2[0])
+        r.close()
