@@ -348,13 +348,16 @@ int build_schedule(kbisim_ctx *c, const int64_t *ptr, Schedule &s, int64_t row_m
     if (!ptr) {
       // one label per vertex: every row has one item, ranges of RANGE_VERTS vertices
       for (int64_t v0 = v_begin; v0 < v_end; v0 += RANGE_VERTS)
-        P.ranges.push_back(Range{(int)v0, (int)std::min<int64_t>(v_end, v0 + RANGE_VERTS)});
+      {
+        const int64_t v1 = std::min<int64_t>(v_end, v0 + RANGE_VERTS);
+        P.ranges.push_back(Range{(int)v0, (int)v1, (int)(v1 - v0), 0, v0});
+      }
       P.info[0] = P.info[1] = P.nonempty = v_end - v_begin;
       return;
     }
     int64_t cur0 = -1, cur_e = 0;
     auto close = [&](int64_t vend) {
-      if (cur0 >= 0) P.ranges.push_back(Range{(int)cur0, (int)vend});
+      if (cur0 >= 0) P.ranges.push_back(Range{(int)cur0, (int)vend, (int)cur_e, 0, rp[(size_t)cur0]});
       cur0 = -1;
       cur_e = 0;
     };
@@ -368,21 +371,21 @@ int build_schedule(kbisim_ctx *c, const int64_t *ptr, Schedule &s, int64_t row_m
       }
       if (d > ROW_MAX) {
         close(v);
-        P.row20.push_back(Range{(int)v, (int)v + 1});
+        P.row20.push_back(Range{(int)v, (int)v + 1, (int)d, 0, rp[(size_t)v]});
         P.info[2] += 1;
         P.info[3] += d;
         continue;
       }
       if (d > RANGE_DMAX) {
         close(v);
-        P.row8.push_back(Range{(int)v, (int)v + 1});
+        P.row8.push_back(Range{(int)v, (int)v + 1, (int)d, 0, rp[(size_t)v]});
         P.info[2] += 1;
         P.info[3] += d;
         continue;
       }
       if (d > t.range_edges) {
         close(v);
-        P.big.push_back(Range{(int)v, (int)v + 1});
+        P.big.push_back(Range{(int)v, (int)v + 1, (int)d, 0, rp[(size_t)v]});
         P.info[2] += 1;
         P.info[3] += d;
         continue;
@@ -583,7 +586,7 @@ int peel_round(kbisim_ctx *c, const Src &src, int *in_cnt, int *in_list, int *ou
 // block alone), so their table span is sized by that count; P0 uses it all.
 template <class Src>
 u64 table_mask(const kbisim_ctx *c) {
-  if constexpr (std::is_same<Src, GraphSrc>::value) return c->tmask_steps;
+  if constexpr (Src::GRAPH) return c->tmask_steps;
   return c->plan.tslots - 1;
 }
 
@@ -607,7 +610,7 @@ int launch_ranges_k(kbisim_ctx *c, const Src &src, const Schedule &s, int zfresh
   const u64 tmask = table_mask<Src>(c);
   if (s.nranges) {
     int rc = 0;
-    if constexpr (std::is_same<Src, GraphSrc>::value) {
+    if constexpr (Src::GRAPH) {
       rc = skip ? launch_range_kernel<Src, K, true>(c, src, s, tmask, zfresh, skip)
                 : launch_range_kernel<Src, K, false>(c, src, s, tmask, zfresh, nullptr);
     } else {
@@ -641,7 +644,7 @@ int launch_ranges_k(kbisim_ctx *c, const Src &src, const Schedule &s, int zfresh
 
 template <class Src>
 int launch_ranges(kbisim_ctx *c, const Src &src, const Schedule &s, int zfresh, const unsigned char *skip) {
-  if constexpr (std::is_same<Src, GraphSrc>::value) {
+  if constexpr (Src::GRAPH) {
     if (c->narrow) return launch_ranges_k<Src, u32>(c, src, s, zfresh, skip);
   }
   return launch_ranges_k<Src, u64>(c, src, s, zfresh, skip);
@@ -693,7 +696,7 @@ int run_step(kbisim_ctx *c, const Src &src, const Schedule &s, int *out, int64_t
   if (s.nhub) {
     const int *hubs = c->lists + s.hub_off;
     if (s.nchunks) {
-      if constexpr (std::is_same<Src, GraphSrc>::value) {
+      if constexpr (Src::GRAPH) {
         rc = c->narrow ? launch_hub_staged<Src, u32>(c, src, s, hubs, skip_in)
                        : launch_hub_staged<Src, u64>(c, src, s, hubs, skip_in);
       } else {
@@ -768,6 +771,9 @@ int run_step(kbisim_ctx *c, const Src &src, const Schedule &s, int *out, int64_t
   return 0;
 }
 
+// Edge labels read from their own array (not packed into gcol, and present).
+bool separate_labels(const kbisim_ctx *c) { return !c->packed && c->g.elabel != nullptr; }
+
 // Enqueue steps [i0, k) starting from partition `prev` (no host
 // synchronisation unless careful).  In a batch, step i refines into an
 // internal buffer of global ids and writes the caller's per-graph ids and
@@ -786,12 +792,17 @@ int enqueue_steps(kbisim_ctx *c, const int32_t *prev, int i0, int k, int32_t *co
   for (int i = i0; i < k; ++i) {
     if (careful && (rc = fill_i32(c, c->counters + CNT_STRIDE * i, CNT_STRIDE, 0))) return rc;
     int *dst = batch ? c->ibuf[i & 1] : out[i];
-    GraphSrc src{c->g.row_ptr, c->gcol, c->packed ? nullptr : c->g.elabel, c->gpid[i & 1], prev, c->pb, c->rbits};
     // work-efficient mode: singletons of P_i (flags of step i-1) are not refined
     const unsigned char *skip_in = (c->work_eff && i > 0) ? c->single[(i - 1) & 1] : nullptr;
     unsigned char *single_out = c->work_eff ? c->single[i & 1] : nullptr;
-    rc = run_step(c, src, c->sched, dst, &c->dcounts[i], c->counters + CNT_STRIDE * i, careful, c->gpid[(i + 1) & 1],
-                  i == 0, skip_in, single_out);
+    auto step = [&](auto src) {
+      return run_step(c, src, c->sched, dst, &c->dcounts[i], c->counters + CNT_STRIDE * i, careful,
+                      c->gpid[(i + 1) & 1], i == 0, skip_in, single_out);
+    };
+    if (separate_labels(c))
+      rc = step(GraphSrcT<true>{c->g.row_ptr, c->gcol, c->g.elabel, c->gpid[i & 1], prev, c->pb, c->rbits});
+    else
+      rc = step(GraphSrcT<false>{c->g.row_ptr, c->gcol, nullptr, c->gpid[i & 1], prev, c->pb, c->rbits});
     if (rc) return rc;
     if (batch) {
       k_rebase<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, c->gid, c->first, dst, out[i]);
@@ -1367,17 +1378,23 @@ int kbisim_gather_probe(kbisim_ctx *c, const int32_t *pid, int reps, double *ms)
   int rc = fill_i32(c, c->vlist, slots, 0);
   if (rc) return rc;
   // the probe reads the same gather index and pairs as the signature kernels
-  GraphSrc src{c->g.row_ptr, c->gcol, c->packed ? nullptr : c->g.elabel, c->gpid[0], pid, c->pb, c->rbits};
   const unsigned grid = (unsigned)std::min<int64_t>((m + 1023) / 1024, 1 << 20);
+  const GraphSrcT<true> sep{c->g.row_ptr, c->gcol, c->g.elabel, c->gpid[0], pid, c->pb, c->rbits};
+  const GraphSrcT<false> pk{c->g.row_ptr, c->gcol, nullptr, c->gpid[0], pid, c->pb, c->rbits};
+  const bool s2 = separate_labels(c);
+  auto probe = [&]() {
+    if (s2) k_gather_probe<<<grid, 256, 0, c->stream>>>(sep, m, (u32 *)c->vlist, slots - 1);
+    else k_gather_probe<<<grid, 256, 0, c->stream>>>(pk, m, (u32 *)c->vlist, slots - 1);
+  };
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIP_TRY(hipEventCreate(&e0));
   if (hipEventCreate(&e1) != hipSuccess) {
     (void)hipEventDestroy(e0);
     return KBISIM_EHIP;
   }
-  k_gather_probe<<<grid, 256, 0, c->stream>>>(src, m, (u32 *)c->vlist, slots - 1);  // warm-up
+  probe();  // warm-up
   (void)hipEventRecord(e0, c->stream);
-  for (int r = 0; r < reps; ++r) k_gather_probe<<<grid, 256, 0, c->stream>>>(src, m, (u32 *)c->vlist, slots - 1);
+  for (int r = 0; r < reps; ++r) probe();
   (void)hipEventRecord(e1, c->stream);
   hipError_t e = hipStreamSynchronize(c->stream);
   float t = 0.f;

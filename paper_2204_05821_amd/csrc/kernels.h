@@ -112,37 +112,44 @@ __device__ inline u64 finalize_key(u64 acc, u32 dc, u32 own) {
 // rank(col[e]) and gpid[rank(w)] = pid[w], where ranks order vertices by
 // decreasing in-degree.  The targets most edges point to then share cache
 // lines, which roughly halves the cost of the per-entry random gather.
-struct GraphSrc {
+// SEP: edge labels come from their own array (elabel); otherwise they sit
+// above the rank in gcol (or there are none), and elabel is unused.
+template <bool SEP>
+struct GraphSrcT {
+  static constexpr bool GRAPH = true;
   const int64_t *row_ptr;
   const int32_t *gcol;    // targets renumbered by in-degree rank (and, packed, their labels)
-  const int32_t *elabel;  // null without labels, or when the labels are packed into gcol
+  const int32_t *elabel;  // the labels when SEP
   const int32_t *gpid;    // previous partition in rank order
   const int32_t *pid;     // previous partition in vertex order
   __device__ inline int64_t begin(int v) const { return row_ptr[v]; }
   __device__ inline int64_t end(int v) const { return row_ptr[v + 1]; }
+  // low word of begin(v): enough for offsets within a range (little endian)
+  __device__ inline u32 begin_lo(int v) const { return reinterpret_cast<const u32 *>(row_ptr)[2 * (int64_t)v]; }
   // A pair keeps the target's block id modulo 2^pb.  The targets of one row
   // lie in one graph, whose block ids form an interval of at most 2^pb ids
   // (pb covers the largest graph; a single graph: all ids), so the reduction
   // is one-to-one within a row, and every kernel reduces the same way.
   u32 pb;
-  // gcol[e] = (label << rbits) | rank when labels are packed (elabel null and
-  // rbits < 31); otherwise rbits = 31 and the label comes from elabel (or is
-  // 0).  Packing halves the streamed bytes per entry.
+  // gcol[e] = (label << rbits) | rank when labels are packed (rbits < 31);
+  // otherwise rbits = 31 and the label comes from elabel (SEP) or is 0.
+  // Packing halves the streamed bytes per entry.
   u32 rbits;
   __device__ inline u32 pmask() const { return pb >= 31 ? 0x7FFFFFFFu : (1u << pb) - 1u; }
   // (label, rank of the target) of entry e; streamed arrays are read
   // non-temporally so they do not evict the gather targets from the L2
   __device__ inline void entry(int64_t e, u32 &l, u32 &r) const {
     const u32 g = (u32)__builtin_nontemporal_load(&gcol[e]);
-    l = elabel ? (u32)__builtin_nontemporal_load(&elabel[e]) : (g >> rbits);
+    if constexpr (SEP) l = (u32)__builtin_nontemporal_load(&elabel[e]);
+    else l = g >> rbits;
     r = g & ((1u << rbits) - 1u);
   }
-  // entry() for first + min(t + u*STRIDE, count - 1), u < U, with the label
-  // branch taken once, so all the streamed words are requested together
+  // entry() for first + min(t + u*STRIDE, count - 1), u < U: all the
+  // streamed words are requested together, with no branch among them
   template <int U, int STRIDE>
   __device__ inline void entries(int64_t first, int t, int count, u32 (&l)[U], u32 (&r)[U]) const {
     const u32 rm = (1u << rbits) - 1u;
-    if (elabel) {
+    if constexpr (SEP) {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int64_t e = first + min(t + u * STRIDE, count - 1);
@@ -181,11 +188,15 @@ struct GraphSrc {
 };
 
 struct LabelSrc {
+  static constexpr bool GRAPH = false;
   const int64_t *ptr;  // may be null: one label per vertex
   const int32_t *lab;
   const int32_t *gid;  // may be null; in a batch, the graph of each vertex (P0 never joins graphs)
   __device__ inline int64_t begin(int v) const { return ptr ? ptr[v] : (int64_t)v; }
   __device__ inline int64_t end(int v) const { return ptr ? ptr[v + 1] : (int64_t)v + 1; }
+  __device__ inline u32 begin_lo(int v) const {
+    return ptr ? reinterpret_cast<const u32 *>(ptr)[2 * (int64_t)v] : (u32)v;
+  }
   __device__ inline u64 pair(int64_t e) const { return (u64)(u32)lab[e]; }
   __device__ inline void entry(int64_t e, u32 &l, u32 &r) const {
     l = (u32)lab[e];
@@ -387,9 +398,13 @@ __global__ void k_validate_vals(int64_t cnt, const int32_t *__restrict__ vals, i
 }
 
 // ---------------------------------------------------------------- signature tiers
-// A run of consecutive vertices [v0, v1) handled by one workgroup.
+// A run of consecutive vertices [v0, v1) handled by one workgroup, with the
+// run's first entry e0 and its entry count ne, so that a workgroup requests
+// its entries without waiting for the row offsets.
 struct Range {
   int v0, v1;
+  int ne, pad;
+  int64_t e0;
 };
 
 __device__ inline u64 scale_to(u32 a, u64 n) { return __umul64hi(((u64)a) << 32, n); }
@@ -457,11 +472,30 @@ __global__ void __launch_bounds__(256) k_sig_range(Src src, const Range *__restr
   const Range rg = ranges[blockIdx.x];
   const int V = rg.v1 - rg.v0;
   const bool single = V == 1;
-  const int64_t eb = src.begin(rg.v0);
-  for (int i = t; i <= V; i += 256) roff[i] = (int)(src.begin(rg.v0 + i) - eb);
-  // this thread's vertex (V <= blockDim): its previous block, fetched with
-  // the row offsets so the epilogue does not wait for it
+  const int64_t eb = rg.e0;
+  // The addresses of the row offsets, this thread's previous block (V <=
+  // blockDim) and the streamed words need only the range, so all three are
+  // requested together; the gathers follow, and the offsets reach LDS last.
+  const u32 b0 = t <= V ? src.begin_lo(rg.v0 + t) : 0u;
+  const u32 b1 = t + 256 <= V ? src.begin_lo(rg.v0 + t + 256) : 0u;
   const u32 own_t = t < V ? src.own(rg.v0 + t) : 0u;
+  u32 el[U], er[U];
+  if constexpr (!SKIP)
+    if (rg.ne > 0) src.template entries<U, 256>(eb, t, rg.ne, el, er);
+  K pr[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) pr[u] = KO::EMPTY;
+  if constexpr (!SKIP) {
+    if (rg.ne > 0) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const K p = KO::from(src, el[u], er[u]);
+        pr[u] = t + u * 256 < rg.ne ? p : KO::EMPTY;
+      }
+    }
+  }
+  if (t <= V) roff[t] = (int)(b0 - (u32)eb);
+  if (t + 256 <= V) roff[t + 256] = (int)(b1 - (u32)eb);
   for (int i = t; i < V; i += 256) {
     acc[i] = 0;
     cnt[i] = 0;
@@ -488,15 +522,6 @@ __global__ void __launch_bounds__(256) k_sig_range(Src src, const Range *__restr
   if (!single)
     for (int i = t; i < V; i += 256)
       if (off[i + 1] > off[i]) owner[off[i]] = (unsigned char)i;
-  K pr[U];
-  if constexpr (!SKIP) {
-    if (E > 0) {
-      load_keys<K, U, 256>(src, eb, t, E, pr);
-    } else {
-#pragma unroll
-      for (int u = 0; u < U; ++u) pr[u] = KO::EMPTY;
-    }
-  }
   __syncthreads();
   if (!single) {
     constexpr int PER = EMAX / 256;
@@ -658,11 +683,12 @@ __global__ void __launch_bounds__(NT) k_sig_row(Src src, const Range *__restrict
   __shared__ u64 sh_acc[NT / WAVE];
   __shared__ u32 sh_cnt[NT / WAVE];
   const int t = threadIdx.x;
-  const int v = rows[blockIdx.x].v0;
+  const Range rw = rows[blockIdx.x];
+  const int v = rw.v0;
   if (skip && skip[v]) return;  // singleton block (work-efficient mode)
-  const int64_t eb = src.begin(v);
+  const int64_t eb = rw.e0;
   const u32 own0 = t == 0 ? src.own(v) : 0u;  // fetched early, used by thread 0 at the end
-  const int E = (int)(src.end(v) - eb);
+  const int E = rw.ne;
   for (int i = t; i < 2 * E; i += NT) set[i] = KO::EMPTY;
   K pr[U];
   if (E > 0) {
@@ -1666,7 +1692,8 @@ __global__ void k_copy16(uint4 *__restrict__ dst, const uint4 *__restrict__ src,
 // random 4-byte gather), and nothing else.  Measures the random-gather rate
 // the signature kernels are bounded by; one value per workgroup is written so
 // the loads cannot be dropped.
-__global__ void __launch_bounds__(256) k_gather_probe(GraphSrc src, int64_t m, u32 *out, u32 omask) {
+template <class Src>
+__global__ void __launch_bounds__(256) k_gather_probe(Src src, int64_t m, u32 *out, u32 omask) {
   u32 acc = 0;
   constexpr int U = 4;
   for (int64_t base = (int64_t)blockIdx.x * 256 * U; base < m; base += (int64_t)gridDim.x * 256 * U) {
