@@ -54,7 +54,7 @@ struct Plan {
   size_t off_H, off_DC, off_rep, off_p0, off_vlist, off_clA, off_clB, off_ranges, off_lists, off_gcol, off_rank,
       off_gpid, off_zrep;
   size_t off_table, off_ctable, off_hacc, off_hcnt, off_chunks, off_parts, off_gchunks, off_poff;
-  size_t off_status, off_counters, off_dcounts, off_err, off_dep, off_hubsets, off_single, off_multi;
+  size_t off_status, off_counters, off_dcounts, off_err, off_dep, off_hubsets, off_single, off_multi, off_nzv;
   size_t off_gid, off_ibuf, off_first, off_next, off_bcounts;  // batches only
   uint64_t tslots;
   int64_t max_ranges, max_lists, nhub_max, nchunk_max, npart_max, ngchunk_max, npoff_max, ntiles, hubset_slots;
@@ -117,6 +117,7 @@ Plan make_plan(int64_t n, int64_t m, int64_t nl, int kmax, int64_t num_graphs) {
   p.off_hubsets = take(8 * (size_t)p.hubset_slots);
   p.off_single = take(2 * N);
   p.off_multi = take(4 * N);
+  p.off_nzv = take(4 * N);
   if (num_graphs > 0) {
     p.off_gid = take(4 * N);
     p.off_ibuf = take(8 * N);
@@ -139,6 +140,7 @@ struct Schedule {
   int nchunks = 0, nparts = 0, ngchunks = 0;
   int64_t gset_begin = 0, gset_end = 0;  // global hash sets of very large hubs
   int64_t nonempty = 0;                   // rows with at least one entry
+  const int *nzv = nullptr;               // their vertices in order (graph rows), or null
   int64_t info[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // vertices, entries per tier
 };
 
@@ -171,7 +173,7 @@ struct kbisim_ctx {
   char *ws;
   u64 *H, *table, *ctable, *hacc, *hubsets, *zrep;
   u32 *DC, *hcnt, *err, *tiles, *dep;
-  int *rep, *p0, *vlist, *clA, *clB, *lists, *counters, *poff, *gcol, *rank, *gpid[2];
+  int *rep, *p0, *vlist, *clA, *clB, *lists, *counters, *poff, *gcol, *rank, *gpid[2], *nzv;
   int64_t *dcounts;
   Range *ranges;
   HubChunk *chunks;
@@ -315,6 +317,27 @@ int hub_parts_for(const Tuning &t, int64_t d) {
   int P = 1;
   while ((int64_t)P * t.hub_part_target < d && P < HUB_PMAX) P <<= 1;
   return P;
+}
+
+// The vertices with at least one entry, in order, into c->nzv (s.nzv then
+// points there): flags, the head scan of the numbering, and a scatter.  Uses
+// rep and vlist as scratch.
+int build_nonempty_list(kbisim_ctx *c, Schedule &s) {
+  const int n = (int)c->g.n;
+  if (n == 0) return 0;
+  k_mark_rows<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, c->g.row_ptr, c->rep);
+  LAUNCH_CHECK();
+  const int ntiles = (int)blocks_for(n, SCAN_TILE);
+  k_tile_count<<<(unsigned)ntiles, 256, 0, c->stream>>>(n, c->rep, c->tiles);
+  LAUNCH_CHECK();
+  k_tile_scan<<<1, 1024, 0, c->stream>>>(ntiles, c->tiles, c->dcounts + (c->plan.ncounter_steps - 1));
+  LAUNCH_CHECK();
+  k_scan_write<<<(unsigned)ntiles, 256, 0, c->stream>>>(n, c->rep, c->tiles, c->vlist, ((uintptr_t)c->vlist & 15) == 0);
+  LAUNCH_CHECK();
+  k_list_from_ids<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, c->vlist, c->nzv);
+  LAUNCH_CHECK();
+  s.nzv = c->nzv;
+  return 0;
 }
 
 // Build the static schedule of the rows of `ptr` (NULL: every row has one
@@ -504,6 +527,7 @@ int build_schedule(kbisim_ctx *c, const int64_t *ptr, Schedule &s, int64_t row_m
   s.ngchunks = (int)gchunks.size();
   if (!ranges.empty())
     HIP_TRY(hipMemcpyAsync(c->ranges, ranges.data(), sizeof(Range) * ranges.size(), hipMemcpyHostToDevice, c->stream));
+
   if (!hubs.empty())
     HIP_TRY(hipMemcpyAsync(c->lists, hubs.data(), 4 * hubs.size(), hipMemcpyHostToDevice, c->stream));
   if (!chunks.empty())
@@ -718,7 +742,12 @@ int run_step(kbisim_ctx *c, const Src &src, const Schedule &s, int *out, int64_t
   }
   {
     ProfScope ps(c, KBISIM_K_LOOKUP);
-    k_lookup<Src><<<blocks_for(n, 256), 256, 0, c->stream>>>(src, n, c->H, c->DC, c->table, tmask, c->dep, c->rep,
+    // after a call's first step only vertices with edges can change their
+    // representative (the others keep the one of that step)
+    const bool listed = !zfresh && s.nzv != nullptr;
+    const int count = listed ? (int)s.nonempty : n;
+    k_lookup<Src><<<blocks_for(std::max(count, 1), 256), 256, 0, c->stream>>>(
+        src, count, listed ? s.nzv : nullptr, c->H, c->DC, c->table, tmask, c->dep, c->rep,
                                                              &cnt[0], c->vlist, &cnt[1], c->clA, c->err, c->zrep,
                                                              zfresh ? 1 : 0, skip_in);
     LAUNCH_CHECK();
@@ -1047,6 +1076,7 @@ int create_impl(const kbisim_graph *g, int kmax, const kbisim_tuning *tuning, vo
   c->single[0] = (unsigned char *)(w + plan.off_single);
   c->single[1] = c->single[0] + std::max<int64_t>(n, 1);
   c->multi = (u32 *)(w + plan.off_multi);
+  c->nzv = (int *)(w + plan.off_nzv);
   if (num_graphs > 0) {
     c->num_graphs = num_graphs;
     c->gid = (int *)(w + plan.off_gid);
@@ -1174,6 +1204,7 @@ int create_impl(const kbisim_graph *g, int kmax, const kbisim_tuning *tuning, vo
   }
   // Static schedule of the graph rows.
   if ((rc = build_schedule(c, g->row_ptr, c->sched, c->narrow ? ROW_MAX_NARROW : ROW_MAX))) return fail(rc);
+  if ((rc = build_nonempty_list(c, c->sched))) return fail(rc);
   c->tmask_steps = std::min<u64>(pow2_at_least(2 * (uint64_t)std::max<int64_t>(c->sched.nonempty, 1)), plan.tslots) - 1;
   *out = c;
   return KBISIM_OK;

@@ -1002,17 +1002,20 @@ __global__ void k_hub_final(Src src, const int *__restrict__ hubs, int nhub, u64
 // collision list with rep = -1.  Lists are appended with one atomic per
 // wave; they stay short, since device-wide atomics on one counter serialise.
 template <class Src>
-__global__ void __launch_bounds__(256) k_lookup(Src src, int n, const u64 *__restrict__ H,
-                                                const u32 *__restrict__ DC, const u64 *table, u64 tmask,
-                                                const u32 *__restrict__ dep, int *__restrict__ rep, int *vcount,
-                                                int *vlist, int *ccount, int *clist, u32 *err, const u64 *zrep,
-                                                int zfresh, const unsigned char *__restrict__ skip) {
+__global__ void __launch_bounds__(256) k_lookup(Src src, int count, const int *__restrict__ list,
+                                                const u64 *__restrict__ H, const u32 *__restrict__ DC,
+                                                const u64 *table, u64 tmask, const u32 *__restrict__ dep,
+                                                int *__restrict__ rep, int *vcount, int *vlist, int *ccount,
+                                                int *clist, u32 *err, const u64 *zrep, int zfresh,
+                                                const unsigned char *__restrict__ skip) {
   const u32 epoch = dep[EP_TABLE], zep = dep[EP_ZERO];
-  const int v = blockIdx.x * 256 + threadIdx.x;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const bool act = i < count;
+  const int v = act ? (list ? list[i] : i) : 0;
   bool to_verify = false, collided = false;
-  if (v < n && skip && skip[v]) {
+  if (act && skip && skip[v]) {
     rep[v] = v;  // a singleton block stays a singleton
-  } else if (v < n) {
+  } else if (act) {
     const u32 dcv = DC[v];
     if (dcv == 0) {
       // empty signature: exact grouping by previous block (without zfresh the
@@ -1311,6 +1314,19 @@ __global__ void __launch_bounds__(256) k_scan_write(int n, const int *__restrict
     for (int j = 0; j < SCAN_ITEMS; ++j)
       if (base + j < n) out[base + j] = o[j];
   }
+}
+
+// rep[v] = v for vertices with at least one entry, else -1 (heads of the
+// numbering scan, which then lists them in order).
+__global__ void k_mark_rows(int n, const int64_t *__restrict__ row_ptr, int *__restrict__ rep) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n) rep[v] = row_ptr[v + 1] > row_ptr[v] ? v : -1;
+}
+
+// list[pos[v]] = v for every v with pos[v] >= 0.
+__global__ void k_list_from_ids(int n, const int *__restrict__ pos, int *__restrict__ list) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n && pos[v] >= 0) list[pos[v]] = v;
 }
 
 // Every non-head copies its representative's id (written by k_scan_write),
