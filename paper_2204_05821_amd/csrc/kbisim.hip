@@ -319,6 +319,9 @@ int hub_parts_for(const Tuning &t, int64_t d) {
   return P;
 }
 
+// Edge labels read from their own array (not packed into gcol, and present).
+bool separate_labels(const kbisim_ctx *c) { return !c->packed && c->g.elabel != nullptr; }
+
 // The vertices with at least one entry, in order, into c->nzv (s.nzv then
 // points there): flags, the head scan of the numbering, and a scatter.  Uses
 // rep and vlist as scratch.
@@ -337,6 +340,34 @@ int build_nonempty_list(kbisim_ctx *c, Schedule &s) {
   k_list_from_ids<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, c->vlist, c->nzv);
   LAUNCH_CHECK();
   s.nzv = c->nzv;
+  return 0;
+}
+
+// Sort the entries of every single-row range and of every staged hub chunk
+// by target rank (results do not depend on the order inside a row).  Only
+// when the labels are packed into gcol or absent: separate labels would have
+// to move with their entries.
+int sort_long_rows(kbisim_ctx *c, const Schedule &s) {
+  if (separate_labels(c)) return 0;
+  u32 *g = reinterpret_cast<u32 *>(c->gcol);
+  const Range *rows = c->ranges + s.nranges;
+  if (s.nbig) {
+    k_sort_rows<RANGE_DMAX><<<(unsigned)s.nbig, 1024, 0, c->stream>>>(g, rows, c->rbits);
+    LAUNCH_CHECK();
+  }
+  if (s.nrow8) {
+    k_sort_rows<ROW_MAX><<<(unsigned)s.nrow8, 1024, 0, c->stream>>>(g, rows + s.nbig, c->rbits);
+    LAUNCH_CHECK();
+  }
+  if (s.nrow20) {
+    k_sort_rows<32768><<<(unsigned)s.nrow20, 1024, 0, c->stream>>>(g, rows + s.nbig + s.nrow8, c->rbits);
+    LAUNCH_CHECK();
+  }
+  if (s.nchunks) {
+    k_sort_hub_chunks<HUB_CHUNK><<<(unsigned)s.nchunks, 1024, 0, c->stream>>>(g, c->g.row_ptr, c->lists + s.hub_off,
+                                                                              c->chunks, c->rbits);
+    LAUNCH_CHECK();
+  }
   return 0;
 }
 
@@ -800,9 +831,6 @@ int run_step(kbisim_ctx *c, const Src &src, const Schedule &s, int *out, int64_t
   return 0;
 }
 
-// Edge labels read from their own array (not packed into gcol, and present).
-bool separate_labels(const kbisim_ctx *c) { return !c->packed && c->g.elabel != nullptr; }
-
 // Enqueue steps [i0, k) starting from partition `prev` (no host
 // synchronisation unless careful).  In a batch, step i refines into an
 // internal buffer of global ids and writes the caller's per-graph ids and
@@ -1205,6 +1233,7 @@ int create_impl(const kbisim_graph *g, int kmax, const kbisim_tuning *tuning, vo
   // Static schedule of the graph rows.
   if ((rc = build_schedule(c, g->row_ptr, c->sched, c->narrow ? ROW_MAX_NARROW : ROW_MAX))) return fail(rc);
   if ((rc = build_nonempty_list(c, c->sched))) return fail(rc);
+  if ((rc = sort_long_rows(c, c->sched))) return fail(rc);
   c->tmask_steps = std::min<u64>(pow2_at_least(2 * (uint64_t)std::max<int64_t>(c->sched.nonempty, 1)), plan.tslots) - 1;
   *out = c;
   return KBISIM_OK;

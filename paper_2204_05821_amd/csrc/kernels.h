@@ -1471,6 +1471,59 @@ __global__ void k_remap(int64_t m, const int *__restrict__ col, const int *__res
     gcol[e] = (int)g;
   }
 }
+// Order of the entries inside a row.  A signature is a set, so the kernels
+// may read a row's entries in any order; with the entries of long rows sorted
+// by target rank, the lanes of a wave gather from fewer cache lines (ranks
+// put the targets of most edges together).  Packed words (label << rbits |
+// rank) are compared with the rank on top: rot(g) = g rotated left by
+// 32 - rbits, which keeps the order of ranks and breaks ties by label.
+__device__ inline u32 rank_first(u32 g, u32 rbits) { return rbits >= 32 ? g : (g << (32 - rbits)) | (g >> rbits); }
+__device__ inline u32 rank_first_inv(u32 x, u32 rbits) { return rbits >= 32 ? x : (x >> (32 - rbits)) | (x << rbits); }
+
+// Sort words[0, len) (len <= N) by rank_first with a bitonic network over N
+// LDS slots (padding sorts last); the whole workgroup of NT threads takes part.
+template <int N, int NT>
+__device__ inline void sort_row_words(u32 *words, int len, u32 rbits, u32 *sh) {
+  for (int i = threadIdx.x; i < N; i += NT) sh[i] = i < len ? rank_first(words[i], rbits) : 0xFFFFFFFFu;
+  __syncthreads();
+  for (int k = 2; k <= N; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < N / 2; i += NT) {
+        const int lo = 2 * j * (i / j) + (i % j), hi = lo + j;  // pairs (lo, lo + j) with lo & j == 0
+        const u32 a = sh[lo], b = sh[hi];
+        const bool up = (lo & k) == 0;
+        if ((a > b) == up) {
+          sh[lo] = b;
+          sh[hi] = a;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = threadIdx.x; i < len; i += NT) words[i] = rank_first_inv(sh[i], rbits);
+}
+
+static_assert(RANGE_DMAX <= 4096 && ROW_MAX <= 8192 && ROW_MAX_NARROW <= 32768 && HUB_CHUNK <= 4096,
+              "row sort sizes");
+
+// One workgroup per single-row range of at most N entries.
+template <int N>
+__global__ void __launch_bounds__(1024) k_sort_rows(u32 *gcol, const Range *__restrict__ rows, u32 rbits) {
+  __shared__ u32 sh[N];
+  const Range r = rows[blockIdx.x];
+  sort_row_words<N, 1024>(gcol + r.e0, r.ne, rbits, sh);
+}
+
+// One workgroup per staged hub chunk (entries [b, e) of the hub's row, e - b <= N).
+template <int N>
+__global__ void __launch_bounds__(1024) k_sort_hub_chunks(u32 *gcol, const int64_t *__restrict__ row_ptr,
+                                                          const int *__restrict__ hubs,
+                                                          const HubChunk *__restrict__ chunks, u32 rbits) {
+  __shared__ u32 sh[N];
+  const HubChunk c = chunks[blockIdx.x];
+  sort_row_words<N, 1024>(gcol + row_ptr[hubs[c.hub]] + c.b, (int)(c.e - c.b), rbits, sh);
+}
+
 __global__ void k_scatter_rank(int n, const int *__restrict__ pid, const int *__restrict__ rank, int *__restrict__ gpid) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v < n) gpid[rank[v]] = pid[v];
