@@ -85,8 +85,9 @@ typedef struct kbisim_ctx kbisim_ctx;
 
 /* Launch-shape parameters chosen by an autotuner (0 = default).  Results do
  * not depend on them; only the work split does.
- *   range_edges      CSR entries per range workgroup: 1024 (default) or 2048
- *   hub_chunk        entries per hub staging workgroup: 2048 or 4096 (default)
+ *   range_edges      CSR entries per range workgroup: 1024 or 2048 (default:
+ *                    2048 with 32-bit set keys, 1024 with 64-bit keys)
+ *   hub_chunk        entries per hub staging workgroup: 2048 (default) or 4096
  *   hub_part_target  expected entries per hub partition: 1024 or 2048 (default)
  *   key_bits         width of pair keys in LDS hash sets: 32 (default; used
  *                    when every (edge label, block id) pair fits in 31 bits,

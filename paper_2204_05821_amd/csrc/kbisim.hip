@@ -132,6 +132,7 @@ Plan make_plan(int64_t n, int64_t m, int64_t nl, int kmax, int64_t num_graphs) {
 // Static degree schedule of one row structure (graph rows or label-set rows),
 // built on the host at create time; degrees never change across iterations.
 struct Schedule {
+  int range_edges = RANGE_EDGES;  // range capacity of this schedule (1024 or 2048)
   int nranges = 0;  // multi-vertex ranges (at most range_edges entries)
   int nbig = 0;     // single-row ranges of range_edges < deg <= RANGE_DMAX
   int nrow8 = 0;    // single-row ranges of RANGE_DMAX < deg <= ROW_MAX (after the nbig ones)
@@ -145,8 +146,8 @@ struct Schedule {
 };
 
 struct Tuning {
-  int range_edges = RANGE_EDGES;
-  int hub_chunk = HUB_CHUNK;
+  int range_edges = 0;  // 0: by key width (range_cap)
+  int hub_chunk = 2048;
   int hub_part_target = HUB_PART_TARGET;
   int key_bits = 0;  // LDS set keys: 0 = narrow (32-bit) where pairs fit, 64 = always 64-bit
 };
@@ -313,6 +314,13 @@ int read_err(kbisim_ctx *c, u32 *out) {
   return 0;
 }
 
+// Range capacity: the tuned one, else 2048 entries with 32-bit set keys and
+// 1024 with 64-bit keys (the larger LDS set would cost occupancy).
+int range_cap(const kbisim_ctx *c, bool wide_keys) {
+  if (c->tune.range_edges) return c->tune.range_edges;
+  return wide_keys ? 1024 : 2048;
+}
+
 int hub_parts_for(const Tuning &t, int64_t d) {
   int P = 1;
   while ((int64_t)P * t.hub_part_target < d && P < HUB_PMAX) P <<= 1;
@@ -364,7 +372,7 @@ int sort_long_rows(kbisim_ctx *c, const Schedule &s) {
     LAUNCH_CHECK();
   }
   if (s.nchunks) {
-    k_sort_hub_chunks<HUB_CHUNK><<<(unsigned)s.nchunks, 1024, 0, c->stream>>>(g, c->g.row_ptr, c->lists + s.hub_off,
+    k_sort_hub_chunks<HUB_CHUNK_MAX><<<(unsigned)s.nchunks, 1024, 0, c->stream>>>(g, c->g.row_ptr, c->lists + s.hub_off,
                                                                               c->chunks, c->rbits);
     LAUNCH_CHECK();
   }
@@ -375,10 +383,11 @@ int sort_long_rows(kbisim_ctx *c, const Schedule &s) {
 // item) on the host: runs of consecutive low-degree vertices, single-row
 // ranges, and hub chunks, partitions and staging areas.  Synchronises.
 // row_max: longest row with a workgroup of its own (longer rows are hubs).
-int build_schedule(kbisim_ctx *c, const int64_t *ptr, Schedule &s, int64_t row_max = ROW_MAX) {
+int build_schedule(kbisim_ctx *c, const int64_t *ptr, Schedule &s, int range_edges, int64_t row_max = ROW_MAX) {
   const int64_t n = c->g.n;
   const Tuning &t = c->tune;
   s = Schedule{};
+  s.range_edges = range_edges;
   std::vector<int64_t> rp;
   if (ptr && n > 0) {
     rp.resize((size_t)n + 1);
@@ -437,14 +446,14 @@ int build_schedule(kbisim_ctx *c, const int64_t *ptr, Schedule &s, int64_t row_m
         P.info[3] += d;
         continue;
       }
-      if (d > t.range_edges) {
+      if (d > range_edges) {
         close(v);
         P.big.push_back(Range{(int)v, (int)v + 1, (int)d, 0, rp[(size_t)v]});
         P.info[2] += 1;
         P.info[3] += d;
         continue;
       }
-      if (cur0 >= 0 && (cur_e + d > t.range_edges || v - cur0 == RANGE_VERTS)) close(v);
+      if (cur0 >= 0 && (cur_e + d > range_edges || v - cur0 == RANGE_VERTS)) close(v);
       if (cur0 < 0) cur0 = v;
       cur_e += d;
       P.info[0] += 1;
@@ -649,7 +658,7 @@ template <class Src, class K, bool SKIP>
 int launch_range_kernel(kbisim_ctx *c, const Src &src, const Schedule &s, u64 tmask, int zfresh,
                         const unsigned char *skip) {
   ProfScope ps(c, KBISIM_K_SIG_RANGE);
-  if (c->tune.range_edges == 1024)
+  if (s.range_edges == 1024)
     k_sig_range<Src, 1024, K, SKIP><<<(unsigned)s.nranges, 256, 0, c->stream>>>(
         src, c->ranges, c->H, c->DC, c->table, tmask, c->dep, c->hmask, c->zrep, zfresh, skip);
   else
@@ -1220,7 +1229,7 @@ int create_impl(const kbisim_graph *g, int kmax, const kbisim_tuning *tuning, vo
     Schedule ls;
     LabelSrc src{g->vlabel_ptr, g->vlabel, c->gid};
     if (!g->vlabel) src = LabelSrc{nullptr, c->gid, nullptr};  // batch without labels: one block per graph
-    if ((rc = build_schedule(c, src.ptr, ls))) return fail(rc);
+    if ((rc = build_schedule(c, src.ptr, ls, range_cap(c, true)))) return fail(rc);
     int *cnt = c->counters + CNT_STRIDE * (plan.ncounter_steps - 2);
     if ((rc = fill_i32(c, cnt, CNT_STRIDE, 0))) return fail(rc);
     int64_t *dcount = c->dcounts + (plan.ncounter_steps - 2);
@@ -1231,7 +1240,9 @@ int create_impl(const kbisim_graph *g, int kmax, const kbisim_tuning *tuning, vo
     if (err) return fail(KBISIM_EINTERNAL);
   }
   // Static schedule of the graph rows.
-  if ((rc = build_schedule(c, g->row_ptr, c->sched, c->narrow ? ROW_MAX_NARROW : ROW_MAX))) return fail(rc);
+  if ((rc = build_schedule(c, g->row_ptr, c->sched, range_cap(c, !c->narrow),
+                           c->narrow ? ROW_MAX_NARROW : ROW_MAX)))
+    return fail(rc);
   if ((rc = build_nonempty_list(c, c->sched))) return fail(rc);
   if ((rc = sort_long_rows(c, c->sched))) return fail(rc);
   c->tmask_steps = std::min<u64>(pow2_at_least(2 * (uint64_t)std::max<int64_t>(c->sched.nonempty, 1)), plan.tslots) - 1;

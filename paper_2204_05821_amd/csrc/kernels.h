@@ -41,14 +41,14 @@ typedef uint32_t u32;
 constexpr u64 EMPTY64 = ~0ULL;
 constexpr int WAVE = 64;
 constexpr int SMALL_MAX = 16;        // inline exact check limit (thread per vertex)
-constexpr int RANGE_EDGES = 1024;    // CSR entries per multi-vertex range workgroup (default)
+constexpr int RANGE_EDGES = 1024;    // CSR entries per multi-vertex range workgroup (or 2048)
 constexpr int RANGE_VERTS = 256;     // vertices per range workgroup
 constexpr int RANGE_DMAX = 4096;     // rows above RANGE_EDGES get a workgroup of 512 threads
 constexpr int ROW_MAX = 8192;        // rows above RANGE_DMAX get one of 1024 threads; above this, hubs
 constexpr int ROW_MAX_NARROW = 19456;  // with 32-bit keys rows up to this fit one workgroup's LDS (152 KB)
 constexpr int BLOCK_MAX = ROW_MAX;
 constexpr int BLOCK_SLOTS = 8192;    // LDS set slots for exact checks (64 KB)
-constexpr int HUB_CHUNK = 4096;      // default entries per hub staging workgroup (16 per thread)
+constexpr int HUB_CHUNK_MAX = 4096;  // entries per hub staging workgroup: 2048 (default) or 4096
 constexpr int HUB_PMAX = 1024;       // partitions per hub at most
 constexpr int HUB_PART_TARGET = 2048;  // expected entries per hub partition
 constexpr int HUB_PSLOTS = 8192;     // LDS set slots per hub partition workgroup
@@ -723,7 +723,7 @@ __global__ void __launch_bounds__(NT) k_sig_row(Src src, const Range *__restrict
 }
 
 // Hub tier (deg > BLOCK_MAX), two passes without per-entry global atomics.
-//  stage:  a workgroup per chunk of HUB_CHUNK entries removes duplicates
+//  stage:  a workgroup per chunk of hub_chunk entries removes duplicates
 //          inside the chunk (LDS set), splits the chunk's distinct pairs into
 //          the hub's P partitions by a partition hash and writes them,
 //          grouped by partition, to the chunk's staging area together with
@@ -735,7 +735,7 @@ struct HubChunk {
   int hub;          // index into the hub arrays
   int parts;        // partitions of this hub (power of two)
   int64_t b, e;     // entry range relative to the start of the hub's row
-  int64_t stage;    // offset of the chunk's staging area (HUB_CHUNK slots)
+  int64_t stage;    // offset of the chunk's staging area (hub_chunk slots)
   int64_t poff;     // offset of the chunk's parts+1 partition offsets
 };
 
@@ -1503,7 +1503,7 @@ __device__ inline void sort_row_words(u32 *words, int len, u32 rbits, u32 *sh) {
   for (int i = threadIdx.x; i < len; i += NT) words[i] = rank_first_inv(sh[i], rbits);
 }
 
-static_assert(RANGE_DMAX <= 4096 && ROW_MAX <= 8192 && ROW_MAX_NARROW <= 32768 && HUB_CHUNK <= 4096,
+static_assert(RANGE_DMAX <= 4096 && ROW_MAX <= 8192 && ROW_MAX_NARROW <= 32768 && HUB_CHUNK_MAX <= 4096,
               "row sort sizes");
 
 // One workgroup per single-row range of at most N entries.
