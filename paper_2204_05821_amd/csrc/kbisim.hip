@@ -351,13 +351,22 @@ int build_nonempty_list(kbisim_ctx *c, Schedule &s) {
   return 0;
 }
 
-// Sort the entries of every single-row range and of every staged hub chunk
-// by target rank (results do not depend on the order inside a row).  Only
+// Sort the entries of every row of the range and row tiers, and of every
+// staged hub chunk, by target rank (results do not depend on the order
+// inside a row).  Only
 // when the labels are packed into gcol or absent: separate labels would have
 // to move with their entries.
 int sort_long_rows(kbisim_ctx *c, const Schedule &s) {
   if (separate_labels(c)) return 0;
   u32 *g = reinterpret_cast<u32 *>(c->gcol);
+  if (s.nranges) {
+    const GraphSrcT<false> src{c->g.row_ptr, c->gcol, nullptr, nullptr, nullptr, c->pb, c->rbits};
+    if (s.range_edges == 1024)
+      k_sort_ranges<GraphSrcT<false>, 1024><<<(unsigned)s.nranges, 256, 0, c->stream>>>(src, g, c->ranges, c->rbits);
+    else
+      k_sort_ranges<GraphSrcT<false>, 2048><<<(unsigned)s.nranges, 256, 0, c->stream>>>(src, g, c->ranges, c->rbits);
+    LAUNCH_CHECK();
+  }
   const Range *rows = c->ranges + s.nranges;
   if (s.nbig) {
     k_sort_rows<RANGE_DMAX><<<(unsigned)s.nbig, 1024, 0, c->stream>>>(g, rows, c->rbits);

@@ -1506,6 +1506,51 @@ __device__ inline void sort_row_words(u32 *words, int len, u32 rbits, u32 *sh) {
 static_assert(RANGE_DMAX <= 4096 && ROW_MAX <= 8192 && ROW_MAX_NARROW <= 32768 && HUB_CHUNK_MAX <= 4096,
               "row sort sizes");
 
+// One workgroup of 256 threads per range of at most N entries: each row of
+// the range sorted by rank_first in place.  Keys (row << 32 | rank_first) in
+// a bitonic network over N LDS slots; the row of an entry is found by
+// binary search over the range's row offsets.
+template <class Src, int N>
+__global__ void __launch_bounds__(256) k_sort_ranges(Src src, u32 *gcol, const Range *__restrict__ ranges,
+                                                     u32 rbits) {
+  __shared__ u64 sh[N];
+  __shared__ int roff[RANGE_VERTS + 1];
+  const Range rg = ranges[blockIdx.x];
+  const int V = rg.v1 - rg.v0, E = rg.ne;
+  u32 *words = gcol + rg.e0;
+  for (int i = threadIdx.x; i <= V; i += 256) roff[i] = (int)(src.begin_lo(rg.v0 + i) - (u32)rg.e0);
+  __syncthreads();
+  for (int i = threadIdx.x; i < N; i += 256) {
+    u64 key = ~0ULL;
+    if (i < E) {
+      int lo = 0, hi = V - 1;  // last row whose start is <= i
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (roff[mid] <= i) lo = mid;
+        else hi = mid - 1;
+      }
+      key = ((u64)lo << 32) | rank_first(words[i], rbits);
+    }
+    sh[i] = key;
+  }
+  __syncthreads();
+  for (int k = 2; k <= N; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < N / 2; i += 256) {
+        const int lo = 2 * j * (i / j) + (i % j), hi = lo + j;
+        const u64 a = sh[lo], b = sh[hi];
+        const bool up = (lo & k) == 0;
+        if ((a > b) == up) {
+          sh[lo] = b;
+          sh[hi] = a;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = threadIdx.x; i < E; i += 256) words[i] = rank_first_inv((u32)sh[i], rbits);
+}
+
 // One workgroup per single-row range of at most N entries.
 template <int N>
 __global__ void __launch_bounds__(1024) k_sort_rows(u32 *gcol, const Range *__restrict__ rows, u32 rbits) {
