@@ -101,11 +101,13 @@ def test_batch_style_graphs():
 # ------------------------------------------------------------------ degree tiers
 
 def tier_graph(seed=3, labels=3, shared_targets=50):
-    """Vertices at every tier boundary (0,1,15-17,63-65,511-513,4095-4097, hubs up to 3 chunks),
+    """Vertices at every tier boundary (0, 1, 15-17, 63-65, 511-513, the range capacities 1023-1025 and
+    2047-2049, 4095-4097, 8191-8193, the 32-bit-key row limit 19455-19457, hubs up to 3 chunks),
     with few labels and targets so rows are full of duplicates, plus twin rows so the
     large-row exact check finds matches."""
     rng = np.random.default_rng(seed)
-    degs = [0, 1, 2, 15, 16, 17, 63, 64, 65, 511, 512, 513, 1000, 4095, 4096, 4097, 8191, 8192, 8193, 20000]
+    degs = [0, 1, 2, 15, 16, 17, 63, 64, 65, 511, 512, 513, 1000, 1023, 1024, 1025, 2047, 2048, 2049, 4095, 4096,
+            4097, 8191, 8192, 8193, 19455, 19456, 19457, 20000]
     n_small = 3000
     n = len(degs) * 2 + n_small
     src, dst, lbl = [], [], []
