@@ -17,6 +17,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <thread>
 #include <type_traits>
@@ -388,6 +389,73 @@ int sort_long_rows(kbisim_ctx *c, const Schedule &s) {
   return 0;
 }
 
+// Host copies of row-offset arrays for schedule building.  Fresh host pages
+// cost more to map than the copy itself, so buffers (pinned when possible)
+// go back to a process-wide pool and serve later creates.  The pool holds at
+// most as many buffers as schedules were built at once; it is never freed.
+struct HostRows {
+  int64_t *p = nullptr;
+  size_t cap = 0;
+  bool pinned = false;
+};
+std::mutex &host_rows_mu() {
+  static std::mutex *m = new std::mutex();
+  return *m;
+}
+std::vector<HostRows> &host_rows_pool() {
+  static std::vector<HostRows> *v = new std::vector<HostRows>();
+  return *v;
+}
+void host_rows_free(HostRows &b) {
+  if (!b.p) return;
+  if (b.pinned) (void)hipHostFree(b.p);
+  else delete[] b.p;
+  b = HostRows{};
+}
+// A buffer of at least cnt entries (p null if none could be had).
+HostRows host_rows_take(size_t cnt) {
+  HostRows old{};
+  {
+    std::lock_guard<std::mutex> lk(host_rows_mu());
+    auto &pool = host_rows_pool();
+    size_t best = pool.size();
+    for (size_t i = 0; i < pool.size(); ++i)
+      if (pool[i].cap >= cnt && (best == pool.size() || pool[i].cap < pool[best].cap)) best = i;
+    if (best < pool.size()) {
+      HostRows b = pool[best];
+      pool.erase(pool.begin() + (std::ptrdiff_t)best);
+      return b;
+    }
+    if (!pool.empty()) {  // replace the largest (too small) buffer
+      size_t big = 0;
+      for (size_t i = 1; i < pool.size(); ++i)
+        if (pool[i].cap > pool[big].cap) big = i;
+      old = pool[big];
+      pool.erase(pool.begin() + (std::ptrdiff_t)big);
+    }
+  }
+  host_rows_free(old);
+  HostRows b;
+  void *q = nullptr;
+  if (hipHostMalloc(&q, 8 * cnt, hipHostMallocDefault) == hipSuccess) {
+    b.p = static_cast<int64_t *>(q);
+    b.pinned = true;
+  } else {
+    (void)hipGetLastError();
+    b.p = new (std::nothrow) int64_t[cnt];
+  }
+  b.cap = b.p ? cnt : 0;
+  return b;
+}
+struct HostRowsLease {
+  HostRows b;
+  ~HostRowsLease() {
+    if (!b.p) return;
+    std::lock_guard<std::mutex> lk(host_rows_mu());
+    host_rows_pool().push_back(b);
+  }
+};
+
 // Build the static schedule of the rows of `ptr` (NULL: every row has one
 // item) on the host: runs of consecutive low-degree vertices, single-row
 // ranges, and hub chunks, partitions and staging areas.  Synchronises.
@@ -397,11 +465,14 @@ int build_schedule(kbisim_ctx *c, const int64_t *ptr, Schedule &s, int range_edg
   const Tuning &t = c->tune;
   s = Schedule{};
   s.range_edges = range_edges;
-  std::vector<int64_t> rp;
+  HostRowsLease lease;
+  const int64_t *rp = nullptr;
   if (ptr && n > 0) {
-    rp.resize((size_t)n + 1);
-    HIP_TRY(hipMemcpyAsync(rp.data(), ptr, 8 * (size_t)(n + 1), hipMemcpyDeviceToHost, c->stream));
+    lease.b = host_rows_take((size_t)n + 1);
+    if (!lease.b.p) return KBISIM_EINTERNAL;
+    HIP_TRY(hipMemcpyAsync(lease.b.p, ptr, 8 * (size_t)(n + 1), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
+    rp = lease.b.p;
   }
   // Degree tiers.  Rows are packed greedily into ranges of consecutive
   // vertices; the vertex sequence is cut into SCHED_CHUNKS fixed chunks that
@@ -608,7 +679,8 @@ int build_rank(kbisim_ctx *c) {
   int rc = fill_i32(c, indeg, n, 0);
   if (rc) return rc;
   if (m > 0) {
-    k_indegree<<<(unsigned)std::min<int64_t>(blocks_for(m, 256), 1 << 16), 256, 0, c->stream>>>(m, c->g.col, indeg);
+    k_indegree<<<(unsigned)std::min<int64_t>(blocks_for(m, INDEG_CHUNK), 1 << 16), 256, 0, c->stream>>>(m, c->g.col,
+                                                                                                       indeg);
     LAUNCH_CHECK();
   }
   u64 *ka = c->table, *kb = c->table + n;  // 8 * tslots >= 16 n bytes
@@ -1614,7 +1686,7 @@ int kbisim_transpose(int64_t n, int64_t m, const int64_t *row_ptr, const int32_t
   HIP_TRY(hipStreamSynchronize(s));
   if (bad) return KBISIM_EGRAPH;
   k_fill_i32<<<blocks_for(n, 256), 256, 0, s>>>(cnt, n, 0);
-  if (m > 0) k_indegree<<<(unsigned)std::min<int64_t>(blocks_for(m, 256), 65536), 256, 0, s>>>(m, col, cnt);
+  if (m > 0) k_indegree<<<(unsigned)std::min<int64_t>(blocks_for(m, INDEG_CHUNK), 65536), 256, 0, s>>>(m, col, cnt);
   k_sum_tiles64<<<(unsigned)p.ntiles, 256, 0, s>>>(n, cnt, tiles);
   k_scan_tiles64<<<1, 256, 0, s>>>(p.ntiles, tiles);
   k_write_ptr64<<<(unsigned)p.ntiles, 256, 0, s>>>(n, cnt, tiles, out_row_ptr, cursor);

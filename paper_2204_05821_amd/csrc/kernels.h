@@ -1457,9 +1457,38 @@ __global__ void __launch_bounds__(256) k_transpose_scatter(int64_t n, const int6
   }
 }
 
-__global__ void k_indegree(int64_t m, const int *__restrict__ col, int *indeg) {
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x)
-    atomicAdd(&indeg[col[e]], 1);
+// Entries per target.  A workgroup counts a chunk of INDEG_CHUNK entries in
+// an LDS table (target -> count), then adds one device atomic per distinct
+// target, so the many entries of a hot target do not serialise on one
+// address across the device.  indeg starts at zero; 256 threads.
+constexpr int INDEG_CHUNK = 2048, INDEG_SLOTS = 4096;
+__global__ void __launch_bounds__(256) k_indegree(int64_t m, const int *__restrict__ col, int *indeg) {
+  __shared__ int key[INDEG_SLOTS];
+  __shared__ int val[INDEG_SLOTS];
+  for (int64_t base = (int64_t)blockIdx.x * INDEG_CHUNK; base < m; base += (int64_t)gridDim.x * INDEG_CHUNK) {
+    for (int i = threadIdx.x; i < INDEG_SLOTS; i += 256) {
+      key[i] = -1;
+      val[i] = 0;
+    }
+    __syncthreads();
+    const int cnt = (int)min<int64_t>(m - base, INDEG_CHUNK);
+    for (int i = threadIdx.x; i < cnt; i += 256) {
+      const int c = col[base + i];
+      u32 sl = ((u32)c * 0x9E3779B1u) >> 20;  // 12 bits: INDEG_SLOTS
+      while (true) {
+        const int old = atomicCAS(&key[sl], -1, c);
+        if (old == -1 || old == c) {
+          atomicAdd(&val[sl], 1);
+          break;
+        }
+        sl = (sl + 1) & (INDEG_SLOTS - 1);
+      }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < INDEG_SLOTS; i += 256)
+      if (key[i] >= 0) atomicAdd(&indeg[key[i]], val[i]);
+    __syncthreads();
+  }
 }
 // gcol[e] = rank[col[e]], with the entry's label in the bits above rbits
 // when elabel is given (packed form).
