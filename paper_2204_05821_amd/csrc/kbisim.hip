@@ -194,6 +194,7 @@ struct kbisim_ctx {
   u32 max_label = 0;    // largest edge label (0 without labels)
   bool packed = false;  // edge labels packed above the target ranks in gcol
   u32 rbits = 31;       // bits of the target rank in gcol
+  int32_t *glab = nullptr;  // separate labels in the order of the sorted rows (else the caller's)
   int64_t p0_count = 0;
   // batches
   int64_t num_graphs = 0;
@@ -330,6 +331,8 @@ int hub_parts_for(const Tuning &t, int64_t d) {
 
 // Edge labels read from their own array (not packed into gcol, and present).
 bool separate_labels(const kbisim_ctx *c) { return !c->packed && c->g.elabel != nullptr; }
+// The separate labels the kernels read: the rank-sorted copy, if made.
+const int32_t *sep_labels(const kbisim_ctx *c) { return c->glab ? c->glab : c->g.elabel; }
 
 // The vertices with at least one entry, in order, into c->nzv (s.nzv then
 // points there): flags, the head scan of the numbering, and a scatter.  Uses
@@ -354,39 +357,55 @@ int build_nonempty_list(kbisim_ctx *c, Schedule &s) {
 
 // Sort the entries of every row of the range and row tiers, and of every
 // staged hub chunk, by target rank (results do not depend on the order
-// inside a row).  Only
-// when the labels are packed into gcol or absent: separate labels would have
-// to move with their entries.
-int sort_long_rows(kbisim_ctx *c, const Schedule &s) {
-  if (separate_labels(c)) return 0;
+// inside a row).  Separate edge labels move with their entries, in a copy
+// kept in the unused tail of the hub staging region; when the tail is too
+// small, such graphs stay unsorted.  PAY: that copy is in use.
+template <bool PAY>
+int sort_rows_impl(kbisim_ctx *c, const Schedule &s, u32 *lab) {
   u32 *g = reinterpret_cast<u32 *>(c->gcol);
   if (s.nranges) {
     const GraphSrcT<false> src{c->g.row_ptr, c->gcol, nullptr, nullptr, nullptr, c->pb, c->rbits};
     if (s.range_edges == 1024)
-      k_sort_ranges<GraphSrcT<false>, 1024><<<(unsigned)s.nranges, 256, 0, c->stream>>>(src, g, c->ranges, c->rbits);
+      k_sort_ranges<GraphSrcT<false>, 1024, PAY><<<(unsigned)s.nranges, 256, 0, c->stream>>>(src, g, lab, c->ranges,
+                                                                                           c->rbits);
     else
-      k_sort_ranges<GraphSrcT<false>, 2048><<<(unsigned)s.nranges, 256, 0, c->stream>>>(src, g, c->ranges, c->rbits);
+      k_sort_ranges<GraphSrcT<false>, 2048, PAY><<<(unsigned)s.nranges, 256, 0, c->stream>>>(src, g, lab, c->ranges,
+                                                                                           c->rbits);
     LAUNCH_CHECK();
   }
   const Range *rows = c->ranges + s.nranges;
   if (s.nbig) {
-    k_sort_rows<RANGE_DMAX><<<(unsigned)s.nbig, 1024, 0, c->stream>>>(g, rows, c->rbits);
+    k_sort_rows<RANGE_DMAX, PAY><<<(unsigned)s.nbig, 1024, 0, c->stream>>>(g, lab, rows, c->rbits);
     LAUNCH_CHECK();
   }
   if (s.nrow8) {
-    k_sort_rows<ROW_MAX><<<(unsigned)s.nrow8, 1024, 0, c->stream>>>(g, rows + s.nbig, c->rbits);
+    k_sort_rows<ROW_MAX, PAY><<<(unsigned)s.nrow8, 1024, 0, c->stream>>>(g, lab, rows + s.nbig, c->rbits);
     LAUNCH_CHECK();
   }
-  if (s.nrow20) {
-    k_sort_rows<32768><<<(unsigned)s.nrow20, 1024, 0, c->stream>>>(g, rows + s.nbig + s.nrow8, c->rbits);
-    LAUNCH_CHECK();
+  if constexpr (!PAY) {  // rows beyond 8192 entries (32-bit keys): no LDS room for the labels
+    if (s.nrow20) {
+      k_sort_rows<32768, false><<<(unsigned)s.nrow20, 1024, 0, c->stream>>>(g, nullptr, rows + s.nbig + s.nrow8,
+                                                                          c->rbits);
+      LAUNCH_CHECK();
+    }
   }
   if (s.nchunks) {
-    k_sort_hub_chunks<HUB_CHUNK_MAX><<<(unsigned)s.nchunks, 1024, 0, c->stream>>>(g, c->g.row_ptr, c->lists + s.hub_off,
-                                                                              c->chunks, c->rbits);
+    k_sort_hub_chunks<HUB_CHUNK_MAX, PAY><<<(unsigned)s.nchunks, 1024, 0, c->stream>>>(
+        g, lab, c->g.row_ptr, c->lists + s.hub_off, c->chunks, c->rbits);
     LAUNCH_CHECK();
   }
   return 0;
+}
+
+int sort_long_rows(kbisim_ctx *c, const Schedule &s) {
+  if (!separate_labels(c)) return sort_rows_impl<false>(c, s, nullptr);
+  const int64_t m = c->g.m;
+  const int64_t need = (m + 1) / 2 + 1;  // u64 slots for m int32 labels
+  if (m == 0 || s.gset_end + need > c->plan.hubset_slots) return 0;
+  int32_t *lab = reinterpret_cast<int32_t *>(c->hubsets + (c->plan.hubset_slots - need));
+  HIP_TRY(hipMemcpyAsync(lab, c->g.elabel, 4 * (size_t)m, hipMemcpyDeviceToDevice, c->stream));
+  c->glab = lab;
+  return sort_rows_impl<true>(c, s, reinterpret_cast<u32 *>(lab));
 }
 
 // Host copies of row-offset arrays for schedule building.  Fresh host pages
@@ -947,7 +966,7 @@ int enqueue_steps(kbisim_ctx *c, const int32_t *prev, int i0, int k, int32_t *co
                       c->gpid[(i + 1) & 1], i == 0, skip_in, single_out);
     };
     if (separate_labels(c))
-      rc = step(GraphSrcT<true>{c->g.row_ptr, c->gcol, c->g.elabel, c->gpid[i & 1], prev, c->pb, c->rbits});
+      rc = step(GraphSrcT<true>{c->g.row_ptr, c->gcol, sep_labels(c), c->gpid[i & 1], prev, c->pb, c->rbits});
     else
       rc = step(GraphSrcT<false>{c->g.row_ptr, c->gcol, nullptr, c->gpid[i & 1], prev, c->pb, c->rbits});
     if (rc) return rc;
@@ -1531,7 +1550,7 @@ int kbisim_gather_probe(kbisim_ctx *c, const int32_t *pid, int reps, double *ms)
   if (rc) return rc;
   // the probe reads the same gather index and pairs as the signature kernels
   const unsigned grid = (unsigned)std::min<int64_t>((m + 1023) / 1024, 1 << 20);
-  const GraphSrcT<true> sep{c->g.row_ptr, c->gcol, c->g.elabel, c->gpid[0], pid, c->pb, c->rbits};
+  const GraphSrcT<true> sep{c->g.row_ptr, c->gcol, sep_labels(c), c->gpid[0], pid, c->pb, c->rbits};
   const GraphSrcT<false> pk{c->g.row_ptr, c->gcol, nullptr, c->gpid[0], pid, c->pb, c->rbits};
   const bool s2 = separate_labels(c);
   auto probe = [&]() {

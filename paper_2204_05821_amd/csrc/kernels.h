@@ -1510,10 +1510,14 @@ __device__ inline u32 rank_first(u32 g, u32 rbits) { return rbits >= 32 ? g : (g
 __device__ inline u32 rank_first_inv(u32 x, u32 rbits) { return rbits >= 32 ? x : (x >> (32 - rbits)) | (x << rbits); }
 
 // Sort words[0, len) (len <= N) by rank_first with a bitonic network over N
-// LDS slots (padding sorts last); the whole workgroup of NT threads takes part.
-template <int N, int NT>
-__device__ inline void sort_row_words(u32 *words, int len, u32 rbits, u32 *sh) {
-  for (int i = threadIdx.x; i < N; i += NT) sh[i] = i < len ? rank_first(words[i], rbits) : 0xFFFFFFFFu;
+// LDS slots (padding sorts last); the whole workgroup of NT threads takes
+// part.  PAY: labels[0, len) (separate edge labels) move with their words.
+template <int N, int NT, bool PAY>
+__device__ inline void sort_row_words(u32 *words, u32 *labels, int len, u32 rbits, u32 *sh, u32 *shl) {
+  for (int i = threadIdx.x; i < N; i += NT) {
+    sh[i] = i < len ? rank_first(words[i], rbits) : 0xFFFFFFFFu;
+    if constexpr (PAY) shl[i] = i < len ? labels[i] : 0u;
+  }
   __syncthreads();
   for (int k = 2; k <= N; k <<= 1) {
     for (int j = k >> 1; j > 0; j >>= 1) {
@@ -1524,12 +1528,20 @@ __device__ inline void sort_row_words(u32 *words, int len, u32 rbits, u32 *sh) {
         if ((a > b) == up) {
           sh[lo] = b;
           sh[hi] = a;
+          if constexpr (PAY) {
+            const u32 t = shl[lo];
+            shl[lo] = shl[hi];
+            shl[hi] = t;
+          }
         }
       }
       __syncthreads();
     }
   }
-  for (int i = threadIdx.x; i < len; i += NT) words[i] = rank_first_inv(sh[i], rbits);
+  for (int i = threadIdx.x; i < len; i += NT) {
+    words[i] = rank_first_inv(sh[i], rbits);
+    if constexpr (PAY) labels[i] = shl[i];
+  }
 }
 
 static_assert(RANGE_DMAX <= 4096 && ROW_MAX <= 8192 && ROW_MAX_NARROW <= 32768 && HUB_CHUNK_MAX <= 4096,
@@ -1539,14 +1551,16 @@ static_assert(RANGE_DMAX <= 4096 && ROW_MAX <= 8192 && ROW_MAX_NARROW <= 32768 &
 // the range sorted by rank_first in place.  Keys (row << 32 | rank_first) in
 // a bitonic network over N LDS slots; the row of an entry is found by
 // binary search over the range's row offsets.
-template <class Src, int N>
-__global__ void __launch_bounds__(256) k_sort_ranges(Src src, u32 *gcol, const Range *__restrict__ ranges,
+template <class Src, int N, bool PAY>
+__global__ void __launch_bounds__(256) k_sort_ranges(Src src, u32 *gcol, u32 *labels, const Range *__restrict__ ranges,
                                                      u32 rbits) {
   __shared__ u64 sh[N];
+  __shared__ u32 shl[PAY ? N : 1];
   __shared__ int roff[RANGE_VERTS + 1];
   const Range rg = ranges[blockIdx.x];
   const int V = rg.v1 - rg.v0, E = rg.ne;
   u32 *words = gcol + rg.e0;
+  u32 *labs = PAY ? labels + rg.e0 : nullptr;
   for (int i = threadIdx.x; i <= V; i += 256) roff[i] = (int)(src.begin_lo(rg.v0 + i) - (u32)rg.e0);
   __syncthreads();
   for (int i = threadIdx.x; i < N; i += 256) {
@@ -1561,6 +1575,7 @@ __global__ void __launch_bounds__(256) k_sort_ranges(Src src, u32 *gcol, const R
       key = ((u64)lo << 32) | rank_first(words[i], rbits);
     }
     sh[i] = key;
+    if constexpr (PAY) shl[i] = i < E ? labs[i] : 0u;
   }
   __syncthreads();
   for (int k = 2; k <= N; k <<= 1) {
@@ -1572,30 +1587,42 @@ __global__ void __launch_bounds__(256) k_sort_ranges(Src src, u32 *gcol, const R
         if ((a > b) == up) {
           sh[lo] = b;
           sh[hi] = a;
+          if constexpr (PAY) {
+            const u32 t = shl[lo];
+            shl[lo] = shl[hi];
+            shl[hi] = t;
+          }
         }
       }
       __syncthreads();
     }
   }
-  for (int i = threadIdx.x; i < E; i += 256) words[i] = rank_first_inv((u32)sh[i], rbits);
+  for (int i = threadIdx.x; i < E; i += 256) {
+    words[i] = rank_first_inv((u32)sh[i], rbits);
+    if constexpr (PAY) labs[i] = shl[i];
+  }
 }
 
 // One workgroup per single-row range of at most N entries.
-template <int N>
-__global__ void __launch_bounds__(1024) k_sort_rows(u32 *gcol, const Range *__restrict__ rows, u32 rbits) {
+template <int N, bool PAY>
+__global__ void __launch_bounds__(1024) k_sort_rows(u32 *gcol, u32 *labels, const Range *__restrict__ rows,
+                                                    u32 rbits) {
   __shared__ u32 sh[N];
+  __shared__ u32 shl[PAY ? N : 1];
   const Range r = rows[blockIdx.x];
-  sort_row_words<N, 1024>(gcol + r.e0, r.ne, rbits, sh);
+  sort_row_words<N, 1024, PAY>(gcol + r.e0, PAY ? labels + r.e0 : nullptr, r.ne, rbits, sh, shl);
 }
 
 // One workgroup per staged hub chunk (entries [b, e) of the hub's row, e - b <= N).
-template <int N>
-__global__ void __launch_bounds__(1024) k_sort_hub_chunks(u32 *gcol, const int64_t *__restrict__ row_ptr,
+template <int N, bool PAY>
+__global__ void __launch_bounds__(1024) k_sort_hub_chunks(u32 *gcol, u32 *labels, const int64_t *__restrict__ row_ptr,
                                                           const int *__restrict__ hubs,
                                                           const HubChunk *__restrict__ chunks, u32 rbits) {
   __shared__ u32 sh[N];
+  __shared__ u32 shl[PAY ? N : 1];
   const HubChunk c = chunks[blockIdx.x];
-  sort_row_words<N, 1024>(gcol + row_ptr[hubs[c.hub]] + c.b, (int)(c.e - c.b), rbits, sh);
+  const int64_t e0 = row_ptr[hubs[c.hub]] + c.b;
+  sort_row_words<N, 1024, PAY>(gcol + e0, PAY ? labels + e0 : nullptr, (int)(c.e - c.b), rbits, sh, shl);
 }
 
 __global__ void k_scatter_rank(int n, const int *__restrict__ pid, const int *__restrict__ rank, int *__restrict__ gpid) {

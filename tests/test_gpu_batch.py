@@ -63,6 +63,20 @@ def test_batch_equals_solo_mixed_sizes():
     check_batch(mixed_graphs(), 6, "mixed")
 
 
+def test_batch_narrow_keys_with_separate_labels():
+    """Labels of 19 bits: with the largest graph's 12 bits of block id they fit 32-bit set keys, but
+    not above the union's 17 rank bits, so the labels stay in their own array (and move with the
+    rank-sorted rows); the tier graph has rows in every tier up to 20,000 entries."""
+    from tests.test_gpu_parity import tier_graph
+    rng = np.random.default_rng(31)
+    graphs = [tier_graph(seed=12, labels=3)]
+    for j in range(40):
+        graphs.append(graphgen.tiny(seed=100 + j, n=3000, m=12000))
+    for g in graphs:
+        g.elabel = ((1 << 18) + rng.integers(0, 4, size=g.m)).astype(np.int32)
+    check_batch(graphs, 5, "narrow-separate")
+
+
 def test_batch_with_degenerate_members():
     gs = [graphgen.batch_graph(1, 3000),
           graphgen.from_edges(1, [], [], None, [3]),

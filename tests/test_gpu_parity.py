@@ -331,6 +331,16 @@ def test_large_sparse_label_values():
     assert_same(h, 6, "spread-labels")
 
 
+def test_tiers_with_separate_labels():
+    """Labels too wide to pack above the ranks: every tier (rows up to 20,000 entries, hub chunks)
+    with the labels in their own array, sorted with their rows, in both key widths."""
+    kb = _kb()
+    g = tier_graph(seed=13, labels=3)
+    g.elabel = (((1 << 30) + 7) * (g.elabel.astype(np.int64) + 1) % ((1 << 31) - 1)).astype(np.int32)
+    assert_same(g, 5, "tiers-separate")
+    assert_same_tuned(g, 5, kb.tuning(key_bits=64), "tiers-separate-64")
+
+
 def giant_hub_graph(seed=23):
     """Two twin rows of 4.5M entries (same pairs, different order and duplicates), one slightly
     different, and small rows."""
