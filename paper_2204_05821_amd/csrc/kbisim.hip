@@ -687,6 +687,13 @@ int build_schedule(kbisim_ctx *c, const int64_t *ptr, Schedule &s, int range_edg
   return 0;
 }
 
+// Bits needed for x (0 for 0).
+int bit_width(uint64_t x) {
+  int b = 0;
+  while (b < 64 && (x >> b) != 0) ++b;
+  return b;
+}
+
 // Rank vertices by decreasing in-degree (ties by vertex id) and renumber the
 // targets of every CSR entry: gcol[e] = rank[col[e]].  A stable LSD radix
 // sort of (in-degree key, vertex) on the device; the grouping tables serve as
@@ -711,17 +718,32 @@ int build_rank(kbisim_ctx *c) {
     return KBISIM_EINTERNAL;
   k_rank_keys<<<(unsigned)std::min<int64_t>(blocks_for(n, 256), 1 << 16), 256, 0, c->stream>>>(n, indeg, ka);
   LAUNCH_CHECK();
-  for (int shift = 32; shift < 32 + RANK_KEYBITS; shift += 8) {
-    k_radix_hist<<<(unsigned)rtiles, 256, 0, c->stream>>>(n, ka, shift, rtiles, hist);
-    LAUNCH_CHECK();
-    const int64_t nt = (hist_n + SCAN_TILE - 1) / SCAN_TILE;
-    k_sum_tiles64<<<(unsigned)nt, 256, 0, c->stream>>>(hist_n, hist, tiles);
-    k_scan_tiles64<<<1, 256, 0, c->stream>>>(nt, tiles);
-    k_write_ptr64<<<(unsigned)nt, 256, 0, c->stream>>>(hist_n, hist, tiles, offs, nullptr);
-    LAUNCH_CHECK();
-    k_radix_scatter<<<(unsigned)rtiles, 256, 0, c->stream>>>(n, ka, shift, rtiles, offs, kb);
+  // stable LSD passes of 8 bits over key bits [32, 32 + bits)
+  auto radix_passes = [&](int bits) -> int {
+    for (int shift = 32; shift < 32 + bits; shift += 8) {
+      k_radix_hist<<<(unsigned)rtiles, 256, 0, c->stream>>>(n, ka, shift, rtiles, hist);
+      LAUNCH_CHECK();
+      const int64_t nt = (hist_n + SCAN_TILE - 1) / SCAN_TILE;
+      k_sum_tiles64<<<(unsigned)nt, 256, 0, c->stream>>>(hist_n, hist, tiles);
+      k_scan_tiles64<<<1, 256, 0, c->stream>>>(nt, tiles);
+      k_write_ptr64<<<(unsigned)nt, 256, 0, c->stream>>>(hist_n, hist, tiles, offs, nullptr);
+      LAUNCH_CHECK();
+      k_radix_scatter<<<(unsigned)rtiles, 256, 0, c->stream>>>(n, ka, shift, rtiles, offs, kb);
+      LAUNCH_CHECK();
+      std::swap(ka, kb);
+    }
+    return 0;
+  };
+  if ((rc = radix_passes(RANK_KEYBITS))) return rc;
+  if (c->num_graphs > 1) {
+    // In a batch, ranks stay inside each graph's vertex range (ordered by
+    // in-degree within the graph): a graph's gathers then touch its own
+    // part of the partition only, instead of the whole union's.
+    k_rank_gid_keys<<<(unsigned)std::min<int64_t>(blocks_for(n, 256), 1 << 16), 256, 0, c->stream>>>(n, ka, c->gid,
+                                                                                                    kb);
     LAUNCH_CHECK();
     std::swap(ka, kb);
+    if ((rc = radix_passes(bit_width((uint64_t)(c->num_graphs - 1))))) return rc;
   }
   k_rank_from_sorted<<<(unsigned)std::min<int64_t>(blocks_for(n, 256), 1 << 16), 256, 0, c->stream>>>(n, ka, c->rank);
   LAUNCH_CHECK();
@@ -1745,12 +1767,6 @@ QuotientPlan quotient_plan(int64_t m) {
   p.off_word = take(16);
   p.total = at;
   return p;
-}
-
-int bit_width(uint64_t x) {
-  int b = 0;
-  while (b < 64 && (x >> b) != 0) ++b;
-  return b;
 }
 
 // Exclusive scan of cnt[0..len) into out[0..len] (64-bit), on `s`.

@@ -1773,6 +1773,15 @@ __global__ void k_rank_keys(int64_t n, const int *__restrict__ indeg, u64 *keys)
     keys[v] = ((u64)(RANK_KEYMAX - min((u32)indeg[v], RANK_KEYMAX)) << 32) | (u64)v;
 }
 
+// Keys (graph of the vertex << 32 | vertex) in the order of `sorted`, for a
+// stable sort by graph that keeps the in-degree order inside each graph.
+__global__ void k_rank_gid_keys(int64_t n, const u64 *__restrict__ sorted, const int *__restrict__ gid, u64 *keys) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const u32 v = (u32)sorted[i];
+    keys[i] = ((u64)(u32)gid[v] << 32) | (u64)v;
+  }
+}
+
 __global__ void k_rank_from_sorted(int64_t n, const u64 *__restrict__ sorted, int *rank) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     rank[(u32)sorted[i]] = (int)i;
