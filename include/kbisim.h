@@ -124,6 +124,13 @@ int kbisim_create_tuned(const kbisim_graph *g, int kmax, const kbisim_tuning *tu
  * per-kernel profiler is on.                                                */
 int kbisim_use_graphs(kbisim_ctx *c, int enable);
 
+/* Bind the context to another stream for its later calls (a scheduler can
+ * prepare contexts on one stream and run them on others).  Work enqueued
+ * later on `stream` starts after all work enqueued so far on the previous
+ * stream (an event orders them; no host synchronisation).  Errors: EINVAL
+ * (null context, or the null stream while graph capture is on), EHIP.      */
+int kbisim_set_stream(kbisim_ctx *c, void *stream);
+
 /* Work-efficient mode (enable = 1; 0 = off, the default; -1 = leave as is).
  * The outputs are the same; the work is not: a vertex alone in its block is
  * not refined again (a singleton block cannot split), and once a step leaves

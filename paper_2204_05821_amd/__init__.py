@@ -71,6 +71,7 @@ def _lib():
     lib.kbisim_create_tuned.argtypes = [ctypes.POINTER(_Graph), i32, ctypes.POINTER(Tuning), vp, sz, vp,
                                         ctypes.POINTER(vp)]
     lib.kbisim_use_graphs.argtypes = [vp, i32]
+    lib.kbisim_set_stream.argtypes = [vp, vp]
     lib.kbisim_step_async.argtypes = [vp, i32, vp, vp]
     lib.kbisim_step_result.argtypes = [vp, i32, vp, vp, ctypes.POINTER(i64)]
     lib.kbisim_batch_workspace_bytes.argtypes = [ctypes.POINTER(_Graph), i64, i32, ctypes.POINTER(sz)]
@@ -205,6 +206,13 @@ class Refiner:
             rc = lib.kbisim_use_graphs(self._ctx, 1)
             if rc:
                 raise KbisimError(rc, "kbisim_use_graphs")
+
+    def set_stream(self, stream) -> None:
+        """Run later calls on `stream`, after everything enqueued so far on the current one."""
+        rc = _lib().kbisim_set_stream(self._ctx, _stream_handle(stream))
+        if rc:
+            raise KbisimError(rc, "kbisim_set_stream")
+        self.stream = stream
 
     def close(self):
         if getattr(self, "_ctx", None):
@@ -440,6 +448,13 @@ class Batch:
             rc = lib.kbisim_use_graphs(self._ctx, 1)
             if rc:
                 raise KbisimError(rc, "kbisim_use_graphs")
+
+    def set_stream(self, stream) -> None:
+        """Run later calls on `stream`, after everything enqueued so far on the current one."""
+        rc = _lib().kbisim_set_stream(self._ctx, _stream_handle(stream))
+        if rc:
+            raise KbisimError(rc, "kbisim_set_stream")
+        self.stream = stream
 
     def close(self):
         if getattr(self, "_b", None):

@@ -1498,6 +1498,21 @@ int kbisim_use_graphs(kbisim_ctx *c, int enable) {
   return KBISIM_OK;
 }
 
+int kbisim_set_stream(kbisim_ctx *c, void *stream) {
+  if (!c) return KBISIM_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  if (c->use_graphs && s == nullptr) return KBISIM_EINVAL;
+  if (s == c->stream) return KBISIM_OK;
+  hipEvent_t e = nullptr;
+  HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  hipError_t r = hipEventRecord(e, c->stream);
+  if (r == hipSuccess) r = hipStreamWaitEvent(s, e, 0);
+  (void)hipEventDestroy(e);
+  if (r != hipSuccess) return hip_fail(r);
+  c->stream = s;
+  return KBISIM_OK;
+}
+
 int kbisim_destroy(kbisim_ctx *c) {
   if (c) {
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);

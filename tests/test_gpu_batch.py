@@ -164,6 +164,40 @@ def test_graph_replay_with_collision_fallback(monkeypatch):
     rg.close()
 
 
+def test_set_stream_after_create():
+    """A context moved to another stream right after create (whose last kernels are still queued
+    on the first stream), and moved again between calls, gives the reference results."""
+    kb = _kb()
+    from tests.test_gpu_parity import tier_graph
+    g = tier_graph(seed=19)
+    exp, ec = ref(g, 5)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    r = kb.Refiner(*kb.to_device(g), kmax=5, stream=s1)
+    r.set_stream(s2)
+    ids, counts = r.refine(5)
+    assert counts == ec
+    for a, b in zip(ids, exp):
+        assert np.array_equal(a.cpu().numpy(), b)
+    r.set_stream(s1)
+    ids, counts = r.refine(3)
+    assert counts == ec[:3]
+    r.close()
+    graphs = mixed_graphs(seed=5, count=8)
+    rp, col, el, vl, vp, off = kb.union_of(graphs)
+    t = lambda a: None if a is None else torch.from_numpy(a).cuda()
+    b = kb.Batch(t(rp), t(col), t(el), t(vl), t(vp), off, kmax=4, stream=s1)
+    b.set_stream(s2)
+    outs, counts = b.refine(4)
+    torch.cuda.synchronize()
+    off = b.vert_off
+    for gi, gg in enumerate(graphs):
+        e, c = ref(gg, 4)
+        assert counts[gi] == c
+        for i in range(4):
+            assert np.array_equal(outs[i][off[gi]:off[gi + 1]].cpu().numpy(), e[i])
+    b.close()
+
+
 # ------------------------------------------------------------------ tunings
 
 @pytest.mark.parametrize("re,hc,hp,kbits", list(itertools.product([1024, 2048], [2048, 4096], [1024, 2048],
