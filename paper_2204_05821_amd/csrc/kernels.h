@@ -1886,13 +1886,4 @@ __global__ void __launch_bounds__(256) k_gather_probe(Src src, int64_t m, u32 *o
   if ((threadIdx.x & (WAVE - 1)) == 0) atomicAdd(&out[blockIdx.x & omask], acc);
 }
 
-// Degrees of the hub list (for host-side chunking at create time).
-__global__ void k_hub_degrees(const int *hubs, int nhub, const int64_t *ptr, int64_t *deg_out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < nhub) {
-    const int v = hubs[i];
-    deg_out[i] = ptr ? ptr[v + 1] - ptr[v] : 1;
-  }
-}
-
 }  // namespace kb
