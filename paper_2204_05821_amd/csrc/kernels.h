@@ -615,14 +615,20 @@ __global__ void __launch_bounds__(256) k_sig_range(Src src, const Range *__restr
   // Sums from the set: thread t reads the 2U consecutive slots from 2Ut on;
   // slot s lies in the region of vertex owner[s / 2].  Runs of one vertex are
   // summed in registers and added to the vertex once per run, so the shared
-  // accumulators see a few atomics per vertex instead of one per pair.
+  // accumulators see a few atomics per vertex instead of one per pair.  Each
+  // lane starts at a different slot of its 2U (rotation by lane / (64 / 2U)),
+  // so the lanes of one read fall in different LDS banks instead of the few
+  // that a stride of 2U words allows; the order of a sum does not matter,
+  // and the rotation breaks at most one run.
   {
+    constexpr int SL = 2 * U, GRP = WAVE / SL > 0 ? WAVE / SL : 1;
+    const int rot = (lane / GRP) & (SL - 1);
     u64 a = 0;
     u32 c = 0;
     int cur = -1;
 #pragma unroll
-    for (int q = 0; q < 2 * U; ++q) {
-      const int sidx = 2 * U * t + q;
+    for (int q = 0; q < SL; ++q) {
+      const int sidx = SL * t + ((q + rot) & (SL - 1));
       if (sidx < 2 * E) {
         const int lo = owner[sidx >> 1];
         if (lo != cur) {
