@@ -478,8 +478,10 @@ struct HostRowsLease {
 // Build the static schedule of the rows of `ptr` (NULL: every row has one
 // item) on the host: runs of consecutive low-degree vertices, single-row
 // ranges, and hub chunks, partitions and staging areas.  Synchronises.
-// row_max: longest row with a workgroup of its own (longer rows are hubs).
-int build_schedule(kbisim_ctx *c, const int64_t *ptr, Schedule &s, int range_edges, int64_t row_max = ROW_MAX) {
+// row_max: longest row with a workgroup of its own (longer rows are hubs);
+// staged_max: longest hub staged in partitions (longer hubs use a global set).
+int build_schedule(kbisim_ctx *c, const int64_t *ptr, Schedule &s, int range_edges, int64_t row_max,
+                   int64_t staged_max) {
   const int64_t n = c->g.n;
   const Tuning &t = c->tune;
   s = Schedule{};
@@ -606,7 +608,7 @@ int build_schedule(kbisim_ctx *c, const int64_t *ptr, Schedule &s, int range_edg
     const int64_t d = deg(hubs[i]);
     const int64_t C = (d + t.hub_chunk - 1) / t.hub_chunk;
     const int P = hub_parts_for(t, d);
-    const bool staged = d <= HUB_STAGED_MAX && C <= HUB_PMAX && poff_at + C * (P + 1) <= c->plan.npoff_max;
+    const bool staged = d <= staged_max && C <= HUB_PMAX && poff_at + C * (P + 1) <= c->plan.npoff_max;
     if (!staged) continue;
     HubPart hp;
     hp.hub = (int)i;
@@ -695,8 +697,9 @@ int bit_width(uint64_t x) {
 }
 
 // Rank vertices by decreasing in-degree (ties by vertex id) and renumber the
-// targets of every CSR entry: gcol[e] = rank[col[e]].  A stable LSD radix
-// sort of (in-degree key, vertex) on the device; the grouping tables serve as
+// targets of every CSR entry: gcol[e] = rank[col[e]].  Vertices no entry
+// names get rank -1: they are never gathered.  A stable LSD radix sort of
+// (in-degree key, vertex) on the device; the grouping tables serve as
 // scratch, so this runs before they are cleared.  Synchronises.
 int build_rank(kbisim_ctx *c) {
   const int64_t n = c->g.n, m = c->g.m;
@@ -745,7 +748,8 @@ int build_rank(kbisim_ctx *c) {
     std::swap(ka, kb);
     if ((rc = radix_passes(bit_width((uint64_t)(c->num_graphs - 1))))) return rc;
   }
-  k_rank_from_sorted<<<(unsigned)std::min<int64_t>(blocks_for(n, 256), 1 << 16), 256, 0, c->stream>>>(n, ka, c->rank);
+  k_rank_from_sorted<<<(unsigned)std::min<int64_t>(blocks_for(n, 256), 1 << 16), 256, 0, c->stream>>>(n, ka, indeg,
+                                                                                                 c->rank);
   LAUNCH_CHECK();
   if (m > 0) {
     k_remap<<<(unsigned)std::min<int64_t>(blocks_for(m, 256), 1 << 16), 256, 0, c->stream>>>(
@@ -1351,7 +1355,7 @@ int create_impl(const kbisim_graph *g, int kmax, const kbisim_tuning *tuning, vo
     Schedule ls;
     LabelSrc src{g->vlabel_ptr, g->vlabel, c->gid};
     if (!g->vlabel) src = LabelSrc{nullptr, c->gid, nullptr};  // batch without labels: one block per graph
-    if ((rc = build_schedule(c, src.ptr, ls, range_cap(c, true)))) return fail(rc);
+    if ((rc = build_schedule(c, src.ptr, ls, range_cap(c, true), ROW_MAX, HUB_STAGED_MAX_WIDE))) return fail(rc);
     int *cnt = c->counters + CNT_STRIDE * (plan.ncounter_steps - 2);
     if ((rc = fill_i32(c, cnt, CNT_STRIDE, 0))) return fail(rc);
     int64_t *dcount = c->dcounts + (plan.ncounter_steps - 2);
@@ -1363,7 +1367,7 @@ int create_impl(const kbisim_graph *g, int kmax, const kbisim_tuning *tuning, vo
   }
   // Static schedule of the graph rows.
   if ((rc = build_schedule(c, g->row_ptr, c->sched, range_cap(c, !c->narrow),
-                           c->narrow ? ROW_MAX_NARROW : ROW_MAX)))
+                           c->narrow ? ROW_MAX_NARROW : ROW_MAX, c->narrow ? HUB_STAGED_MAX : HUB_STAGED_MAX_WIDE)))
     return fail(rc);
   if ((rc = build_nonempty_list(c, c->sched))) return fail(rc);
   if ((rc = sort_long_rows(c, c->sched))) return fail(rc);

@@ -51,8 +51,15 @@ constexpr int BLOCK_SLOTS = 8192;    // LDS set slots for exact checks (64 KB)
 constexpr int HUB_CHUNK_MAX = 4096;  // entries per hub staging workgroup: 2048 (default) or 4096
 constexpr int HUB_PMAX = 1024;       // partitions per hub at most
 constexpr int HUB_PART_TARGET = 2048;  // expected entries per hub partition
-constexpr int HUB_PSLOTS = 8192;     // LDS set slots per hub partition workgroup
-constexpr int64_t HUB_STAGED_MAX = (int64_t)HUB_PMAX * 4096;  // larger hubs use a global hash set
+// LDS set slots per hub partition workgroup, and the largest staged hub (a
+// larger one uses a global hash set): a partition then expects at most half
+// as many distinct keys as its set has slots.  64-bit keys take half the
+// slots (and half the staged hub size), so three workgroups fit a CU
+// instead of two.
+constexpr int HUB_PSLOTS = 8192;
+constexpr int HUB_PSLOTS_WIDE = 4096;
+constexpr int64_t HUB_STAGED_MAX = (int64_t)HUB_PMAX * HUB_PSLOTS / 2;
+constexpr int64_t HUB_STAGED_MAX_WIDE = (int64_t)HUB_PMAX * HUB_PSLOTS_WIDE / 2;
 constexpr int HUB_GCHUNK = 8192;     // entries per workgroup in the global-set path
 constexpr int SCAN_ITEMS = 16;       // items per thread in the scan
 constexpr int SCAN_TILE = 256 * SCAN_ITEMS;
@@ -844,7 +851,8 @@ __global__ void __launch_bounds__(256) k_hub_reduce(Src src, const HubPart *__re
                                                     u64 *hub_acc, u32 *hub_cnt, u32 *err, const int *__restrict__ hubs,
                                                     const unsigned char *__restrict__ skip) {
   typedef Keys<K> KO;
-  __shared__ K set[HUB_PSLOTS];
+  constexpr int PS = sizeof(K) == 8 ? HUB_PSLOTS_WIDE : HUB_PSLOTS;
+  __shared__ K set[PS];
   __shared__ int64_t sbase[HUB_PMAX]; // per chunk: staging position of this partition's segment
   __shared__ int pre[HUB_PMAX + 1];    // exclusive prefix of segment lengths
   __shared__ int wtot[4];
@@ -853,7 +861,7 @@ __global__ void __launch_bounds__(256) k_hub_reduce(Src src, const HubPart *__re
   const HubPart hp = parts[blockIdx.x];
   if (skip && skip[hubs[hp.hub]]) return;  // singleton block (work-efficient mode)
   const int C = hp.nchunks;
-  for (int i = threadIdx.x; i < HUB_PSLOTS; i += 256) set[i] = KO::EMPTY;
+  for (int i = threadIdx.x; i < PS; i += 256) set[i] = KO::EMPTY;
   // segment lengths, then an exclusive scan over the (at most 1024) chunks
   {
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -912,13 +920,13 @@ __global__ void __launch_bounds__(256) k_hub_reduce(Src src, const HubPart *__re
     for (int u = 0; u < 4; ++u) {
       const K p = pr[u];
       if (p == KO::EMPTY) continue;
-      u32 sl = KO::hash(p) & (HUB_PSLOTS - 1);
+      u32 sl = KO::hash(p) & (PS - 1);
       for (int probes = 0;; ++probes) {
-        if (probes >= HUB_PSLOTS) { atomicOr(err, ERR_VERIFY_OVERFLOW); break; }
+        if (probes >= PS) { atomicOr(err, ERR_VERIFY_OVERFLOW); break; }
         const K old = atomicCAS(&set[sl], KO::EMPTY, p);
         if (old == KO::EMPTY) { acc += mix_pair(KO::wide(src, p)); ++cnt; break; }
         if (old == p) break;
-        sl = (sl + 1) & (HUB_PSLOTS - 1);
+        sl = (sl + 1) & (PS - 1);
       }
     }
   }
@@ -929,7 +937,8 @@ __global__ void __launch_bounds__(256) k_hub_reduce(Src src, const HubPart *__re
   }
 }
 
-// Very large hubs (deg > HUB_STAGED_MAX): workgroups of one hub share a
+// Very large hubs (deg > HUB_STAGED_MAX, or HUB_STAGED_MAX_WIDE with 64-bit
+// keys): workgroups of one hub share a
 // global hash set of 2*deg slots; slot = pair | (epoch << 62), 0 = unused,
 // epochs 1..3.  Pairs are < 2^62.
 struct HubGChunk {
@@ -1336,7 +1345,8 @@ __global__ void k_list_from_ids(int n, const int *__restrict__ pos, int *__restr
 }
 
 // Every non-head copies its representative's id (written by k_scan_write),
-// and the new partition is also written in rank order for the next gather.
+// and the new partition is also written in rank order for the next gather
+// (vertices no entry names have rank -1 and are left out).
 // Work-efficient mode (multi != NULL): every non-head marks its head with the
 // step's stamp, so a head left unmarked is a singleton block (k_singletons).
 __global__ void k_assign(int n, const int *__restrict__ rep, int *out, const int *__restrict__ rank,
@@ -1350,7 +1360,10 @@ __global__ void k_assign(int n, const int *__restrict__ rep, int *out, const int
     out[v] = val;
     if (multi && r >= 0) multi[r] = dep[EP_ZERO];
   }
-  if (rank) gpid_next[rank[v]] = val;
+  if (rank) {
+    const int rk = rank[v];
+    if (rk >= 0) gpid_next[rk] = val;
+  }
 }
 
 // single[v] = 1 iff v is alone in its block of the partition just computed.
@@ -1631,9 +1644,12 @@ __global__ void __launch_bounds__(1024) k_sort_hub_chunks(u32 *gcol, u32 *labels
   sort_row_words<N, 1024, PAY>(gcol + e0, PAY ? labels + e0 : nullptr, (int)(c.e - c.b), rbits, sh, shl);
 }
 
+// gpid[rank[v]] = pid[v] for every vertex some entry names (rank >= 0).
 __global__ void k_scatter_rank(int n, const int *__restrict__ pid, const int *__restrict__ rank, int *__restrict__ gpid) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v < n) gpid[rank[v]] = pid[v];
+  if (v >= n) return;
+  const int r = rank[v];
+  if (r >= 0) gpid[r] = pid[v];
 }
 
 // ---------------------------------------------------------------- batches
@@ -1788,9 +1804,14 @@ __global__ void k_rank_gid_keys(int64_t n, const u64 *__restrict__ sorted, const
   }
 }
 
-__global__ void k_rank_from_sorted(int64_t n, const u64 *__restrict__ sorted, int *rank) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    rank[(u32)sorted[i]] = (int)i;
+// rank[v] = position of v in the sorted order, or -1 when no entry names v:
+// such vertices are never gathered, so the rank-order copies skip them.
+__global__ void k_rank_from_sorted(int64_t n, const u64 *__restrict__ sorted, const int *__restrict__ indeg,
+                                   int *rank) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const u32 v = (u32)sorted[i];
+    rank[v] = indeg[v] > 0 ? (int)i : -1;
+  }
 }
 
 // flag[i] = 1 where a run of equal keys starts.

@@ -371,3 +371,43 @@ def test_giant_hubs_use_the_global_set_path():
     exp, _ = ref_all(g, 3)
     assert exp[1][0] == exp[1][1] != exp[1][2]
     assert_same(g, 3, "giant-hubs")
+
+
+def wide_hub_graph(seed=43):
+    """Hub rows over 2^20 distinct targets whose P0 blocks all differ, so every pair of a row is
+    distinct and 64-bit keys are needed (22 bits of block id, 10 of edge label): row 1 is row 0
+    with one target replaced, row 2 holds row 0's pairs twice and one more copy (2^21 + 1
+    entries, past the largest staged hub).  5M small random entries give the schedule room to
+    stage the two shorter hubs."""
+    rng = np.random.default_rng(seed)
+    n, d, m_small = 2_200_000, 1 << 20, 5_000_000
+    tg = rng.choice(np.arange(3, n), size=d + 1, replace=False)
+    t, extra = tg[:d], tg[d]
+    lb = rng.integers(0, 1000, size=d)
+    t1 = t.copy()
+    t1[-1] = extra
+    perm = rng.permutation(2 * d + 1)
+    t2 = np.concatenate([t, t, t[:1]])[perm]
+    l2 = np.concatenate([lb, lb, lb[:1]])[perm]
+    src = np.concatenate([np.zeros(d), np.ones(d), np.full(2 * d + 1, 2), rng.integers(3, n, size=m_small)])
+    dst = np.concatenate([t, t1, t2, rng.integers(0, n, size=m_small)])
+    lab = np.concatenate([lb, lb, l2, rng.integers(0, 1000, size=m_small)])
+    vlabel = np.arange(n) - 2
+    vlabel[:3] = 0
+    return graphgen.from_edges(n, src.astype(np.int64), dst, lab, vlabel, name="wide-hubs")
+
+
+def test_wide_key_hubs_fill_their_partition_sets():
+    """With 64-bit keys a staged hub's partitions have 4,096-slot sets: a row of 2^20 distinct
+    pairs has 512 partitions of about 2,048 pairs each, the most a partition is planned for.  A
+    row past 2^21 entries takes the global set, and both paths must give the same signature
+    for the same pair set."""
+    kb = _kb()
+    g = wide_hub_graph()
+    r = kb.refiner_for(g, kmax=1)
+    info = r.schedule_info()
+    r.close()
+    assert info["hub"]["vertices"] == 2 and info["hub_global"]["vertices"] == 1, info
+    exp, _ = ref_all(g, 2)
+    assert exp[1][0] == exp[1][2] != exp[1][1]
+    assert_same(g, 2, "wide-hubs")
