@@ -164,6 +164,37 @@ def test_graph_replay_with_collision_fallback(monkeypatch):
     rg.close()
 
 
+def test_epochs_wrap_across_eager_and_replayed_calls(monkeypatch):
+    """Table epochs cycle every 15 steps and a wrap clears the table on the device.  Many eager
+    and replayed calls on two contexts, eager single steps after replays, and forced collisions
+    (host-driven peeling rounds advance the peeling-table epoch too) cross several wraps and must
+    all give the reference results."""
+    monkeypatch.setenv("KBISIM_DEBUG_HASH_BITS", "6")
+    kb = _kb()
+    g = graphgen.tiny(seed=8, n=3000, m=12000)
+    exp, ec = ref(g, 5)
+    r = kb.refiner_for(g, kmax=5)
+    rg = kb.Refiner(*kb.to_device(g), kmax=5, graphs=True)
+    outs = rg.alloc_outputs(5)
+    sout = rg.alloc_outputs(5)
+    for rep in range(7):
+        print(f"[epochs] round {rep}", flush=True)
+        for ctx, o in ((r, None), (rg, outs)):
+            ids, counts = ctx.refine(5, out=o)
+            assert counts == ec, (rep, counts, ec)
+            for a, b in zip(ids, exp):
+                assert np.array_equal(a.cpu().numpy(), b)
+        counts = []
+        for i in range(5):
+            rg.step_async(i, None if i == 0 else sout[i - 1], sout[i])
+            counts.append(rg.step_result(i, None if i == 0 else sout[i - 1], sout[i]))
+        assert counts == ec
+        for a, b in zip(sout, exp):
+            assert np.array_equal(a.cpu().numpy(), b)
+    r.close()
+    rg.close()
+
+
 def test_set_stream_after_create():
     """A context moved to another stream right after create (whose last kernels are still queued
     on the first stream), and moved again between calls, gives the reference results."""
