@@ -113,3 +113,21 @@ def test_transpose_argument_checks_before_touching_the_device(lib):
     assert f(1000, 5000, fake, fake, None, fake, fake, None, None, 1 << 30, None) == -3
     assert f(1000, 5000, fake, fake, None, fake, fake, None, fake, 8, None) == -3
     assert f(1 << 31, 5, fake, fake, None, fake, fake, None, fake, 1 << 30, None) == -5
+
+
+def test_the_two_billion_edge_graph_fits_one_gpu(lib):
+    """The workspace of the 2B-edge RDF-like graph (2^28 vertices, about one label each), its CSR,
+    labels and ten output arrays fit the 288 GB of one MI355X with room to spare, and the
+    workspace grows linearly with the graph (the sizes are computed on the host)."""
+    f = lib.kbisim_workspace_bytes
+    f.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]
+    f.restype = ctypes.c_int
+    out = ctypes.c_size_t(0)
+    n, m = 1 << 28, 2_000_000_000
+    assert f(ctypes.byref(Graph(n, m, n)), 10, ctypes.byref(out)) == 0
+    ws = out.value
+    csr = 8 * (n + 1) + 4 * m + 4 * m + 8 * (n + 1) + 4 * n   # row_ptr, col, elabel, label-set CSR
+    outputs = 10 * 4 * n
+    assert ws + csr + outputs < 0.5 * 288e9, (ws, csr, outputs)
+    assert f(ctypes.byref(Graph(n // 2, m // 2, n // 2)), 10, ctypes.byref(out)) == 0
+    assert 0.45 < out.value / ws < 0.55
