@@ -75,6 +75,26 @@ def test_brute_force_relation_is_equivalence():
             assert brute.is_equivalence(R)
 
 
+def test_is_equivalence_rejects_non_equivalences():
+    """The relation check must fail on each way a relation can miss being an equivalence."""
+    n = 4
+    ident = [[u == v for v in range(n)] for u in range(n)]
+    full = [[True] * n for _ in range(n)]
+    assert brute.is_equivalence(ident) and brute.is_equivalence(full)
+    two_blocks = [[(u < 2) == (v < 2) for v in range(n)] for u in range(n)]
+    assert brute.is_equivalence(two_blocks)
+    not_reflexive = [row[:] for row in two_blocks]
+    not_reflexive[3][3] = False
+    assert not brute.is_equivalence(not_reflexive)
+    asymmetric = [row[:] for row in ident]
+    asymmetric[0][2] = True            # 0 ~ 2 but not 2 ~ 0
+    assert not brute.is_equivalence(asymmetric)
+    not_transitive = [row[:] for row in ident]
+    for u, v in [(0, 1), (1, 0), (1, 2), (2, 1)]:   # 0 ~ 1 ~ 2 but not 0 ~ 2
+        not_transitive[u][v] = True
+    assert not brute.is_equivalence(not_transitive)
+
+
 @pytest.mark.parametrize("seed", range(8))
 def test_oracle_matches_brute_force(seed):
     """Random graphs with n <= 12: empty label sets, parallel edges, self-loops, 1-3 edge labels."""
@@ -211,6 +231,49 @@ def test_refinement_invariants(maker):
                 fixed = k - 1
                 assert ids[k] == ids[k - 1]
                 assert splitter.is_stable(g, ids[k])
+
+
+def test_is_stable_rejects_unstable_partitions():
+    """Stability (Def. partition-stable, with labelled splitters) on hand-built cases.
+
+    Vertex 0 has an a-edge into block {2}, vertex 1 a b-edge into it: the
+    block {0, 1} is split by either splitter, so only the partition that
+    separates 0 from 1 is stable.  A vertex without an edge into a block is
+    split from one that has such an edge.
+    """
+    g = graphgen.from_edges(3, [0, 1], [2, 2], [0, 1])
+    assert not splitter.is_stable(g, [0, 0, 1])
+    assert splitter.is_stable(g, [0, 1, 2])
+    g = graphgen.from_edges(3, [0, 1], [2, 2], [0, 0])
+    assert splitter.is_stable(g, [0, 0, 1])           # same label: {0, 1} is stable
+    assert not splitter.is_stable(g, [0, 0, 0])       # 2 has no edge into the block, 0 does
+    g = graphgen.from_edges(2, [0], [1], [0])
+    assert not splitter.is_stable(g, [0, 0])
+    assert splitter.is_stable(g, [0, 1])
+
+
+@pytest.mark.parametrize("mode", ["fw", "bw", "schaetzle", "kaushik"])
+def test_is_stable_matches_printed_fixpoints(mode):
+    """In the printed tables a partition is stable exactly when the next one repeats it."""
+    g = helpers.example_variant(mode)
+    printed = PRINTED[mode]
+    for k in sorted(printed):
+        if k + 1 in printed:
+            assert splitter.is_stable(g, printed[k]) == (printed[k + 1] == printed[k]), (mode, k)
+
+
+def test_is_stable_iff_brute_force_fixpoint():
+    """On random tiny graphs: P_k is stable iff brute force gives P_{k+1} = P_k."""
+    rng = random.Random(23)
+    seen = {True: 0, False: 0}
+    for _ in range(150):
+        g = helpers.random_small_graph(rng, n_max=9, m_max=16)
+        bids, _ = brute.brute_force(g, 5)
+        for k in range(5):
+            fix = bids[k + 1] == bids[k]
+            assert splitter.is_stable(g, bids[k]) == fix, k
+            seen[fix] += 1
+    assert seen[True] > 50 and seen[False] > 50
 
 
 def test_resume_from_intermediate_partition():
