@@ -6,21 +6,28 @@ refinement iterations (signature gather and dedupe, key hashing, grouping,
 exact check, first-vertex numbering), inputs already resident in HBM.  The
 metric is edge-iterations per second: m * k * steps / time.
 
-Default workload: RMAT scale 23 (8,388,608 vertices), 100,000,000 directed
-edges, (a, b, c, d) = (0.57, 0.19, 0.19, 0.05), one vertex label per vertex
-drawn Zipf(1.0) over 32 labels, edge labels Zipf(1.1) over 64, seed 2.
-The paper's datasets are not available; this synthetic recipe stands in for
-its 100M-edge class.
+Default workload: RDF-like RMAT, scale 27 (134,217,728 vertices),
+1,000,000,000 directed edges, (a, b, c, d) = (0.57, 0.19, 0.19, 0.05),
+0-3 type labels per vertex (sizes 0/1/2/3 with probability .25/.55/.15/.05)
+drawn Zipf(1.0) from 1,000 types and distinct within a vertex, 1,000 edge
+labels Zipf(1.2), seed 3.  The paper's datasets are not available; this
+synthetic recipe stands in for its billion-edge class (BSBM1B; the 2B-edge
+run, --workload rmat_rdf_s28_m2B_k10, for BTC2B).
 
 Prints one JSON line with the throughput, a roofline entry for the dominant
 kernel (timed with HIP events inside the timed region) and the CPU reference
-timed on a bounded sample of the same workload.  With --mode all (the
-default) the line also carries the batched form (4,096 graphs, edge counts
-log-uniform 1k-2M, half uniform-random and half RMAT, k = 10, autotuned
-launch shapes, against per-graph plain calls) and the served form (Poisson
-arrivals at 200 jobs/s of RMAT jobs with 10k-50M edges and k uniform in
-1..10 under a 200 GB budget: p50/p99 latency and jobs/s, and the capacity of
-the continuous-batching server against a one-job-at-a-time server).
+timed on a bounded sample of the same graph.  The sample is the rows of the
+first n/32 vertices with their targets renumbered compactly; its first
+refinement step equals the full graph's on those vertices (ids are numbered
+by first vertex), which the run checks against the GPU.  The reference runs
+in a child process forked before the GPU is touched, so it overlaps the GPU
+legs.  With --mode all (the default) the line also carries the 100M-edge
+plain figure, the batched form (4,096 graphs, edge counts log-uniform
+1k-2M, half uniform-random and half RMAT, k = 10, autotuned launch shapes,
+against per-graph plain calls) and the served form (Poisson arrivals at 200
+jobs/s of RMAT jobs with 10k-50M edges and k uniform in 1..10 under a 200 GB
+budget: p50/p99 latency and jobs/s, and the capacity of the
+continuous-batching server against a one-job-at-a-time server).
 """
 from __future__ import annotations
 
@@ -120,18 +127,73 @@ def measured_traffic(kernel: str, workload: str):
         return None
 
 
-def cpu_baseline(g, w, max_iters: int = 1):
-    """The CPU reference, as it stands, on a bounded sample: the first refinement iteration(s)."""
-    import oracle
-    t0 = time.perf_counter()
-    ids, counts, secs = oracle.refine(g, max_iters, timings=True)
-    wall = time.perf_counter() - t0
-    it = sum(secs)
-    value = g.m * max_iters / it
-    return {"value": value, "unit": "edge-iterations/s", "cores": 1, "kind": "oracle",
-            "sample": f"iteration 1..{max_iters} of {w['k']} on the full graph (n={g.n}, m={g.m}), "
-                      f"{it:.1f} s of refinement, {wall:.1f} s wall, single-threaded C++",
-            "counts": counts}
+def host_info():
+    """Cores this process may use, the machine's core count and the CPU model."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"nproc": usable, "cpu_count": os.cpu_count(), "cpu_model": model}
+
+
+def _cpu_child(g, w, conn):
+    try:
+        import graphgen
+        import oracle
+        t0 = time.perf_counter()
+        vs = max(1, g.n >> 5)
+        s = graphgen.prefix_subgraph(g, vs)
+        build_s = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        ids, counts, secs = oracle.refine(s, 1, timings=True)
+        wall = time.perf_counter() - t0
+        it = secs[0]
+        conn.send({"value": s.m / it, "unit": "edge-iterations/s", "cores": 1, "kind": "oracle",
+                   "sample": f"refinement iteration 1 of {w['k']} on the rows of the first {vs} of {g.n} vertices "
+                             f"({s.m} of {g.m} entries; the {s.n - vs} other vertices they name renumbered "
+                             f"compactly, labels kept), {it:.1f} s of refinement, {wall:.1f} s with P0, "
+                             f"{build_s:.1f} s to cut the sample; single-threaded C++, one process",
+                   "prefix_vertices": vs, "sample_entries": int(s.m), "host": host_info(),
+                   "_p1_prefix": ids[0][:vs].copy()})
+    except BaseException as e:  # report instead of dying silently
+        conn.send({"error": repr(e)})
+    finally:
+        conn.close()
+
+
+class CpuBaseline:
+    """The CPU reference on a bounded sample, in a child forked before any GPU call."""
+
+    def __init__(self, g, w):
+        import multiprocessing as mp
+        ctx = mp.get_context("fork")
+        self.rx, tx = ctx.Pipe(duplex=False)
+        self.proc = ctx.Process(target=_cpu_child, args=(g, w, tx), daemon=True)
+        self.proc.start()
+        tx.close()
+
+    def collect(self, gpu_p1_prefix=None, gpu_count1=None):
+        res = self.rx.recv()
+        self.proc.join()
+        if "error" in res:
+            log(f"[bench] CPU reference failed: {res['error']}")
+            return None
+        p1 = res.pop("_p1_prefix")
+        if gpu_p1_prefix is not None:
+            import numpy as np
+            res["agrees_with_gpu"] = bool(np.array_equal(p1, gpu_p1_prefix[:len(p1)]))
+            if not res["agrees_with_gpu"]:
+                log("[bench] WARNING: the CPU reference differs from the GPU on the sample's vertices")
+        return res
 
 
 def copy_probe(kb, torch, mib):
@@ -152,12 +214,10 @@ def copy_probe(kb, torch, mib):
     return {"copy_probe_bytes": nbytes, "ms": ms, "GBs_read_plus_write": 2 * nbytes / ms / 1e6}
 
 
-def run_plain(args, kb, torch):
-    w = WORKLOADS[args.workload]
+def run_plain(args, kb, torch, workload, g, cpu_job=None, extras=True):
+    """The plain form on one graph: timed k = 10 calls, per-kernel figures, roofline entry."""
+    w = WORKLOADS[workload]
     k = w["k"]
-    t0 = time.perf_counter()
-    g = make_graph(w)
-    log(f"[bench] generated {args.workload}: n={g.n} m={g.m} in {time.perf_counter() - t0:.1f}s")
     dev = torch.device("cuda:0")
     rp, col, el, vl, vp = kb.to_device(g, dev)
     torch.cuda.synchronize()
@@ -205,6 +265,7 @@ def run_plain(args, kb, torch):
     ms_per_step = max(gpu_ms, wall * 1e3) / args.steps
     value = g.m * k * args.steps / (ms_per_step * args.steps / 1e3)
     log(f"[bench] {args.steps} steps: {ms_per_step:.3f} ms/step ({gpu_ms:.1f} ms events, {wall * 1e3:.1f} ms wall)")
+    p1_prefix = outs[0][:max(1, g.n >> 5)].cpu().numpy() if cpu_job is not None else None
 
     kernels = {}
     roofline = None
@@ -227,7 +288,7 @@ def run_plain(args, kb, torch):
         achieved = ab / (avg / 1e3) / 1e9
         roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": measured_traffic(dom, args.workload),
+                    "traffic": measured_traffic(dom, workload),
                     "algorithmic_bytes_per_launch": ab, "avg_launch_ms": round(avg, 5)}
     b_alg = 12.0 * g.m + 16.0 * g.n
     step_gbs = b_alg * k / (ms_per_step / 1e3) / 1e9
@@ -244,6 +305,18 @@ def run_plain(args, kb, torch):
     log(f"[bench] gather probe: {probe_ms:.3f} ms per pass over {g.m} entries "
         f"({gather['G_gathers_per_s']:.1f} G gathers/s)")
 
+    work_efficient = summary = None
+    if not extras:
+        r.close()
+        del rp, col, el, vl, vp, outs, r
+        torch.cuda.empty_cache()
+        return {"workload": workload, "value": value, "unit": "edge-iterations/s", "ms_per_step": ms_per_step,
+                "steps": args.steps, "n": g.n, "m": g.m, "k": k, "recipe": w["desc"], "seed": w["seed"],
+                "roofline": roofline, "step_hbm": {"algorithmic_bytes_per_iteration": b_alg,
+                                                   "achieved_GBs": round(step_gbs, 1),
+                                                   "frac_of_peak": round(step_gbs / HBM_PEAK_GBS, 4)},
+                "counts": counts, "gather_probe": gather, "create_ms": round(create_ms, 1), "kernels": kernels,
+                "tiers": tiers}
     # Work-efficient mode (singleton blocks skipped, stop at the fixpoint): reported
     # separately; its outputs must equal the full-work outputs.
     full = [o.clone() for o in outs]
@@ -275,14 +348,15 @@ def run_plain(args, kb, torch):
                       "note": "singleton blocks skipped and the loop stopped at the fixpoint; not the headline value"}
     r.close()
     del rp, col, el, vl, vp, outs, r
+    torch.cuda.empty_cache()
 
     cpu = None
-    if not args.no_cpu_baseline:
-        log("[bench] timing the CPU reference on iteration 1 ...")
-        cpu = cpu_baseline(g, w)
-        log(f"[bench] CPU reference: {cpu['value']:.3e} edge-iterations/s ({cpu['sample']})")
-        if cpu.pop("counts")[0] != counts[0]:
-            log("[bench] WARNING: CPU reference count differs from the GPU count at iteration 1")
+    if cpu_job is not None:
+        log("[bench] waiting for the CPU reference ...")
+        cpu = cpu_job.collect(p1_prefix)
+        if cpu:
+            log(f"[bench] CPU reference: {cpu['value']:.3e} edge-iterations/s ({cpu['sample']}); "
+                f"agrees with the GPU: {cpu.get('agrees_with_gpu')}")
 
     return {
         "metric": "edge-iterations/sec at k=10 (plain)",
@@ -297,7 +371,7 @@ def run_plain(args, kb, torch):
         "vs_baseline": None,
         "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "n": g.n, "m": g.m, "k": k, "recipe": w["desc"],
+        "config": {"workload": workload, "n": g.n, "m": g.m, "k": k, "recipe": w["desc"],
                    "seed": w["seed"], "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
@@ -408,9 +482,9 @@ def run_serve(args, kb, torch):
     import graphgen
     from paper_2204_05821_amd import serve
     t0 = time.perf_counter()
-    pool_h = [graphgen.serving_pool_graph(j) for j in range(args.serve_pool)]
-    pool = [serve.DeviceBackend.pin(g) for g in pool_h]
-    del pool_h
+    pool = []
+    for j in range(args.serve_pool):   # one host graph at a time: only the pinned copies stay
+        pool.append(serve.DeviceBackend.pin(graphgen.serving_pool_graph(j)))
     pool_m = [g.m for g in pool]
     log(f"[serve] pool of {len(pool)} graphs ({sum(pool_m)} edges) pinned in {time.perf_counter() - t0:.1f}s")
     budget = 200 * 10**9
@@ -487,16 +561,22 @@ def run_serve(args, kb, torch):
                          "speedup": fifo_s / cont_s, "identical_counts": cont_counts == fifo_counts,
                          "mean_jobs_per_tick": cont_st["mean_jobs_per_tick"]},
             "pool": {"graphs": len(pool), "edges": sum(pool_m)},
+            "shape": ("as configured: 256 pool graphs, 60 s of arrivals" if len(pool) == 256 and
+                      args.serve_seconds == 60 else f"reduced: {len(pool)} pool graphs, {args.serve_seconds:g} s "
+                                                     "of arrivals (configured: 256 graphs, 60 s)"),
             "latency": "arrival to counts on the host and ids on the device, H2D of the CSR included"}
 
 
 def main():
+    wall0 = time.perf_counter()
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--mode", default="all", choices=["all", "plain", "batched", "serve"])
-    ap.add_argument("--workload", default="rmat_s23_m100M_k10", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="rmat_rdf_s27_m1B_k10", choices=sorted(WORKLOADS))
+    ap.add_argument("--extra-workload", default="rmat_s23_m100M_k10",
+                    help="a second plain workload reported beside the headline in --mode all ('' = none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip per-kernel event timing")
     ap.add_argument("--autotune", action="store_true",
@@ -506,9 +586,9 @@ def main():
     ap.add_argument("--batch-graphs", type=int, default=4096)
     ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--tune-cache", default=None, help="JSON file for autotuner choices (default: none kept)")
-    ap.add_argument("--serve-pool", type=int, default=64)
+    ap.add_argument("--serve-pool", type=int, default=256)
     ap.add_argument("--serve-rate", type=float, default=200.0)
-    ap.add_argument("--serve-seconds", type=float, default=20.0)
+    ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--serve-capacity-jobs", type=int, default=200)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run the library's streaming copy kernel on this many MiB (bandwidth and counter "
@@ -519,6 +599,15 @@ def main():
               "(the sharding design is described in the design notes).", file=sys.stderr)
         sys.exit(2)
 
+    # Host inputs first: the CPU reference is forked before anything touches the GPU.
+    g = cpu_job = None
+    if args.mode in ("all", "plain") and not args.copy_probe_mib:
+        t0 = time.perf_counter()
+        g = make_graph(WORKLOADS[args.workload])
+        log(f"[bench] generated {args.workload}: n={g.n} m={g.m} in {time.perf_counter() - t0:.1f}s")
+        if not args.no_cpu_baseline:
+            cpu_job = CpuBaseline(g, WORKLOADS[args.workload])
+
     import torch
     import paper_2204_05821_amd as kb
     torch.cuda.set_device(torch.device("cuda:0"))
@@ -528,13 +617,21 @@ def main():
         return
     res = None
     if args.mode in ("all", "plain"):
-        res = run_plain(args, kb, torch)
+        res = run_plain(args, kb, torch, args.workload, g, cpu_job)
+        del g
+        if args.mode == "all" and args.extra_workload and args.extra_workload != args.workload:
+            t0 = time.perf_counter()
+            g2 = make_graph(WORKLOADS[args.extra_workload])
+            log(f"[bench] generated {args.extra_workload}: n={g2.n} m={g2.m} in {time.perf_counter() - t0:.1f}s")
+            res["plain_extra"] = run_plain(args, kb, torch, args.extra_workload, g2, None, extras=False)
+            del g2
     if args.mode in ("all", "batched"):
         bres = run_batched(args, kb, torch)
         res = bres if res is None else dict(res, batched=bres)
     if args.mode in ("all", "serve"):
         sres = run_serve(args, kb, torch)
         res = sres if res is None else dict(res, served=sres)
+    res["bench_wall_s"] = round(time.perf_counter() - wall0, 1)
     print(json.dumps(res), flush=True)
 
 

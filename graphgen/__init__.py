@@ -187,6 +187,44 @@ def from_edges(n: int, src, dst, lbl=None, vlabel=None, vlabel_ptr=None, name=""
     return Graph(n, row_ptr, col, el, vp, vl, name=name)
 
 
+def prefix_subgraph(g: Graph, vs: int) -> Graph:
+    """The rows of vertices [0, vs) of g, every vertex they name kept.
+
+    Vertices [0, vs) keep their ids; the other targets of those rows get ids
+    vs, vs + 1, ... in increasing order of their old id.  Every kept vertex
+    keeps its label set (or label); the other vertices of g are dropped.  Rows
+    of the renumbered targets are empty.
+    """
+    vs = max(0, min(int(vs), g.n))
+    e_end = int(g.row_ptr[vs])
+    cols = g.col[:e_end]
+    mark = np.zeros(g.n, dtype=bool)
+    mark[cols] = True
+    mark[:vs] = False
+    outside = np.flatnonzero(mark)
+    del mark
+    remap = np.arange(g.n, dtype=np.int64)
+    remap[outside] = vs + np.arange(len(outside), dtype=np.int64)
+    col = remap[cols].astype(np.int32)
+    del remap
+    ns = vs + len(outside)
+    rp = np.empty(ns + 1, dtype=np.int64)
+    rp[:vs + 1] = g.row_ptr[:vs + 1]
+    rp[vs + 1:] = e_end
+    keep = np.concatenate([np.arange(vs, dtype=np.int64), outside])
+    vp = vl = None
+    if g.vlabel_ptr is not None:
+        lens = g.vlabel_ptr[keep + 1] - g.vlabel_ptr[keep]
+        vp = np.zeros(ns + 1, dtype=np.int64)
+        np.cumsum(lens, out=vp[1:])
+        idx = np.repeat(g.vlabel_ptr[keep] - vp[:-1], lens) + np.arange(vp[-1], dtype=np.int64)
+        vl = np.ascontiguousarray(g.vlabel[idx], dtype=np.int32)
+    elif g.vlabel is not None:
+        vl = np.ascontiguousarray(g.vlabel[keep], dtype=np.int32)
+    el = None if g.elabel is None else g.elabel[:e_end].copy()
+    return Graph(ns, rp, col, el, vp, vl, name=f"{g.name}_rows{vs}")
+
+
 def transpose(g: Graph) -> Graph:
     """The inverse graph E^-1 with l_E^-1(y, x) = l_E(x, y) (Def. inverse-schema-element)."""
     src = np.repeat(np.arange(g.n, dtype=np.int32), np.diff(g.row_ptr))

@@ -75,6 +75,16 @@ def test_rmat_100M_k10():
     say("P1 equals the plain reference element by element")
 
 
+def check_prefix(g, host, shift, label):
+    """P1 on the first n >> shift vertices equals the plain reference run on those rows
+    (other targets renumbered; ids are numbered by first vertex, so the prefix agrees)."""
+    vs = max(1, g.n >> shift)
+    s = graphgen.prefix_subgraph(g, vs)
+    ref, _ = oracle.refine(s, 1)
+    assert np.array_equal(ref[0][:vs], host[1][:vs]), label
+    say(f"{label}: P1 on the first {vs} vertices ({s.m} entries) equals the plain reference")
+
+
 @pytest.mark.timeout(1200)
 def test_rdf_rmat_1B_k10():
     oracle.check_threads(16)
@@ -83,6 +93,20 @@ def test_rdf_rmat_1B_k10():
     host, counts = gpu_plain(g, 10)
     say("counts", counts)
     verify_chain(g, host, counts, "rdf_s27")
+    check_prefix(g, host, 6, "rdf_s27")
+
+
+@pytest.mark.timeout(1500)
+def test_rdf_rmat_2B_k10():
+    """The 2B-edge run (scale 28, seed 4) in the benchmark's launch configuration."""
+    oracle.check_threads(16)
+    g = graphgen.rmat_rdf(28, 2_000_000_000, seed=4)
+    say(f"RDF-like RMAT s28: n={g.n} m={g.m}")
+    host, counts = gpu_plain(g, 10)
+    say("counts", counts)
+    verify_chain(g, host, counts, "rdf_s28")
+    check_prefix(g, host, 8, "rdf_s28")
+    del host, g
 
 
 @pytest.mark.timeout(900)

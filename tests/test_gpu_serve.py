@@ -125,3 +125,48 @@ def test_tiny_budget_forces_queueing_on_device():
     srv, jobs = run_mix(graphs, ks, budget=one + 1024, cohort_edges=60_000, gap_s=0.0005)
     assert srv.peak_used <= one + 1024
     check_jobs(graphs, ks, jobs, "tiny-budget")
+
+
+def test_serving_pool_jobs_up_to_24M_edges():
+    """Jobs of the serving workload's own pool (RMAT, m log-uniform 10k-50M, labels as the
+    100M-edge recipe): small pool graphs share cohorts, three jobs of 10-24M edges run
+    beside them.  Every job equals its solo refinement; the small ones equal the plain
+    reference, the large ones pass the property checker step by step."""
+    oracle.check_threads(16)
+    small = [1, 3, 8, 17, 20, 21, 26, 28, 41, 43]
+    big = [11, 56, 44]
+    order = [1, 11, 3, 8, 56, 17, 20, 44, 21, 26, 28, 41, 43]
+    assert sorted(order) == sorted(small + big)
+    graphs = [graphgen.serving_pool_graph(j) for j in order]
+    rnd = random.Random(17)
+    ks = [rnd.randint(1, 10) for _ in graphs]
+    for i, j in enumerate(order):
+        if j in big:
+            ks[i] = 10 - i % 3
+    print(f"[serve] pool jobs {order}, m={[g.m for g in graphs]}, k={ks}", flush=True)
+    assert max(g.m for g in graphs) >= 20_000_000
+    srv, jobs = run_mix(graphs, ks, budget=200 << 30, cohort_edges=2_000_000, pin=True, burst=4, gap_s=0.005)
+    st = srv.stats()
+    print(f"[serve] stats {st}", flush=True)
+    assert st["units"] < len(graphs)
+    for i, (g, k, j) in enumerate(zip(graphs, ks, jobs)):
+        assert j.error is None, (i, j.error)
+        got = [o.cpu().numpy() for o in (j.outputs or [])]
+        assert len(got) == k
+        exp_ids, exp_counts = alone(g, k)
+        assert j.counts == exp_counts, (i, j.counts, exp_counts)
+        for step in range(k):
+            assert np.array_equal(got[step], exp_ids[step]), (i, step)
+        if order[i] in small:
+            ref_ids, ref_counts = oracle.refine(g, k)
+            assert j.counts == list(ref_counts)
+            for step in range(k):
+                assert np.array_equal(got[step], ref_ids[step]), (i, step)
+        else:
+            p0, c0 = oracle.initial(g)
+            prev = p0
+            for step in range(k):
+                assert oracle.check_step(g, prev, got[step]) == j.counts[step], (i, step)
+                prev = got[step]
+        print(f"[serve] job {order[i]} (m={g.m}, k={k}) checked", flush=True)
+        j.outputs = None

@@ -317,6 +317,22 @@ def test_row_shuffle_and_duplicates_do_not_matter():
     assert a == b and ca == cb
 
 
+@pytest.mark.parametrize("maker", ["tiny", "rmat", "rdf"])
+def test_prefix_rows_keep_the_first_step(maker):
+    """The rows of the first vs vertices, with all other targets renumbered, give the whole
+    graph's P0 and P1 on those vertices: a step only reads a vertex's own row and its
+    targets' previous blocks, and ids are numbered by first vertex."""
+    g = {"tiny": lambda: graphgen.tiny(seed=4),
+         "rmat": lambda: graphgen.rmat(12, 40000, seed=5),
+         "rdf": lambda: graphgen.rmat_rdf(12, 30000, seed=6, types=50, elabels=40)}[maker]()
+    full, fc = oracle_all(g, 2)
+    for vs in (1, g.n // 7, g.n // 2, g.n):
+        s = graphgen.prefix_subgraph(g, vs)
+        assert s.m == int(g.row_ptr[vs])
+        sub, _ = oracle_all(s, 1)
+        assert sub[0][:vs] == full[0][:vs] and sub[1][:vs] == full[1][:vs], vs
+
+
 def test_label_bijection_does_not_matter():
     g = graphgen.tiny(seed=6, n=3000, m=9000)
     h = graphgen.Graph(g.n, g.row_ptr, g.col, (g.elabel * 7919 + 13).astype(np.int32), None,
