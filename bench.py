@@ -17,7 +17,7 @@ run, --workload rmat_rdf_s28_m2B_k10, for BTC2B).
 Prints one JSON line with the throughput, a roofline entry for the dominant
 kernel (timed with HIP events inside the timed region) and the CPU reference
 timed on a bounded sample of the same graph.  The sample is the rows of the
-first n/32 vertices with their targets renumbered compactly; its first
+first n/8 vertices with their targets renumbered compactly; its first
 refinement step equals the full graph's on those vertices (ids are numbered
 by first vertex), which the run checks against the GPU.  The reference runs
 in a child process forked before the GPU is touched, so it overlaps the GPU
@@ -38,11 +38,14 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s (published)
+CPU_SAMPLE_SHIFT = 3   # the CPU reference refines the rows of the first n >> 3 vertices
 
 WORKLOADS = {
     "rmat_s23_m100M_k10": dict(kind="rmat", scale=23, m=100_000_000, seed=2, k=10,
@@ -127,6 +130,13 @@ def measured_traffic(kernel: str, workload: str):
         return None
 
 
+def pair_bits(g) -> int:
+    """Bits of the largest (edge label, block id) pair of a graph: label bits + block-id bits."""
+    import numpy as np
+    lb = int(np.max(g.elabel)).bit_length() if g.elabel is not None and g.m else 0
+    return max(1, int(max(1, g.n) - 1).bit_length()) + lb
+
+
 def host_info():
     """Cores this process may use, the machine's core count and the CPU model."""
     model = None
@@ -150,7 +160,7 @@ def _cpu_child(g, w, conn):
         import graphgen
         import oracle
         t0 = time.perf_counter()
-        vs = max(1, g.n >> 5)
+        vs = max(1, g.n >> CPU_SAMPLE_SHIFT)
         s = graphgen.prefix_subgraph(g, vs)
         build_s = time.perf_counter() - t0
         t0 = time.perf_counter()
@@ -226,14 +236,16 @@ def run_plain(args, kb, torch, workload, g, cpu_job=None, extras=True):
         from paper_2204_05821_amd import tune
         holder = {}
 
-        def make(cand):
-            rr = kb.Refiner(rp, col, el, vl, vp, kmax=k, tuning=kb.tuning(**cand))
+        def make(cand):   # every candidate on the first candidate's workspace
+            rr = kb.Refiner(rp, col, el, vl, vp, kmax=k, tuning=kb.tuning(**cand), workspace=holder.get("ws"))
+            holder["ws"] = rr.workspace
             holder["outs"] = holder.get("outs") or rr.alloc_outputs(k)
             return rr
 
         t0 = time.perf_counter()
         best, tune_report = tune.autotune(make, lambda rr: rr.refine(k, out=holder["outs"]),
-                                          key="plain|" + tune.degree_signature(g.row_ptr), reps=2,
+                                          key="plain|" + tune.degree_signature(g.row_ptr), rounds=3, reps=1,
+                                          knobs=tune.knobs_for(int(np.diff(g.row_ptr).max()), pair_bits(g)),
                                           cache_path=args.tune_cache)
         del holder
         log(f"[bench] autotune {time.perf_counter() - t0:.1f}s: best {best}; {tune_report['ms']}")
@@ -265,7 +277,7 @@ def run_plain(args, kb, torch, workload, g, cpu_job=None, extras=True):
     ms_per_step = max(gpu_ms, wall * 1e3) / args.steps
     value = g.m * k * args.steps / (ms_per_step * args.steps / 1e3)
     log(f"[bench] {args.steps} steps: {ms_per_step:.3f} ms/step ({gpu_ms:.1f} ms events, {wall * 1e3:.1f} ms wall)")
-    p1_prefix = outs[0][:max(1, g.n >> 5)].cpu().numpy() if cpu_job is not None else None
+    p1_prefix = outs[0][:max(1, g.n >> CPU_SAMPLE_SHIFT)].cpu().numpy() if cpu_job is not None else None
 
     kernels = {}
     roofline = None
@@ -409,20 +421,24 @@ def run_batched(args, kb, torch):
 
     holder = {}
 
-    def make(cand):
-        b = kb.Batch(*d, off, kmax=k, tuning=kb.tuning(**cand), graphs=True)
+    def make(cand):   # every candidate on the first candidate's workspace
+        b = kb.Batch(*d, off, kmax=k, tuning=kb.tuning(**cand), graphs=True, workspace=holder.get("ws"))
+        holder["ws"] = b.workspace
         holder["outs"] = holder.get("outs") or b.alloc_outputs(k)
         return b
 
     def run(b):
         return b.refine(k, out=holder["outs"])
 
+    max_deg = max(int(np.diff(gr.row_ptr).max()) if gr.m else 0 for gr in graphs)
+    pbits = max(int(max(1, gr.n) - 1).bit_length() for gr in graphs) + max(
+        int(gr.elabel.max()).bit_length() if gr.elabel is not None and gr.m else 0 for gr in graphs)
     t0 = time.perf_counter()
-    best, report = tune.autotune(make, run, key="batch|" + tune.degree_signature(d[0].cpu().numpy()), reps=1,
-                                 cache_path=args.tune_cache)
+    best, report = tune.autotune(make, run, key="batch|" + tune.degree_signature(d[0].cpu().numpy()), rounds=3,
+                                 reps=1, knobs=tune.knobs_for(max_deg, pbits), cache_path=args.tune_cache)
     log(f"[batched] autotune {time.perf_counter() - t0:.1f}s: best {best}; {report['ms']}")
     t0 = time.perf_counter()
-    b = kb.Batch(*d, off, kmax=k, tuning=kb.tuning(**best), graphs=True)
+    b = kb.Batch(*d, off, kmax=k, tuning=kb.tuning(**best), graphs=True, workspace=holder["ws"])
     torch.cuda.synchronize()
     create_ms = (time.perf_counter() - t0) * 1e3
     outs = holder["outs"]
@@ -471,7 +487,8 @@ def run_batched(args, kb, torch):
             "ms_per_pass": batched_s * 1e3, "per_graph_plain": {"value": m_total * k / plain_s,
                                                                  "ms_per_pass": plain_s * 1e3},
             "speedup_vs_per_graph": plain_s / batched_s, "identical_to_per_graph": bool(same),
-            "tuning": best, "autotune_ms": report["ms"], "create_ms": round(create_ms, 1),
+            "tuning": best, "autotune_ms": report["ms"][:8], "autotune_samples": report.get("samples"),
+            "create_ms": round(create_ms, 1),
             "recipe": "graph g: m_g log-uniform 1e3..2e6; even g uniform-random n=max(16,m/8), odd g RMAT "
                       "(0.57,0.19,0.19,0.05) scale ceil(log2(m/8)); 16 vertex and 32 edge labels uniform"}
 

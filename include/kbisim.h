@@ -89,15 +89,21 @@ typedef struct kbisim_ctx kbisim_ctx;
  *                    2048 with 32-bit set keys, 1024 with 64-bit keys)
  *   hub_chunk        entries per hub staging workgroup: 2048 (default) or 4096
  *   hub_part_target  expected entries per hub partition: 1024 or 2048 (default)
- *   key_bits         width of pair keys in LDS hash sets: 32 (default; used
- *                    when every (edge label, block id) pair fits in 31 bits,
- *                    else 64) or 64 (always)                                  */
+ *   key_bits         pair keys in LDS hash sets: 0 (default) = 32-bit keys,
+ *                    exact (label, block) when every pair fits in 31 bits and
+ *                    a 32-bit hash of the pair otherwise; 32 = hashed 32-bit
+ *                    keys always; 64 = exact 64-bit keys always.  With hashed
+ *                    keys the signature is deduplicated by key and every
+ *                    grouping is still confirmed on the pairs themselves.
+ *   scan_items       vertices per thread in the numbering scan: 8 or 16
+ *                    (default)                                                */
 typedef struct {
   int range_edges;
   int hub_chunk;
   int hub_part_target;
   int key_bits;
-  int reserved[4];
+  int scan_items;
+  int reserved[3];
 } kbisim_tuning;
 
 /* Workspace bytes needed by kbisim_create for a graph of g->n vertices,

@@ -44,15 +44,16 @@ class _Graph(ctypes.Structure):
 class Tuning(ctypes.Structure):
     """Launch-shape parameters (0 = default); results never depend on them."""
     _fields_ = [("range_edges", ctypes.c_int), ("hub_chunk", ctypes.c_int), ("hub_part_target", ctypes.c_int),
-                ("key_bits", ctypes.c_int), ("reserved", ctypes.c_int * 4)]
+                ("key_bits", ctypes.c_int), ("scan_items", ctypes.c_int), ("reserved", ctypes.c_int * 3)]
 
     def as_dict(self):
         return {"range_edges": self.range_edges, "hub_chunk": self.hub_chunk,
-                "hub_part_target": self.hub_part_target, "key_bits": self.key_bits}
+                "hub_part_target": self.hub_part_target, "key_bits": self.key_bits, "scan_items": self.scan_items}
 
 
-def tuning(range_edges: int = 0, hub_chunk: int = 0, hub_part_target: int = 0, key_bits: int = 0) -> Tuning:
-    return Tuning(range_edges, hub_chunk, hub_part_target, key_bits)
+def tuning(range_edges: int = 0, hub_chunk: int = 0, hub_part_target: int = 0, key_bits: int = 0,
+           scan_items: int = 0) -> Tuning:
+    return Tuning(range_edges, hub_chunk, hub_part_target, key_bits, scan_items)
 
 
 _LIB = None
@@ -159,6 +160,16 @@ def _stream_handle(stream) -> ctypes.c_void_p:
     return ctypes.c_void_p(s.cuda_stream)
 
 
+def _workspace(given: Optional[torch.Tensor], nbytes: int, device) -> torch.Tensor:
+    """The caller's workspace (a uint8 device tensor of at least nbytes), or a new one."""
+    if given is None:
+        return torch.empty(nbytes, dtype=torch.uint8, device=device)
+    _check(given, torch.uint8, "workspace", device)
+    if given.numel() < nbytes:
+        raise ValueError(f"workspace holds {given.numel()} bytes, {nbytes} needed")
+    return given
+
+
 class Refiner:
     """A context bound to one graph: P0 and the degree schedule are computed once.
 
@@ -167,7 +178,8 @@ class Refiner:
 
     def __init__(self, row_ptr: torch.Tensor, col: torch.Tensor, elabel: Optional[torch.Tensor] = None,
                  vlabel: Optional[torch.Tensor] = None, vlabel_ptr: Optional[torch.Tensor] = None,
-                 kmax: int = 10, stream=None, tuning: Optional[Tuning] = None, graphs: bool = False):
+                 kmax: int = 10, stream=None, tuning: Optional[Tuning] = None, graphs: bool = False,
+                 workspace: Optional[torch.Tensor] = None):
         lib = _lib()
         self.device = row_ptr.device
         self.row_ptr = _check(row_ptr, torch.int64, "row_ptr", self.device)
@@ -187,7 +199,7 @@ class Refiner:
             raise KbisimError(rc, "kbisim_workspace_bytes")
         self.workspace_bytes = int(nbytes.value)
         with torch.cuda.device(self.device):
-            self.workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
+            self.workspace = _workspace(workspace, self.workspace_bytes, self.device)
             if stream is None:
                 # graph capture needs a stream of its own (default priority)
                 stream = torch.cuda.Stream(device=self.device) if graphs else torch.cuda.current_stream()
@@ -404,7 +416,7 @@ class Batch:
     """
 
     def __init__(self, row_ptr, col, elabel, vlabel, vlabel_ptr, vert_off, kmax: int = 10, stream=None,
-                 tuning: Optional[Tuning] = None, graphs: bool = False):
+                 tuning: Optional[Tuning] = None, graphs: bool = False, workspace: Optional[torch.Tensor] = None):
         import numpy as np
         lib = _lib()
         self.device = row_ptr.device
@@ -427,7 +439,7 @@ class Batch:
             raise KbisimError(rc, "kbisim_batch_workspace_bytes")
         self.workspace_bytes = int(nbytes.value)
         with torch.cuda.device(self.device):
-            self.workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
+            self.workspace = _workspace(workspace, self.workspace_bytes, self.device)
             if stream is None:
                 stream = torch.cuda.Stream(device=self.device) if graphs else torch.cuda.current_stream()
             self.stream = stream

@@ -86,7 +86,7 @@ Plan make_plan(int64_t n, int64_t m, int64_t nl, int kmax, int64_t num_graphs) {
   p.npart_max = big / (HUB_PART_TARGET / 4) + 2 * p.nhub_max + 1;
   p.ngchunk_max = big / HUB_GCHUNK + p.nhub_max + 1;
   p.npoff_max = big / 16 + 4 * (HUB_PMAX + 1) + p.nchunk_max;
-  p.ntiles = (int64_t)(N + SCAN_TILE - 1) / SCAN_TILE + 1;
+  p.ntiles = (int64_t)(N + 256 * SCAN_ITEMS_MIN - 1) / (256 * SCAN_ITEMS_MIN) + 1;
   p.hubset_slots = 2 * big + 64;
   p.ncounter_steps = kmax + 4;
   p.off_H = take(8 * N);
@@ -150,7 +150,9 @@ struct Tuning {
   int range_edges = 0;  // 0: by key width (range_cap)
   int hub_chunk = 2048;
   int hub_part_target = HUB_PART_TARGET;
-  int key_bits = 0;  // LDS set keys: 0 = narrow (32-bit) where pairs fit, 64 = always 64-bit
+  int key_bits = 0;  // LDS set keys: 0 = 32-bit (exact where pairs fit, else hashed), 32 = hashed, 64 = 64-bit
+  int hub_parts_cap = HUB_PMAX;  // most partitions per staged hub (a smaller cap is a test knob)
+  int scan_items = SCAN_ITEMS;   // vertices per thread in the numbering scan: 8 or 16
 };
 
 struct GraphKey {
@@ -183,13 +185,15 @@ struct kbisim_ctx {
   HubGChunk *gchunks;
   Schedule sched;  // graph rows
   u64 hmask = ~0ULL;
+  u32 kmask = 0xFFFFFFFFu;  // bits kept of hashed set keys (test knob)
   u64 tmask_steps = 0;   // grouping-table mask of refinement steps (sized by vertices with edges)
   bool work_eff = false;  // skip singleton blocks, stop at the fixpoint
   int we_steps = 0;       // steps computed by the last work-efficient call
   unsigned char *single[2] = {nullptr, nullptr};  // singleton flags of the last two partitions
   u32 *multi = nullptr;  // stamps of heads that have a non-head member
   u32 prof_mask = ~0u;   // kernel kinds timed by the profiler
-  bool narrow = false;  // 32-bit LDS keys: (edge label << pb) | block fits in 31 bits
+  bool narrow = false;  // 32-bit LDS keys
+  bool hashed = false;  // ... that hash the pair (it does not fit 31 bits, or 32-bit keys were asked for)
   u32 pb = 31;
   u32 max_label = 0;    // largest edge label (0 without labels)
   bool packed = false;  // edge labels packed above the target ranks in gcol
@@ -325,7 +329,7 @@ int range_cap(const kbisim_ctx *c, bool wide_keys) {
 
 int hub_parts_for(const Tuning &t, int64_t d) {
   int P = 1;
-  while ((int64_t)P * t.hub_part_target < d && P < HUB_PMAX) P <<= 1;
+  while ((int64_t)P * t.hub_part_target < d && P < t.hub_parts_cap) P <<= 1;
   return P;
 }
 
@@ -333,6 +337,23 @@ int hub_parts_for(const Tuning &t, int64_t d) {
 bool separate_labels(const kbisim_ctx *c) { return !c->packed && c->g.elabel != nullptr; }
 // The separate labels the kernels read: the rank-sorted copy, if made.
 const int32_t *sep_labels(const kbisim_ctx *c) { return c->glab ? c->glab : c->g.elabel; }
+
+// Dense ids numbered by first vertex: out[v] = number of heads (rep[v] == v)
+// before v for heads, -1 for the others; the head count into *count_dev.
+int numbering_scan(kbisim_ctx *c, int n, int *out, int64_t *count_dev) {
+  const int items = c->tune.scan_items;
+  const int ntiles = (int)blocks_for(n, 256 * items);
+  const int aligned = ((uintptr_t)out & 15) == 0;
+  if (items == 8) k_tile_count<8><<<(unsigned)ntiles, 256, 0, c->stream>>>(n, c->rep, c->tiles);
+  else k_tile_count<16><<<(unsigned)ntiles, 256, 0, c->stream>>>(n, c->rep, c->tiles);
+  LAUNCH_CHECK();
+  k_tile_scan<<<1, 1024, 0, c->stream>>>(ntiles, c->tiles, count_dev);
+  LAUNCH_CHECK();
+  if (items == 8) k_scan_write<8><<<(unsigned)ntiles, 256, 0, c->stream>>>(n, c->rep, c->tiles, out, aligned);
+  else k_scan_write<16><<<(unsigned)ntiles, 256, 0, c->stream>>>(n, c->rep, c->tiles, out, aligned);
+  LAUNCH_CHECK();
+  return 0;
+}
 
 // The vertices with at least one entry, in order, into c->nzv (s.nzv then
 // points there): flags, the head scan of the numbering, and a scatter.  Uses
@@ -342,13 +363,8 @@ int build_nonempty_list(kbisim_ctx *c, Schedule &s) {
   if (n == 0) return 0;
   k_mark_rows<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, c->g.row_ptr, c->rep);
   LAUNCH_CHECK();
-  const int ntiles = (int)blocks_for(n, SCAN_TILE);
-  k_tile_count<<<(unsigned)ntiles, 256, 0, c->stream>>>(n, c->rep, c->tiles);
-  LAUNCH_CHECK();
-  k_tile_scan<<<1, 1024, 0, c->stream>>>(ntiles, c->tiles, c->dcounts + (c->plan.ncounter_steps - 1));
-  LAUNCH_CHECK();
-  k_scan_write<<<(unsigned)ntiles, 256, 0, c->stream>>>(n, c->rep, c->tiles, c->vlist, ((uintptr_t)c->vlist & 15) == 0);
-  LAUNCH_CHECK();
+  int rc = numbering_scan(c, n, c->vlist, c->dcounts + (c->plan.ncounter_steps - 1));
+  if (rc) return rc;
   k_list_from_ids<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, c->vlist, c->nzv);
   LAUNCH_CHECK();
   s.nzv = c->nzv;
@@ -834,10 +850,14 @@ int launch_ranges_k(kbisim_ctx *c, const Src &src, const Schedule &s, int zfresh
 
 template <class Src>
 int launch_ranges(kbisim_ctx *c, const Src &src, const Schedule &s, int zfresh, const unsigned char *skip) {
-  if constexpr (Src::GRAPH) {
-    if (c->narrow) return launch_ranges_k<Src, u32>(c, src, s, zfresh, skip);
+  if constexpr (Src::HASHED) {
+    return launch_ranges_k<Src, u32>(c, src, s, zfresh, skip);
+  } else {
+    if constexpr (Src::GRAPH) {
+      if (c->narrow) return launch_ranges_k<Src, u32>(c, src, s, zfresh, skip);
+    }
+    return launch_ranges_k<Src, u64>(c, src, s, zfresh, skip);
   }
-  return launch_ranges_k<Src, u64>(c, src, s, zfresh, skip);
 }
 
 // Staged hub rows: chunk dedupe and partitioned staging, then per-partition
@@ -886,7 +906,9 @@ int run_step(kbisim_ctx *c, const Src &src, const Schedule &s, int *out, int64_t
   if (s.nhub) {
     const int *hubs = c->lists + s.hub_off;
     if (s.nchunks) {
-      if constexpr (Src::GRAPH) {
+      if constexpr (Src::HASHED) {
+        rc = launch_hub_staged<Src, u32>(c, src, s, hubs, skip_in);
+      } else if constexpr (Src::GRAPH) {
         rc = c->narrow ? launch_hub_staged<Src, u32>(c, src, s, hubs, skip_in)
                        : launch_hub_staged<Src, u64>(c, src, s, hubs, skip_in);
       } else {
@@ -945,13 +967,7 @@ int run_step(kbisim_ctx *c, const Src &src, const Schedule &s, int *out, int64_t
   }
   {
     ProfScope ps(c, KBISIM_K_SCAN);
-    const int ntiles = (int)blocks_for(n, SCAN_TILE);
-    k_tile_count<<<(unsigned)ntiles, 256, 0, c->stream>>>(n, c->rep, c->tiles);
-    LAUNCH_CHECK();
-    k_tile_scan<<<1, 1024, 0, c->stream>>>(ntiles, c->tiles, count_dev);
-    LAUNCH_CHECK();
-    k_scan_write<<<(unsigned)ntiles, 256, 0, c->stream>>>(n, c->rep, c->tiles, out, ((uintptr_t)out & 15) == 0);
-    LAUNCH_CHECK();
+    if ((rc = numbering_scan(c, n, out, count_dev))) return rc;
   }
   {
     ProfScope ps(c, KBISIM_K_ASSIGN);
@@ -991,10 +1007,17 @@ int enqueue_steps(kbisim_ctx *c, const int32_t *prev, int i0, int k, int32_t *co
       return run_step(c, src, c->sched, dst, &c->dcounts[i], c->counters + CNT_STRIDE * i, careful,
                       c->gpid[(i + 1) & 1], i == 0, skip_in, single_out);
     };
-    if (separate_labels(c))
-      rc = step(GraphSrcT<true>{c->g.row_ptr, c->gcol, sep_labels(c), c->gpid[i & 1], prev, c->pb, c->rbits});
-    else
-      rc = step(GraphSrcT<false>{c->g.row_ptr, c->gcol, nullptr, c->gpid[i & 1], prev, c->pb, c->rbits});
+    const int32_t *lab = separate_labels(c) ? sep_labels(c) : nullptr;
+    if (c->hashed) {
+      if (lab)
+        rc = step(GraphSrcT<true, true>{c->g.row_ptr, c->gcol, lab, c->gpid[i & 1], prev, c->pb, c->rbits, c->kmask});
+      else
+        rc = step(
+            GraphSrcT<false, true>{c->g.row_ptr, c->gcol, nullptr, c->gpid[i & 1], prev, c->pb, c->rbits, c->kmask});
+    } else {
+      if (lab) rc = step(GraphSrcT<true>{c->g.row_ptr, c->gcol, lab, c->gpid[i & 1], prev, c->pb, c->rbits});
+      else rc = step(GraphSrcT<false>{c->g.row_ptr, c->gcol, nullptr, c->gpid[i & 1], prev, c->pb, c->rbits});
+    }
     if (rc) return rc;
     if (batch) {
       k_rebase<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, c->gid, c->first, dst, out[i]);
@@ -1171,6 +1194,10 @@ int read_tuning(const kbisim_tuning *t, Tuning &out) {
     if (t->key_bits != 32 && t->key_bits != 64) return KBISIM_EINVAL;
     out.key_bits = t->key_bits;
   }
+  if (t->scan_items) {
+    if (t->scan_items != 8 && t->scan_items != 16) return KBISIM_EINVAL;
+    out.scan_items = t->scan_items;
+  }
   return 0;
 }
 
@@ -1254,6 +1281,20 @@ int create_impl(const kbisim_graph *g, int kmax, const kbisim_tuning *tuning, vo
     int b = atoi(dbg);
     if (b >= 0 && b < 64) c->hmask = b == 0 ? 0ULL : ((1ULL << b) - 1ULL);
   }
+  // Test knob: at most this many partitions per staged hub, so that hub
+  // partitions overflow their sets and take the sub-pass path.
+  const char *pdbg = getenv("KBISIM_DEBUG_HUB_PARTS");
+  if (pdbg && *pdbg) {
+    int q = atoi(pdbg);
+    if (q >= 1 && q <= HUB_PMAX && (q & (q - 1)) == 0) c->tune.hub_parts_cap = q;
+  }
+  // Test knob: keep only this many bits of hashed set keys, so that keys
+  // collide inside rows (the exact check must still separate the pair sets).
+  const char *kdbg = getenv("KBISIM_DEBUG_KEY_BITS");
+  if (kdbg && *kdbg) {
+    int b = atoi(kdbg);
+    if (b >= 1 && b < 32) c->kmask = (1u << b) - 1u;
+  }
 
   auto fail = [&](int code) {
     delete c;
@@ -1312,7 +1353,11 @@ int create_impl(const kbisim_graph *g, int kmax, const kbisim_tuning *tuning, vo
       c->packed = true;
       c->rbits = rb;
     }
-    c->narrow = c->tune.key_bits != 64 && pb + lb <= 31;
+    // 32-bit set keys unless 64-bit ones are asked for: exact when the label
+    // and reduced block fit 31 bits together, else a hash of the pair
+    // (key_bits = 32 asks for hashed keys in any case)
+    c->narrow = c->tune.key_bits != 64;
+    c->hashed = c->narrow && (c->tune.key_bits == 32 || pb + lb > 31);
   }
 
   if (num_graphs > 0) {

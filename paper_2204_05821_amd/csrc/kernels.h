@@ -61,8 +61,9 @@ constexpr int HUB_PSLOTS_WIDE = 4096;
 constexpr int64_t HUB_STAGED_MAX = (int64_t)HUB_PMAX * HUB_PSLOTS / 2;
 constexpr int64_t HUB_STAGED_MAX_WIDE = (int64_t)HUB_PMAX * HUB_PSLOTS_WIDE / 2;
 constexpr int HUB_GCHUNK = 8192;     // entries per workgroup in the global-set path
-constexpr int SCAN_ITEMS = 16;       // items per thread in the scan
+constexpr int SCAN_ITEMS = 16;       // items per thread in the 64-bit offset scans (and the numbering, by default)
 constexpr int SCAN_TILE = 256 * SCAN_ITEMS;
+constexpr int SCAN_ITEMS_MIN = 8;    // smallest tunable items per thread of the numbering scan
 
 // Device-resident epoch state (read by kernels at launch, advanced by
 // k_advance), so a captured sequence of steps can be replayed.
@@ -106,6 +107,13 @@ __device__ inline u32 set_hash(u64 p) {
   return h ^ (h >> 15);
 }
 __device__ inline u32 part_hash(u64 p) { return (u32)fmix64(p ^ 0x6a09e667f3bcc909ULL); }
+__device__ inline u32 sub_hash(u64 p) { return (u32)(fmix64(p ^ 0xa0761d6478bd642fULL) >> 32); }
+// Hashed 32-bit set key of a 64-bit pair (bits 16..47 of a Murmur3 fmix64);
+// never the empty marker 0xFFFFFFFF.
+__device__ inline u32 pair_key32(u64 p) {
+  const u32 k = (u32)(fmix64(p ^ 0x3c6ef372fe94f82bULL) >> 16);
+  return k == 0xFFFFFFFFu ? 0xFFFFFFFEu : k;
+}
 __device__ inline u64 finalize_key(u64 acc, u32 dc, u32 own) {
   return fmix64(acc + fmix64((((u64)own) << 32 | (u64)dc) ^ 0xc2b2ae3d27d4eb4fULL));
 }
@@ -121,9 +129,12 @@ __device__ inline u64 finalize_key(u64 acc, u32 dc, u32 own) {
 // lines, which roughly halves the cost of the per-entry random gather.
 // SEP: edge labels come from their own array (elabel); otherwise they sit
 // above the rank in gcol (or there are none), and elabel is unused.
-template <bool SEP>
+// HK: 32-bit set keys are a hash of the pair (used when the label and the
+// reduced block do not fit 31 bits together); see key32_of.
+template <bool SEP, bool HK = false>
 struct GraphSrcT {
   static constexpr bool GRAPH = true;
+  static constexpr bool HASHED = HK;
   const int64_t *row_ptr;
   const int32_t *gcol;    // targets renumbered by in-degree rank (and, packed, their labels)
   const int32_t *elabel;  // the labels when SEP
@@ -142,6 +153,9 @@ struct GraphSrcT {
   // otherwise rbits = 31 and the label comes from elabel (SEP) or is 0.
   // Packing halves the streamed bytes per entry.
   u32 rbits;
+  // bits kept of hashed keys (all but for tests that make key collisions routine)
+  u32 kmask = 0xFFFFFFFFu;
+  __device__ inline u32 hkey(u64 p) const { return pair_key32(p) & kmask; }
   __device__ inline u32 pmask() const { return pb >= 31 ? 0x7FFFFFFFu : (1u << pb) - 1u; }
   // (label, rank of the target) of entry e; streamed arrays are read
   // non-temporally so they do not evict the gather targets from the L2
@@ -183,19 +197,35 @@ struct GraphSrcT {
     return pair_of(l, r);
   }
   __device__ inline u32 own(int v) const { return (u32)pid[v]; }
-  // Narrow form of a pair, used inside LDS sets when every edge label and
-  // reduced block id fit together in 31 bits: (label << pb) | block.
-  __device__ inline u32 key32_of(u32 l, u32 r) const { return (l << pb) | ((u32)gpid[r] & pmask()); }
+  // Narrow form of a pair, used inside LDS sets.  When every edge label and
+  // reduced block id fit together in 31 bits it is exact: (label << pb) |
+  // block.  Otherwise (HK) it is a 32-bit hash of the pair.  Deduplicating
+  // and summing hashed keys gives a function of the signature (equal pair
+  // sets give equal key sets), so equal signatures still get equal key
+  // hashes; the distinct count is then the number of distinct keys, and the
+  // exact check compares pair sets in both directions (a key collision
+  // inside a row could otherwise make a proper subset look equal).
+  __device__ inline u32 key32_of(u32 l, u32 r) const {
+    if constexpr (HK) return hkey(pair_of(l, r));
+    else return (l << pb) | ((u32)gpid[r] & pmask());
+  }
   __device__ inline u32 key32(int64_t e) const {
     u32 l, r;
     entry(e, l, r);
     return key32_of(l, r);
   }
-  __device__ inline u64 wide(u32 q) const { return ((u64)(q >> pb) << 31) | (u64)(q & pmask()); }
+  // The value a distinct narrow key contributes to the key-hash sum: the
+  // pair itself for exact keys (so every tier mixes the same values), the
+  // key for hashed ones.
+  __device__ inline u64 mixin(u32 q) const {
+    if constexpr (HK) return (u64)q;
+    else return ((u64)(q >> pb) << 31) | (u64)(q & pmask());
+  }
 };
 
 struct LabelSrc {
   static constexpr bool GRAPH = false;
+  static constexpr bool HASHED = false;
   const int64_t *ptr;  // may be null: one label per vertex
   const int32_t *lab;
   const int32_t *gid;  // may be null; in a batch, the graph of each vertex (P0 never joins graphs)
@@ -232,7 +262,7 @@ struct Keys<u64> {
   template <class Src>
   __device__ static inline u64 from(const Src &s, u32 l, u32 r) { return s.pair_of(l, r); }
   template <class Src>
-  __device__ static inline u64 wide(const Src &, u64 p) { return p; }
+  __device__ static inline u64 mixin(const Src &, u64 p) { return p; }
   __device__ static inline u32 hash(u64 p) { return set_hash(p); }
 };
 template <>
@@ -243,7 +273,7 @@ struct Keys<u32> {
   template <class Src>
   __device__ static inline u32 from(const Src &s, u32 l, u32 r) { return s.key32_of(l, r); }
   template <class Src>
-  __device__ static inline u64 wide(const Src &s, u32 q) { return s.wide(q); }
+  __device__ static inline u64 mixin(const Src &s, u32 q) { return s.mixin(q); }
   __device__ static inline u32 hash(u32 q) {
     const u32 h = q * 0x9E3779B1u;
     return h ^ (h >> 15);
@@ -584,7 +614,7 @@ __global__ void __launch_bounds__(256) k_sig_range(Src src, const Range *__restr
       u32 sl = (u32)scale_to(KO::hash(p), sz);
       while (true) {
         const K old = atomicCAS(&set[sl], KO::EMPTY, p);
-        if (old == KO::EMPTY) { a += mix_pair(KO::wide(src, p)); ++c; break; }
+        if (old == KO::EMPTY) { a += mix_pair(KO::mixin(src, p)); ++c; break; }
         if (old == p) break;
         sl = (sl + 1 == sz) ? 0u : sl + 1;
       }
@@ -649,7 +679,7 @@ __global__ void __launch_bounds__(256) k_sig_range(Src src, const Range *__restr
         }
         const K p = set[sidx];
         if (p != KO::EMPTY) {
-          a += mix_pair(KO::wide(src, p));
+          a += mix_pair(KO::mixin(src, p));
           ++c;
         }
       }
@@ -721,7 +751,7 @@ __global__ void __launch_bounds__(NT) k_sig_row(Src src, const Range *__restrict
     u32 sl = (u32)scale_to(KO::hash(p), sz);
     while (true) {
       const K old = atomicCAS(&set[sl], KO::EMPTY, p);
-      if (old == KO::EMPTY) { a += mix_pair(KO::wide(src, p)); ++c; break; }
+      if (old == KO::EMPTY) { a += mix_pair(KO::mixin(src, p)); ++c; break; }
       if (old == p) break;
       sl = (sl + 1 == sz) ? 0u : sl + 1;
     }
@@ -858,6 +888,7 @@ __global__ void __launch_bounds__(256) k_hub_reduce(Src src, const HubPart *__re
   __shared__ int wtot[4];
   __shared__ u64 sh_acc[4];
   __shared__ u32 sh_cnt[4];
+  __shared__ u32 sh_fill[2];  // distinct keys in the set, overflow flag
   const HubPart hp = parts[blockIdx.x];
   if (skip && skip[hubs[hp.hub]]) return;  // singleton block (work-efficient mode)
   const int C = hp.nchunks;
@@ -899,36 +930,83 @@ __global__ void __launch_bounds__(256) k_hub_reduce(Src src, const HubPart *__re
     __syncthreads();
   }
   const int T = pre[C];
+  // Distinct keys of this partition, PS slots at a time.  A partition is
+  // planned to hold at most PS / 2 of them, but a skewed hub can put more in
+  // one partition: then the set stops filling at 3/4 (so probes always end),
+  // and the partition is redone in Q sub-passes, each taking the keys whose
+  // sub-partition hash (independent of the partition and slot hashes) is q,
+  // with Q doubled until every sub-pass fits.  Sub-passes hold disjoint key
+  // sets, so their sums and counts add up to the partition's.
   u64 acc = 0;
   u32 cnt = 0;
-  for (int t0 = 0; t0 < T; t0 += 4 * 256) {
-    K pr[4];
+  u32 Q = 1;
+  for (u32 q = 0; q < Q;) {
+    if (threadIdx.x == 0) { sh_fill[0] = 0; sh_fill[1] = 0; }
+    __syncthreads();
+    u64 pacc = 0;
+    u32 pcnt = 0;
+    for (int t0 = 0; t0 < T; t0 += 4 * 256) {
+      K pr[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int t = t0 + threadIdx.x + u * 256;
-      pr[u] = KO::EMPTY;
-      if (t < T) {
-        int lo = 0, hi = C - 1;
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (pre[mid] <= t) lo = mid; else hi = mid - 1;
+      for (int u = 0; u < 4; ++u) {
+        const int t = t0 + threadIdx.x + u * 256;
+        pr[u] = KO::EMPTY;
+        if (t < T) {
+          int lo = 0, hi = C - 1;
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (pre[mid] <= t) lo = mid; else hi = mid - 1;
+          }
+          pr[u] = stage[sbase[lo] + (t - pre[lo])];
         }
-        pr[u] = stage[sbase[lo] + (t - pre[lo])];
       }
-    }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const K p = pr[u];
-      if (p == KO::EMPTY) continue;
-      u32 sl = KO::hash(p) & (PS - 1);
-      for (int probes = 0;; ++probes) {
-        if (probes >= PS) { atomicOr(err, ERR_VERIFY_OVERFLOW); break; }
-        const K old = atomicCAS(&set[sl], KO::EMPTY, p);
-        if (old == KO::EMPTY) { acc += mix_pair(KO::wide(src, p)); ++cnt; break; }
-        if (old == p) break;
-        sl = (sl + 1) & (PS - 1);
+      for (int u = 0; u < 4; ++u) {
+        const K p = pr[u];
+        if (p == KO::EMPTY) continue;
+        if (Q > 1 && (sub_hash((u64)p) & (Q - 1)) != q) continue;
+        u32 sl = KO::hash(p) & (PS - 1);
+        while (true) {
+          const K cur = set[sl];
+          if (cur == p) break;
+          if (cur == KO::EMPTY) {
+            // once the pass has overflowed nothing more is inserted (it is redone);
+            // at most one insertion per thread lands after the 3/4 mark, so empty
+            // slots remain and every probe sequence ends
+            if (sh_fill[1]) break;
+            const K old = atomicCAS(&set[sl], KO::EMPTY, p);
+            if (old == KO::EMPTY) {
+              pacc += mix_pair(KO::mixin(src, p));
+              ++pcnt;
+              if (atomicAdd(&sh_fill[0], 1u) + 1u >= (u32)(PS / 4 * 3)) sh_fill[1] = 1u;
+              break;
+            }
+            if (old == p) break;
+          }
+          sl = (sl + 1) & (PS - 1);
+        }
       }
+      __syncthreads();
     }
+    __syncthreads();
+    const bool over = sh_fill[1] != 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < PS; i += 256) set[i] = KO::EMPTY;
+    if (over) {
+      if (Q >= 4096) {  // 4096 * PS * 3/4 slots exceed any staged hub; not reached
+        if (threadIdx.x == 0) atomicOr(err, ERR_VERIFY_OVERFLOW);
+        return;
+      }
+      Q <<= 1;
+      q = 0;
+      acc = 0;
+      cnt = 0;
+    } else {
+      acc += pacc;
+      cnt += pcnt;
+      ++q;
+    }
+    __syncthreads();
   }
   block_reduce_2(acc, cnt, sh_acc, sh_cnt);
   if (threadIdx.x == 0) {
@@ -965,7 +1043,8 @@ __global__ void __launch_bounds__(256) k_sig_hub_global(Src src, const HubGChunk
   u64 acc = 0;
   u32 cnt = 0;
   for (int64_t i = row + c.b + threadIdx.x; i < row + c.e; i += 256) {
-    const u64 p = src.pair(i);
+    u64 p = src.pair(i);
+    if constexpr (Src::HASHED) p = (u64)src.hkey(p);  // the tiers of one graph dedupe the same keys
     const u64 want = p | ((u64)hepoch << 62);
     u64 sl = scale_to(set_hash(p), size);
     while (true) {
@@ -1058,20 +1137,25 @@ __global__ void __launch_bounds__(256) k_lookup(Src src, int count, const int *_
         const int64_t bv = src.begin(v), ev = src.end(v);
         const int64_t br = src.begin(r), er = src.end(r);
         if (ev - bv <= SMALL_MAX && er - br <= SMALL_MAX) {
-          // small rows: r's pairs in registers (static indexing), every pair
-          // of v must occur among them (equal distinct counts were checked,
-          // so inclusion is equality)
+          // small rows: r's pairs in registers (static indexing); every pair
+          // of v must occur among them, and every entry of r must be met by
+          // some pair of v (set equality in both directions, so it does not
+          // rest on the distinct counts)
           u64 rp[SMALL_MAX];
 #pragma unroll
           for (int j = 0; j < SMALL_MAX; ++j) rp[j] = br + j < er ? src.pair(br + j) : EMPTY64;
+          const u32 want = (u32)((1ull << (er - br)) - 1ull);
+          u32 met = 0;
           bool ok = true;
           for (int64_t j = bv; j < ev && ok; ++j) {
             const u64 p = src.pair(j);
-            bool found = false;
+            u32 hit = 0;
 #pragma unroll
-            for (int q = 0; q < SMALL_MAX; ++q) found |= rp[q] == p;
-            ok = found;
+            for (int q = 0; q < SMALL_MAX; ++q) hit |= (rp[q] == p ? 1u : 0u) << q;
+            met |= hit;
+            ok = hit != 0;
           }
+          ok = ok && met == want;
           if (ok) {
             rep[v] = r;
           } else {
@@ -1139,7 +1223,7 @@ __device__ int wg_subset_pass(const Src &src, int v, int r, u32 parts, u64 *set,
 }
 
 template <class Src>
-__device__ bool wg_subset(const Src &src, int v, int r, u32 dcr, u64 *set, int *sh_flag, u32 *err) {
+__device__ bool wg_subset_one(const Src &src, int v, int r, u32 dcr, u64 *set, int *sh_flag, u32 *err) {
   u32 parts = 1;
   while ((u64)parts * (BLOCK_SLOTS / 2) < (u64)dcr) parts <<= 1;
   while (true) {
@@ -1151,6 +1235,16 @@ __device__ bool wg_subset(const Src &src, int v, int r, u32 dcr, u64 *set, int *
     }
     parts <<= 1;
   }
+}
+
+// Equal signatures of v and r, given equal distinct counts.  With exact keys
+// the counts are the pair counts and one inclusion decides; with hashed keys
+// they count distinct keys, so both inclusions are checked.
+template <class Src>
+__device__ bool wg_subset(const Src &src, int v, int r, u32 dcr, u64 *set, int *sh_flag, u32 *err) {
+  if (!wg_subset_one(src, v, r, dcr, set, sh_flag, err)) return false;
+  if constexpr (Src::HASHED) return wg_subset_one(src, r, v, dcr, set, sh_flag, err);
+  return true;
 }
 
 // Persistent: grid-strides over the verification list (count read on device).
@@ -1229,16 +1323,17 @@ __global__ void __launch_bounds__(256) k_res_verify(Src src, const int *__restri
 
 // ---------------------------------------------------------------- numbering
 // Reduce-then-scan over the flags "rep[v] == v" in vertex order (tiles of
-// SCAN_TILE vertices): per-tile head counts, one workgroup scans the tile
+// 256 * ITEMS vertices, ITEMS = 8 or 16 per thread): per-tile head counts, one workgroup scans the tile
 // counts, then every tile numbers its heads.  A head's exclusive prefix is its
 // dense id, so blocks are numbered by their first vertex.  Non-heads get -1
 // here and their representative's id in k_assign.
+template <int ITEMS>
 __device__ inline u32 tile_flags(int n, const int *__restrict__ rep, int64_t base) {
-  int r[SCAN_ITEMS];
-  if (base + SCAN_ITEMS <= n) {
+  int r[ITEMS];
+  if (base + ITEMS <= n) {
     const int4 *p4 = reinterpret_cast<const int4 *>(rep + base);
 #pragma unroll
-    for (int q = 0; q < SCAN_ITEMS / 4; ++q) {
+    for (int q = 0; q < ITEMS / 4; ++q) {
       const int4 x = p4[q];
       r[4 * q] = x.x;
       r[4 * q + 1] = x.y;
@@ -1247,20 +1342,21 @@ __device__ inline u32 tile_flags(int n, const int *__restrict__ rep, int64_t bas
     }
   } else {
 #pragma unroll
-    for (int j = 0; j < SCAN_ITEMS; ++j) r[j] = (base + j < n) ? rep[base + j] : -1;
+    for (int j = 0; j < ITEMS; ++j) r[j] = (base + j < n) ? rep[base + j] : -1;
   }
   u32 bits = 0;
 #pragma unroll
-  for (int j = 0; j < SCAN_ITEMS; ++j)
+  for (int j = 0; j < ITEMS; ++j)
     if (r[j] == (int)(base + j)) bits |= 1u << j;
   return bits;
 }
 
 
+template <int ITEMS>
 __global__ void __launch_bounds__(256) k_tile_count(int n, const int *__restrict__ rep, u32 *__restrict__ tile_sum) {
   __shared__ u32 sh_w[4];
-  const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
-  const u32 mine = __popc(tile_flags(n, rep, base));
+  const int64_t base = (int64_t)blockIdx.x * (256 * ITEMS) + (int64_t)threadIdx.x * ITEMS;
+  const u32 mine = __popc(tile_flags<ITEMS>(n, rep, base));
   u32 total;
   block_exclusive_scan(mine, sh_w, &total);
   if (threadIdx.x == 0) tile_sum[blockIdx.x] = total;
@@ -1307,26 +1403,27 @@ __global__ void __launch_bounds__(1024) k_tile_scan(int ntiles, u32 *tile_sum, i
   if (t == 0) *count_out = (int64_t)carry;
 }
 
+template <int ITEMS>
 __global__ void __launch_bounds__(256) k_scan_write(int n, const int *__restrict__ rep, const u32 *__restrict__ tile_pre,
                                                     int *__restrict__ out, int out_aligned) {
   __shared__ u32 sh_w[4];
-  const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
-  const u32 bits = tile_flags(n, rep, base);
+  const int64_t base = (int64_t)blockIdx.x * (256 * ITEMS) + (int64_t)threadIdx.x * ITEMS;
+  const u32 bits = tile_flags<ITEMS>(n, rep, base);
   u32 total;
   u32 id = tile_pre[blockIdx.x] + block_exclusive_scan(__popc(bits), sh_w, &total);
-  int o[SCAN_ITEMS];
+  int o[ITEMS];
 #pragma unroll
-  for (int j = 0; j < SCAN_ITEMS; ++j) {
+  for (int j = 0; j < ITEMS; ++j) {
     o[j] = (bits & (1u << j)) ? (int)id : -1;
     id += (bits >> j) & 1u;
   }
-  if (out_aligned && base + SCAN_ITEMS <= n) {
+  if (out_aligned && base + ITEMS <= n) {
     int4 *q4 = reinterpret_cast<int4 *>(out + base);
 #pragma unroll
-    for (int q = 0; q < SCAN_ITEMS / 4; ++q) q4[q] = make_int4(o[4 * q], o[4 * q + 1], o[4 * q + 2], o[4 * q + 3]);
+    for (int q = 0; q < ITEMS / 4; ++q) q4[q] = make_int4(o[4 * q], o[4 * q + 1], o[4 * q + 2], o[4 * q + 3]);
   } else {
 #pragma unroll
-    for (int j = 0; j < SCAN_ITEMS; ++j)
+    for (int j = 0; j < ITEMS; ++j)
       if (base + j < n) out[base + j] = o[j];
   }
 }

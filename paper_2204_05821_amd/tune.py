@@ -1,25 +1,37 @@
-"""Autotuner for launch shapes (range capacity, hub chunk, hub partition size).
+"""Autotuner for launch shapes.
 
-For a given graph or batch it runs every candidate tuning, times a few
-refinement calls after a warm-up, checks that every candidate's partitions
-and counts are bit-identical to the first candidate's (launch shape must
-never change results), and returns the fastest.  Choices are cached in a
-JSON file keyed by the GPU architecture and a coarse degree histogram of the
-input, so a later run on a similar input skips the search.
+Knobs (all in ``kbisim_tuning``; results never depend on them): set-key form
+(``key_bits``: 32-bit exact-or-hashed, hashed, 64-bit), range capacity (the
+row-tier threshold, ``range_edges``), hub chunk and hub partition size (only
+when the graph has hub rows) and the numbering scan's items per thread
+(``scan_items``).
+
+The search is coordinate-wise: starting from the defaults, one knob at a
+time takes each of its values, keeping the others at the best found so far.
+For one knob every value is timed in ``rounds`` interleaved rounds, the order
+of the values rotating from round to round, and the median decides, so a
+value is not favoured by where it falls in the sequence.  Every runner is
+built on the same workspace (the caller's ``make`` passes one buffer, sized
+for the input, to every candidate), so no candidate pays for allocator churn
+left by another.  Every candidate's partitions and counts must be
+bit-identical to the first one's.  Choices are cached in a JSON file keyed by
+the GPU architecture and a coarse degree histogram of the input.
 """
 from __future__ import annotations
 
 import hashlib
-import itertools
 import json
 import os
+import statistics
 import time
-from typing import Callable, Dict, List, Optional, Tuple
+from typing import Callable, Dict, List, Optional, Sequence, Tuple
 
 import numpy as np
 
-CANDIDATES = [dict(range_edges=re, hub_chunk=hc, hub_part_target=hp)
-              for re, hc, hp in itertools.product([1024, 2048], [2048, 4096], [1024, 2048])]
+DEFAULTS = dict(key_bits=0, range_edges=0, hub_chunk=2048, hub_part_target=2048, scan_items=16)
+KNOBS = [("key_bits", [0, 32, 64]), ("range_edges", [1024, 2048]), ("hub_chunk", [2048, 4096]),
+         ("hub_part_target", [1024, 2048]), ("scan_items", [8, 16])]
+HUB_KNOBS = ("hub_chunk", "hub_part_target")
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "kbisim", "tune.json")
 
@@ -36,6 +48,24 @@ def degree_signature(row_ptr: np.ndarray) -> str:
     share = np.bincount(cls, weights=deg, minlength=32)[:32] / m
     coarse = ",".join(f"{x:.2f}" for x in share)
     return f"n{n.bit_length()}_m{m.bit_length()}_{hashlib.sha1(coarse.encode()).hexdigest()[:12]}"
+
+
+def knobs_for(max_degree: int, pair_bits: int) -> List[Tuple[str, List[int]]]:
+    """The knobs that can change the work split of an input.
+
+    max_degree: longest row.  pair_bits: bits of the largest (edge label, block
+    id) pair, i.e. bit width of the largest label plus that of the largest
+    graph's vertex count.  Hub knobs matter only with rows beyond the row tiers
+    (8,192 entries, or 19,456 with 32-bit keys); exact 32-bit keys exist only
+    when pairs fit 31 bits (otherwise the default already hashes them)."""
+    out = []
+    for name, vals in KNOBS:
+        if name in HUB_KNOBS and max_degree <= 8192:
+            continue
+        if name == "key_bits" and pair_bits > 31:
+            vals = [0, 64]
+        out.append((name, list(vals)))
+    return out
 
 
 def _arch() -> str:
@@ -63,45 +93,69 @@ def save_cache(data: Dict, path: str = DEFAULT_CACHE) -> None:
 
 
 def autotune(make: Callable[[Dict], object], run: Callable[[object], Tuple[list, list]], key: str,
-             reps: int = 2, candidates: Optional[List[Dict]] = None, cache_path: Optional[str] = DEFAULT_CACHE,
-             close: Callable[[object], None] = lambda r: r.close()) -> Tuple[Dict, Dict]:
-    """Pick the fastest candidate for `key`.
+             rounds: int = 3, reps: int = 1, knobs: Optional[Sequence[Tuple[str, List[int]]]] = None,
+             start: Optional[Dict] = None, cache_path: Optional[str] = DEFAULT_CACHE,
+             close: Callable[[object], None] = lambda r: r.close(), sync: Optional[Callable[[], None]] = None,
+             ) -> Tuple[Dict, Dict]:
+    """Pick the fastest tuning for `key`.
 
-    make(tuning_dict) builds a runner, run(runner) performs one refinement call
-    and returns (device outputs, counts); close(runner) releases it.  Returns
-    (best tuning dict, report).  Raises if two candidates disagree.
+    make(tuning_dict) builds a runner (on the caller's shared workspace),
+    run(runner) performs one refinement call and returns (device outputs,
+    counts), close(runner) releases it.  Each timed sample is one warm-up
+    call followed by `reps` timed calls on a freshly made runner.  Returns
+    (best tuning dict, report with every sample).  Raises if two candidates
+    disagree.
     """
-    import torch
+    if sync is None:
+        import torch
+        sync = torch.cuda.synchronize
     cache = load_cache(cache_path) if cache_path else {}
     full_key = f"{_arch()}|{key}"
     if full_key in cache:
         return cache[full_key]["best"], cache[full_key]
-    cands = candidates or CANDIDATES
-    ref_outs, ref_counts = None, None
-    timings = []
-    for cand in cands:
+    best = dict(DEFAULTS, **(start or {}))
+    knobs = list(knobs if knobs is not None else KNOBS)
+    ref = {}
+    samples: Dict[str, List[float]] = {}
+
+    def sample(cand: Dict) -> float:
         r = make(cand)
-        outs, counts = run(r)                 # warm-up (and capture), also the result to compare
-        run(r)
-        torch.cuda.synchronize()
-        if ref_outs is None:
-            ref_outs = [o.clone() for o in outs]
-            ref_counts = counts
-        else:
-            if counts != ref_counts or any(not torch.equal(a, b) for a, b in zip(outs, ref_outs)):
-                close(r)
+        try:
+            outs, counts = run(r)                 # warm-up (and capture), also the result to compare
+            sync()
+            if not ref:
+                ref["outs"] = [o.clone() for o in outs]
+                ref["counts"] = counts
+            elif counts != ref["counts"] or any(not bool((a == b).all()) for a, b in zip(outs, ref["outs"])):
                 raise AssertionError(f"tuning {cand} changed the result")
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            run(r)
-        torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) * 1e3 / reps
-        timings.append((ms, cand))
-        close(r)
-    timings.sort(key=lambda x: x[0])
-    report = {"best": timings[0][1], "ms": [[round(ms, 3), c] for ms, c in timings]}
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                run(r)
+            sync()
+            return (time.perf_counter() - t0) * 1e3 / reps
+        finally:
+            close(r)
+
+    for name, values in knobs:
+        values = list(values)
+        if len(values) < 2:
+            continue
+        times: Dict[int, List[float]] = {v: [] for v in values}
+        for rd in range(rounds):
+            order = values[rd % len(values):] + values[:rd % len(values)]
+            if rd % 2:
+                order = order[::-1]
+            for v in order:
+                cand = dict(best, **{name: v})
+                ms = sample(cand)
+                times[v].append(ms)
+                samples.setdefault(json.dumps(cand, sort_keys=True), []).append(round(ms, 3))
+        med = {v: statistics.median(t) for v, t in times.items()}
+        best[name] = min(values, key=lambda v: (med[v], values.index(v)))
+    ranked = sorted(((statistics.median(t), json.loads(c)) for c, t in samples.items()), key=lambda x: x[0])
+    report = {"best": best, "ms": [[round(ms, 3), c] for ms, c in ranked], "samples": samples,
+              "rounds": rounds, "reps": reps, "search": "coordinate, interleaved rounds, median"}
     if cache_path:
         cache[full_key] = report
         save_cache(cache, cache_path)
-    return timings[0][1], report
+    return best, report

@@ -143,6 +143,31 @@ def test_degree_tiers_many_labels():
     assert_same(tier_graph(seed=4, labels=200, shared_targets=3000), 5, "tiers-many")
 
 
+@pytest.mark.parametrize("kbits", [0, 32, 64])
+def test_hub_partition_overflow_takes_sub_passes(kbits, monkeypatch):
+    """One partition per staged hub (a test knob): a 20,000-entry hub row of ~19,000 distinct
+    pairs overflows its partition set (8,192 slots, or 4,096 with 64-bit keys), and the reduce
+    pass must redo that partition in sub-passes instead of failing; results stay exact."""
+    kb = _kb()
+    monkeypatch.setenv("KBISIM_DEBUG_HUB_PARTS", "1")
+    g = tier_graph(seed=10, labels=200, shared_targets=3000)
+    r = kb.Refiner(*kb.to_device(g), kmax=1, tuning=kb.tuning(key_bits=kbits))
+    info = r.schedule_info()
+    r.close()
+    assert info["hub"]["vertices"] >= 2, info
+    assert_same_tuned(g, 4, kb.tuning(key_bits=kbits), f"hub-overflow-{kbits}")
+
+
+def test_wide_hub_partitions_overflow(monkeypatch):
+    """Hubs of 2^20 distinct pairs cut into at most 4 partitions: each partition holds ~2^18
+    distinct keys and is reduced in many sub-passes."""
+    kb = _kb()
+    monkeypatch.setenv("KBISIM_DEBUG_HUB_PARTS", "4")
+    g = wide_hub_graph()
+    assert_same(g, 2, "wide-hubs-overflow")
+    assert_same_tuned(g, 2, kb.tuning(key_bits=64), "wide-hubs-overflow-64")
+
+
 # ------------------------------------------------------------------ key width
 
 def assert_same_tuned(g, k, tune, label):
@@ -157,9 +182,10 @@ def assert_same_tuned(g, k, tune, label):
     r.close()
 
 
-@pytest.mark.parametrize("kbits", [0, 64])
+@pytest.mark.parametrize("kbits", [0, 32, 64])
 def test_key_width_forced_and_automatic(kbits):
-    """32-bit LDS keys are used where (edge label, block) fits in 31 bits; 64-bit keys always work."""
+    """32-bit LDS keys: exact where (edge label, block) fits in 31 bits, else hashed; hashed keys
+    (32) and 64-bit keys (64) forced on every graph."""
     kb = _kb()
     for g in [graphgen.rmat(14, 200_000, seed=2), tier_graph(seed=6), graphgen.rmat_rdf(12, 60_000, seed=8),
               graphgen.deep(seed=9, n=20_000, avg_degree=1.5)]:
@@ -179,6 +205,30 @@ def test_key_width_boundary(label_max):
     vl = rng.integers(0, 3, size=n)
     g = graphgen.from_edges(n, src, dst, lab, vl, name=f"bound{label_max}")
     assert_same_tuned(g, 4, kb.tuning(), f"boundary-{label_max}")
+
+
+@pytest.mark.parametrize("key_bits", [2, 5, 12])
+def test_hashed_keys_colliding_inside_rows(key_bits, monkeypatch):
+    """Hashed set keys cut to a few bits collide inside rows, so rows with different pair sets
+    share key sets and distinct-key counts; the two-sided exact check must keep every
+    partition exact (tiers from single entries to hub chunks)."""
+    kb = _kb()
+    monkeypatch.setenv("KBISIM_DEBUG_KEY_BITS", str(key_bits))
+    t = kb.tuning(key_bits=32)
+    for mode in ["full_fw", "kaushik"]:
+        assert_same_tuned(helpers.example_variant(mode), 3, t, f"kcollide{key_bits}-{mode}")
+    for g in [graphgen.tiny(seed=3, n=2000, m=9000), graphgen.deep(seed=4, n=5000, avg_degree=1.4),
+              graphgen.rmat(12, 60_000, seed=6), tier_graph(seed=8)]:
+        assert_same_tuned(g, 5, t, f"kcollide{key_bits}-{g.name}")
+
+
+def test_hashed_keys_with_forced_hash_collisions(monkeypatch):
+    kb = _kb()
+    monkeypatch.setenv("KBISIM_DEBUG_HASH_BITS", "5")
+    monkeypatch.setenv("KBISIM_DEBUG_KEY_BITS", "6")
+    t = kb.tuning(key_bits=32)
+    assert_same_tuned(graphgen.tiny(seed=2, n=3000, m=12000), 4, t, "hcollide-tiny")
+    assert_same_tuned(tier_graph(seed=9), 3, t, "hcollide-tiers")
 
 
 # ------------------------------------------------------------------ hash collisions
@@ -339,6 +389,7 @@ def test_tiers_with_separate_labels():
     g.elabel = (((1 << 30) + 7) * (g.elabel.astype(np.int64) + 1) % ((1 << 31) - 1)).astype(np.int32)
     assert_same(g, 5, "tiers-separate")
     assert_same_tuned(g, 5, kb.tuning(key_bits=64), "tiers-separate-64")
+    assert_same_tuned(g, 5, kb.tuning(key_bits=32), "tiers-separate-32")
 
 
 def giant_hub_graph(seed=23):
@@ -404,10 +455,42 @@ def test_wide_key_hubs_fill_their_partition_sets():
     for the same pair set."""
     kb = _kb()
     g = wide_hub_graph()
-    r = kb.refiner_for(g, kmax=1)
+    t64 = kb.tuning(key_bits=64)
+    r = kb.Refiner(*kb.to_device(g), kmax=1, tuning=t64)
     info = r.schedule_info()
     r.close()
     assert info["hub"]["vertices"] == 2 and info["hub_global"]["vertices"] == 1, info
     exp, _ = ref_all(g, 2)
     assert exp[1][0] == exp[1][2] != exp[1][1]
-    assert_same(g, 2, "wide-hubs")
+    assert_same_tuned(g, 2, t64, "wide-hubs-64")
+    # default: hashed 32-bit keys (the pairs need 32 bits); the longest row has more
+    # chunks than a hub can be staged in, so it keeps the global set
+    r = kb.refiner_for(g, kmax=1)
+    info = r.schedule_info()
+    r.close()
+    assert info["hub"]["vertices"] == 2 and info["hub_global"]["vertices"] == 1, info
+    assert_same(g, 2, "wide-hubs-hashed")
+
+
+def test_hashed_keys_agree_between_staged_and_global_hubs():
+    """Hashed keys: a staged hub (2^20 distinct pairs) and a row past the staged limit holding
+    the same pairs five times (global set) have one signature; a third row lacks one pair."""
+    kb = _kb()
+    rng = np.random.default_rng(51)
+    n, d = 2_200_000, 1 << 20          # 22 bits of block id + 10 of edge label: hashed keys
+    t = rng.choice(np.arange(3, n), size=d, replace=False)
+    lb = rng.integers(0, 1000, size=d)
+    perm = rng.permutation(5 * d)
+    src = np.concatenate([np.zeros(d), np.ones(5 * d), np.full(d - 1, 2), rng.integers(3, n, size=2_000_000)])
+    dst = np.concatenate([t, np.tile(t, 5)[perm], t[1:], rng.integers(0, n, size=2_000_000)])
+    lab = np.concatenate([lb, np.tile(lb, 5)[perm], lb[1:], rng.integers(0, 1000, size=2_000_000)])
+    vlabel = np.arange(n) - 2
+    vlabel[:3] = 0
+    g = graphgen.from_edges(n, src.astype(np.int64), dst, lab, vlabel, name="hashed-hubs")
+    r = kb.refiner_for(g, kmax=1)
+    info = r.schedule_info()
+    r.close()
+    assert info["hub"]["vertices"] == 2 and info["hub_global"]["vertices"] == 1, info
+    exp, _ = ref_all(g, 2)
+    assert exp[1][0] == exp[1][1] != exp[1][2]
+    assert_same(g, 2, "hashed-hubs")
