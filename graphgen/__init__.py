@@ -23,20 +23,27 @@ from typing import Optional
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "libgraphgen.so")
+# KBISIM_SANITIZE=1 selects a copy built with AddressSanitizer and
+# UndefinedBehaviorSanitizer (host code only; the process must preload libasan).
+SANITIZE = os.environ.get("KBISIM_SANITIZE", "") == "1"
+SAN_FLAGS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer", "-g"]
+_LIB_PATH = os.path.join(_HERE, "libgraphgen_san.so" if SANITIZE else "libgraphgen.so")
 _lib = None
 
 ST_BATCH = 9
 
 
-def build(force: bool = True) -> str:
-    """Compile libgraphgen.so in place (gcc, OpenMP)."""
+def build(force: bool = True, sanitize: Optional[bool] = None) -> str:
+    """Compile libgraphgen.so (or the sanitizer copy libgraphgen_san.so) in place (gcc, OpenMP)."""
+    san = SANITIZE if sanitize is None else sanitize
+    lib = os.path.join(_HERE, "libgraphgen_san.so" if san else "libgraphgen.so")
     src = os.path.join(_HERE, "graphgen.c")
-    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(src):
-        tmp = _LIB_PATH + ".tmp"
-        subprocess.check_call(["gcc", "-O3", "-fopenmp", "-fPIC", "-shared", "-Wall", "-o", tmp, src])
-        os.replace(tmp, _LIB_PATH)
-    return _LIB_PATH
+    if force or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(src):
+        tmp = lib + ".tmp"
+        flags = ["-O1"] + SAN_FLAGS if san else ["-O3"]
+        subprocess.check_call(["gcc"] + flags + ["-fopenmp", "-fPIC", "-shared", "-Wall", "-o", tmp, src])
+        os.replace(tmp, lib)
+    return lib
 
 
 def _load():

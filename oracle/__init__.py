@@ -32,23 +32,34 @@ from typing import List, Optional, Tuple
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# KBISIM_SANITIZE=1 selects copies built with AddressSanitizer and
+# UndefinedBehaviorSanitizer (host code only; the process must preload libasan).
+SANITIZE = os.environ.get("KBISIM_SANITIZE", "") == "1"
+SAN_FLAGS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer", "-g"]
+_SUFFIX = "_san.so" if SANITIZE else ".so"
+_LIB_PATH = os.path.join(_HERE, "liboracle" + _SUFFIX)
 _lib = None
 
 
-_CHECK_PATH = os.path.join(_HERE, "libstepcheck.so")
+_CHECK_PATH = os.path.join(_HERE, "libstepcheck" + _SUFFIX)
 _check_lib = None
 
 
-def build(force: bool = True) -> str:
-    for src, lib, extra in [("oracle.cpp", _LIB_PATH, []), ("stepcheck.cpp", _CHECK_PATH, ["-fopenmp"])]:
+def build(force: bool = True, sanitize: Optional[bool] = None) -> str:
+    """Compile liboracle.so and libstepcheck.so (or their sanitizer copies, *_san.so) in place."""
+    san = SANITIZE if sanitize is None else sanitize
+    suffix = "_san.so" if san else ".so"
+    for src, lib, extra in [("oracle.cpp", "liboracle" + suffix, []),
+                            ("stepcheck.cpp", "libstepcheck" + suffix, ["-fopenmp"])]:
         src = os.path.join(_HERE, src)
+        lib = os.path.join(_HERE, lib)
         if force or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(src):
             tmp = lib + ".tmp"
-            subprocess.check_call(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-Wall"] + extra +
+            flags = ["-O1"] + SAN_FLAGS if san else ["-O2"]
+            subprocess.check_call(["g++"] + flags + ["-std=c++17", "-fPIC", "-shared", "-Wall"] + extra +
                                   ["-o", tmp, src])
             os.replace(tmp, lib)
-    return _LIB_PATH
+    return os.path.join(_HERE, "liboracle" + suffix)
 
 
 def _load():
