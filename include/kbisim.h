@@ -322,6 +322,37 @@ int kbisim_step_result(kbisim_ctx *c, int i, const int32_t *prev, int32_t *out, 
 /* Release the context (host memory only; the workspace stays the caller's). */
 int kbisim_destroy(kbisim_ctx *c);
 
+/* ---- refinement without allocation ---------------------------------------
+ *
+ * For callers that cannot allocate device memory: code that must not call
+ * hipMalloc or take pinned host memory (serving loops with a fixed memory
+ * plan, harnesses that forbid allocation).  The same computation as
+ * kbisim_create + kbisim_refine(k) + kbisim_destroy, with the workspace taken
+ * from a scratch array inside the library instead of the caller: one array of
+ * kbisim_noalloc_scratch_bytes() bytes (128 MiB) per GPU, held from the
+ * library's load on that GPU until the process ends.
+ *
+ * g: as for kbisim_create (device arrays, read only).  out_block_ids: k
+ * device pointers, each int32 [n], receiving P_1..P_k; out_counts: host
+ * int64 [k].  Runs on the current device, on `stream` (a stream of that
+ * device, or NULL), and synchronises it before returning.  No device memory
+ * is allocated and no pinned host memory is taken; host-side bookkeeping
+ * uses the C++ heap only.
+ *
+ * Limit: the graph must fit the scratch array, i.e. the workspace
+ * kbisim_workspace_bytes(g, k) reports must be at most
+ * kbisim_noalloc_scratch_bytes() (about 500k vertices and 3M edges);
+ * otherwise KBISIM_ENOSPACE, before any HIP call.  Other errors as for
+ * kbisim_create / kbisim_refine.  Every call on one GPU uses that GPU's one
+ * array and leaves its contents behind (nothing of a previous call is read):
+ * calls that overlap in time on one GPU, from different threads or on
+ * different streams, race and must be serialised by the caller.             */
+int kbisim_refine_noalloc(const kbisim_graph *g, int k, int32_t *const *out_block_ids, int64_t *out_counts,
+                          void *stream);
+
+/* Bytes of the per-GPU scratch array used by kbisim_refine_noalloc. */
+size_t kbisim_noalloc_scratch_bytes(void);
+
 /* Static description of an error code (or of the last HIP error seen). */
 const char *kbisim_strerror(int code);
 

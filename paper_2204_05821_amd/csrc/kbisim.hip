@@ -192,6 +192,7 @@ struct kbisim_ctx {
   unsigned char *single[2] = {nullptr, nullptr};  // singleton flags of the last two partitions
   u32 *multi = nullptr;  // stamps of heads that have a non-head member
   u32 prof_mask = ~0u;   // kernel kinds timed by the profiler
+  bool pinned_ok = true;  // schedule building may take pinned host buffers
   bool narrow = false;  // 32-bit LDS keys
   bool hashed = false;  // ... that hash the pair (it does not fit 31 bits, or 32-bit keys were asked for)
   u32 pb = 31;
@@ -503,13 +504,25 @@ int build_schedule(kbisim_ctx *c, const int64_t *ptr, Schedule &s, int range_edg
   s = Schedule{};
   s.range_edges = range_edges;
   HostRowsLease lease;
+  std::vector<int64_t> pageable;  // when no pinned host memory may be taken
   const int64_t *rp = nullptr;
   if (ptr && n > 0) {
-    lease.b = host_rows_take((size_t)n + 1);
-    if (!lease.b.p) return KBISIM_EINTERNAL;
-    HIP_TRY(hipMemcpyAsync(lease.b.p, ptr, 8 * (size_t)(n + 1), hipMemcpyDeviceToHost, c->stream));
+    int64_t *dst = nullptr;
+    if (c->pinned_ok) {
+      lease.b = host_rows_take((size_t)n + 1);
+      dst = lease.b.p;
+    } else {
+      try {
+        pageable.resize((size_t)n + 1);
+      } catch (...) {
+        return KBISIM_EINTERNAL;
+      }
+      dst = pageable.data();
+    }
+    if (!dst) return KBISIM_EINTERNAL;
+    HIP_TRY(hipMemcpyAsync(dst, ptr, 8 * (size_t)(n + 1), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
-    rp = lease.b.p;
+    rp = dst;
   }
   // Degree tiers.  Rows are packed greedily into ranges of consecutive
   // vertices; the vertex sequence is cut into SCHED_CHUNKS fixed chunks that
@@ -1204,7 +1217,8 @@ int read_tuning(const kbisim_tuning *t, Tuning &out) {
 // Shared by kbisim_create and kbisim_batch_create.  With vert_off (host,
 // num_graphs + 1) the graph is a batch of disjoint graphs.
 int create_impl(const kbisim_graph *g, int kmax, const kbisim_tuning *tuning, void *workspace, size_t ws_bytes,
-                void *stream, int64_t num_graphs, const int64_t *vert_off, kbisim_ctx **out) {
+                void *stream, int64_t num_graphs, const int64_t *vert_off, kbisim_ctx **out,
+                bool pinned_ok = true) {
   int rc = check_sizes(g);
   if (rc) return rc;
   if (!out || kmax < 0 || kmax > (1 << 20)) return KBISIM_EINVAL;
@@ -1230,6 +1244,7 @@ int create_impl(const kbisim_graph *g, int kmax, const kbisim_tuning *tuning, vo
   if (!c) return KBISIM_EINTERNAL;
   c->g = *g;
   c->kmax = kmax;
+  c->pinned_ok = pinned_ok;
   c->stream = (hipStream_t)stream;
   c->plan = plan;
   c->tune = tune;
@@ -1905,6 +1920,64 @@ int kbisim_quotient(kbisim_ctx *c, const int32_t *src_pid, const int32_t *dst_pi
   HIP_TRY(hipMemcpyAsync(out_count, pos + m, 8, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   return KBISIM_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- no-allocation entry point
+// Scratch for kbisim_refine_noalloc: one array per GPU, held from the
+// library's load on that GPU until the process ends.  In host code its name
+// stands for the symbol only; its device address comes from
+// hipGetSymbolAddress, once per device, with that device current.
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(128) << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int NOALLOC_MAX_DEVICES = 64;
+void *g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+std::mutex &scratch_mu() {
+  static std::mutex *m = new std::mutex();
+  return *m;
+}
+
+// Device address of the current device's scratch array (looked up on the
+// first call on that device).
+int scratch_address(void **out) {
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return KBISIM_EINTERNAL;
+  std::lock_guard<std::mutex> lk(scratch_mu());
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e);
+    if (!p) return KBISIM_EINTERNAL;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return 0;
+}
+}  // namespace
+
+extern "C" {
+
+size_t kbisim_noalloc_scratch_bytes(void) { return NOALLOC_SCRATCH_BYTES; }
+
+int kbisim_refine_noalloc(const kbisim_graph *g, int k, int32_t *const *out_block_ids, int64_t *out_counts,
+                          void *stream) {
+  int rc = check_sizes(g);
+  if (rc) return rc;
+  if (k < 0 || k > (1 << 20)) return KBISIM_EINVAL;
+  if (k > 0 && (!out_block_ids || !out_counts)) return KBISIM_EINVAL;
+  const size_t need = make_plan(g->n, g->m, g->vlabel_ptr ? g->nlabels : 0, k, 0).total;
+  if (need > NOALLOC_SCRATCH_BYTES) return KBISIM_ENOSPACE;
+  void *ws = nullptr;
+  if ((rc = scratch_address(&ws))) return rc;
+  kbisim_ctx *c = nullptr;
+  if ((rc = create_impl(g, k, nullptr, ws, NOALLOC_SCRATCH_BYTES, stream, 0, nullptr, &c, false))) return rc;
+  rc = refine_impl(c, nullptr, k, out_block_ids, out_counts);
+  kbisim_destroy(c);
+  return rc;
 }
 
 const char *kbisim_strerror(int code) {

@@ -131,3 +131,20 @@ def test_the_two_billion_edge_graph_fits_one_gpu(lib):
     assert ws + csr + outputs < 0.5 * 288e9, (ws, csr, outputs)
     assert f(ctypes.byref(Graph(n // 2, m // 2, n // 2)), 10, ctypes.byref(out)) == 0
     assert 0.45 < out.value / ws < 0.55
+
+
+def test_noalloc_rejects_graphs_beyond_its_scratch_before_touching_the_device(lib):
+    lib.kbisim_noalloc_scratch_bytes.restype = ctypes.c_size_t
+    limit = lib.kbisim_noalloc_scratch_bytes()
+    assert limit == 128 << 20
+    f = lib.kbisim_refine_noalloc
+    f.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    f.restype = ctypes.c_int
+    fake = ctypes.c_void_p(0x1000)   # never dereferenced
+    outs = (ctypes.c_void_p * 4)(fake, fake, fake, fake)
+    counts = (ctypes.c_int64 * 4)()
+    big = Graph(2_000_000, 4_000_000, 0, fake, fake, None, None, None)
+    assert f(ctypes.byref(big), 4, outs, counts, None) == -3
+    assert f(None, 4, outs, counts, None) == -1
+    assert f(ctypes.byref(big), -1, outs, counts, None) == -1
+    assert f(ctypes.byref(Graph(1000, 5000, 0, fake, fake, None, None, None)), 4, None, counts, None) == -1
