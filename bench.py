@@ -329,6 +329,8 @@ def run_plain(args, kb, torch, workload, g, cpu_job=None, extras=True):
                                                    "frac_of_peak": round(step_gbs / HBM_PEAK_GBS, 4)},
                 "counts": counts, "gather_probe": gather, "create_ms": round(create_ms, 1), "kernels": kernels,
                 "tiers": tiers}
+    incremental = None if args.no_incremental else incremental_leg(kb, torch, g, (rp, col, el, vl, vp), k,
+                                                                   ms_per_step)
     # Work-efficient mode (singleton blocks skipped, stop at the fixpoint): reported
     # separately; its outputs must equal the full-work outputs.
     full = [o.clone() for o in outs]
@@ -393,12 +395,64 @@ def run_plain(args, kb, torch, workload, g, cpu_job=None, extras=True):
         "gather_probe": gather,
         "work_efficient": work_efficient,
         "summary_graph": summary,
+        "incremental": incremental,
         "create_ms": round(create_ms, 1),
         "tuning": best,
         "autotune_ms": tune_report["ms"] if tune_report else None,
         "kernels": kernels,
         "tiers": tiers,
     }
+
+
+def incremental_leg(kb, torch, g, dev, k, full_ms, sizes=(1, 1000, 100_000), reps=3):
+    """Updates after edits: a context with its chain cached, then edited copies of the graph
+    (the targets of `e` random entries replaced by random vertices, so the rows of their
+    sources change), recomputed by kbisim_incr_update and timed against a full refine call;
+    each result is compared with a fresh context's refinement of the edited graph."""
+    rp, col, el, vl, vp = dev
+    r = kb.Refiner(rp, col, el, vl, vp, kmax=k)
+    t0 = time.perf_counter()
+    r.incremental()
+    torch.cuda.synchronize()
+    enable_ms = (time.perf_counter() - t0) * 1e3
+    r.refine(k)
+    t0 = time.perf_counter()
+    base_ids, base_counts = r.refine(k)
+    torch.cuda.synchronize()
+    cached_ms = (time.perf_counter() - t0) * 1e3
+    rng = np.random.default_rng(123)
+    out = {"cached_refine_ms": cached_ms, "full_refine_ms": full_ms, "enable_ms": enable_ms,
+           "state_GiB": r.incr_state.numel() / 2**30, "edits": []}
+    outs = r.alloc_outputs(k)
+    for e in sizes:
+        idx = np.sort(rng.choice(g.m, size=e, replace=False))
+        rows = np.unique(np.searchsorted(g.row_ptr, idx, side="right") - 1).astype(np.int32)
+        col2 = col.clone()
+        col2[torch.from_numpy(idx).to(col.device)] = torch.from_numpy(
+            rng.integers(0, g.n, size=e).astype(np.int32)).to(col.device)
+        rows_d = torch.from_numpy(rows).to(col.device)
+        r.update(rp, col2, el, rows_d, k, out=outs)      # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            _, counts = r.update(rp, col2, el, rows_d, k, out=outs)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / reps
+        f = kb.Refiner(rp, col2, el, vl, vp, kmax=k)
+        fids, fcounts = f.refine(k)
+        same = fcounts == counts and all(torch.equal(a, b) for a, b in zip(fids, outs))
+        f.close()
+        del f, fids, col2
+        torch.cuda.empty_cache()
+        out["edits"].append({"edited_entries": e, "edited_rows": int(len(rows)), "update_ms": ms,
+                             "speedup_vs_full_refine": full_ms / ms, "identical_to_refine_of_edited_graph": same,
+                             "counts": counts})
+        log(f"[bench] incremental: {e} edited entries ({len(rows)} rows): {ms:.2f} ms per k={k} update "
+            f"({full_ms / ms:.1f}x a full refine), identical {same}")
+    r.close()
+    del r, outs, base_ids
+    torch.cuda.empty_cache()
+    return out
 
 
 def run_batched(args, kb, torch):
@@ -596,6 +650,7 @@ def main():
                     help="a second plain workload reported beside the headline in --mode all ('' = none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip per-kernel event timing")
+    ap.add_argument("--no-incremental", action="store_true", help="skip the incremental-update leg")
     ap.add_argument("--autotune", action="store_true",
                     help="plain form: search the launch shapes first (default: the library defaults, which the "
                          "search picks within noise on this workload)")

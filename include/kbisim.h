@@ -322,6 +322,53 @@ int kbisim_step_result(kbisim_ctx *c, int i, const int32_t *prev, int32_t *out, 
 /* Release the context (host memory only; the workspace stays the caller's). */
 int kbisim_destroy(kbisim_ctx *c);
 
+/* ---- incremental updates on an edited graph --------------------------------
+ *
+ * After edits (edges deleted and inserted), P_1..P_k of the edited graph are
+ * recomputed from the cached chain of the original graph instead of from
+ * scratch; the paper names incremental computation on evolving graphs as
+ * future work (Sec. "Discussion").  Within a cached chain, blocks are named
+ * by their minimum vertex, so a vertex whose own block name and targets'
+ * block names did not change keeps its cached key hash; only the others are
+ * re-signed: the edited rows at every step, and from step 2 on the vertices
+ * whose name changed in the previous step and every vertex with an edge into
+ * one (that set grows along in-edges from step to step).  Grouping, exact
+ * checks and numbering cover every vertex, so the result is exactly the
+ * refinement of the edited graph from scratch (ids numbered by first
+ * vertex).
+ *
+ * Bytes of the caller buffer that holds the cached chain of a graph of
+ * g->n vertices and g->m edges for up to kmax steps: per step a key hash, a
+ * distinct count and a block name per vertex (16 bytes), the graph's in-rows
+ * (8 (n+1) + 4 m) and scratch; about 16 kmax n + 4 m + 40 n bytes.  Host
+ * only.  Errors: EINVAL (null, kmax < 1), ERANGE.                           */
+int kbisim_incr_state_bytes(const kbisim_graph *g, int kmax, size_t *bytes);
+
+/* Keep the chain of every later kbisim_refine call (from P0) in `state`
+ * (device, at least kbisim_incr_state_bytes(g, kmax) bytes, owned by the
+ * caller and left to the context until it is destroyed), so that
+ * kbisim_incr_update can follow.  Builds the in-rows of the context's graph
+ * (synchronises).  Not for batch contexts, and not together with the
+ * work-efficient mode (EINVAL either way; kbisim_work_efficient(c, 1, ...)
+ * fails once this is on).  Errors: EINVAL, ENOSPACE, EHIP.                  */
+int kbisim_incr_enable(kbisim_ctx *c, void *state, size_t bytes);
+
+/* P_1..P_k (k <= the steps of the last kbisim_refine call, which must have
+ * started from P0 after kbisim_incr_enable) of an edited graph g_new: device
+ * CSR of the same n vertices, with the same vertex labels as the context's
+ * graph (only its row_ptr, col, elabel and m are read; elabel present exactly
+ * when the context's graph has edge labels, each label at most the context
+ * graph's largest).  rows: device int32 [nrows], nrows <= n, the vertices
+ * whose rows differ from the context graph's as multisets of (label,
+ * target); repeats are allowed, rows not listed must be unchanged.
+ * out_block_ids: k device int32 [n] arrays; out_counts: host int64 [k].  The
+ * cached chain is not changed, so several edits can each be applied to it.
+ * Synchronises.  Errors: EINVAL (arguments, a listed vertex out of range, no
+ * cached chain of k steps), EGRAPH (invalid row offsets, a target out of
+ * range or a label beyond the cached graph's largest), EHIP, EINTERNAL.     */
+int kbisim_incr_update(kbisim_ctx *c, const kbisim_graph *g_new, const int32_t *rows, int64_t nrows, int k,
+                       int32_t *const *out_block_ids, int64_t *out_counts);
+
 /* ---- refinement without allocation ---------------------------------------
  *
  * For callers that cannot allocate device memory: code that must not call

@@ -87,6 +87,13 @@ def _lib():
     lib.kbisim_quotient_workspace_bytes.restype = i32
     lib.kbisim_quotient.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.POINTER(i64), vp, sz]
     lib.kbisim_quotient.restype = i32
+    lib.kbisim_incr_state_bytes.argtypes = [ctypes.POINTER(_Graph), i32, ctypes.POINTER(sz)]
+    lib.kbisim_incr_state_bytes.restype = i32
+    lib.kbisim_incr_enable.argtypes = [vp, vp, sz]
+    lib.kbisim_incr_enable.restype = i32
+    lib.kbisim_incr_update.argtypes = [vp, ctypes.POINTER(_Graph), vp, i64, i32, ctypes.POINTER(vp),
+                                       ctypes.POINTER(i64)]
+    lib.kbisim_incr_update.restype = i32
     lib.kbisim_gather_probe.argtypes = [vp, vp, i32, ctypes.POINTER(ctypes.c_double)]
     lib.kbisim_gather_probe.restype = i32
     lib.kbisim_work_efficient.argtypes = [vp, i32, ctypes.POINTER(i32)]
@@ -252,6 +259,44 @@ class Refiner:
         if rc:
             raise KbisimError(rc, "kbisim_work_efficient")
         return int(steps.value)
+
+    def incremental(self, state: Optional[torch.Tensor] = None) -> None:
+        """Cache the chain of later refine calls (from P0) so that update() can recompute it after edits.
+
+        The state buffer (device uint8, kbisim_incr_state_bytes) is allocated unless given.
+        """
+        lib = _lib()
+        nbytes = ctypes.c_size_t(0)
+        rc = lib.kbisim_incr_state_bytes(ctypes.byref(self._g), self.kmax, ctypes.byref(nbytes))
+        if rc:
+            raise KbisimError(rc, "kbisim_incr_state_bytes")
+        with torch.cuda.device(self.device):
+            self.incr_state = _workspace(state, int(nbytes.value), self.device)
+        rc = lib.kbisim_incr_enable(self._ctx, _ptr(self.incr_state), int(nbytes.value))
+        if rc:
+            raise KbisimError(rc, "kbisim_incr_enable")
+
+    def update(self, row_ptr: torch.Tensor, col: torch.Tensor, elabel: Optional[torch.Tensor],
+               rows: torch.Tensor, k: int, out: Optional[Sequence[torch.Tensor]] = None):
+        """P'_1..P'_k of the edited graph (row_ptr, col, elabel: same vertices and vertex labels)
+        whose rows differ from the cached graph's only at the vertices in ``rows`` (int32 device
+        tensor).  The cached chain (the last refine call) is left as it is."""
+        if out is None:
+            out = self.alloc_outputs(k)
+        row_ptr = _check(row_ptr, torch.int64, "row_ptr", self.device)
+        col = _check(col, torch.int32, "col", self.device)
+        elabel = _check(elabel, torch.int32, "elabel", self.device)
+        rows = _check(rows, torch.int32, "rows", self.device)
+        g = _Graph(int(row_ptr.numel()) - 1, int(col.numel()), self._g.nlabels, _ptr(row_ptr), _ptr(col),
+                   _ptr(elabel), self._g.vlabel_ptr, self._g.vlabel)
+        for t in out[:k]:
+            _check(t, torch.int32, "out", self.device)
+        ptrs = (ctypes.c_void_p * max(k, 1))(*[t.data_ptr() for t in out[:k]])
+        counts = (ctypes.c_int64 * max(k, 1))()
+        rc = _lib().kbisim_incr_update(self._ctx, ctypes.byref(g), _ptr(rows), int(rows.numel()), k, ptrs, counts)
+        if rc:
+            raise KbisimError(rc, "kbisim_incr_update")
+        return list(out[:k]), [int(counts[i]) for i in range(k)]
 
     def gather_probe(self, pid: torch.Tensor, reps: int = 5) -> float:
         """Milliseconds of one pass of the bare random gather over all entries (the signature bound)."""

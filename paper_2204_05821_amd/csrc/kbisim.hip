@@ -219,6 +219,21 @@ struct kbisim_ctx {
   // captured refinement loops
   bool use_graphs = false;
   std::map<GraphKey, hipGraphExec_t> graphs;
+  // incremental updates: refine calls from P0 cache their chain (key hashes,
+  // distinct counts and minimum-vertex block names per step) in the caller's
+  // state buffer; updates recompute only what edits can have changed
+  bool incr = false;
+  int incr_k = 0;  // steps of the cached chain
+  struct {
+    u64 *Hc;
+    u32 *DCc;
+    int32_t *MVc;
+    int64_t *tptr;
+    int32_t *tcol;
+    int32_t *names[2];
+    unsigned char *edited, *flag, *dirty, *skip;
+    int *small, *large, *changed, *cnt;
+  } is{};
 };
 
 struct kbisim_batch {
@@ -906,15 +921,12 @@ int launch_hub_staged(kbisim_ctx *c, const Src &src, const Schedule &s, const in
 // skip_in / single_out (work-efficient mode, else NULL): singleton flags of
 // the previous partition (those vertices are not refined: a singleton block
 // cannot split) and of the new one.
+// Signatures of every vertex not flagged in skip_in (all tiers): key hash,
+// distinct count and the insertion into the grouping table.
 template <class Src>
-int run_step(kbisim_ctx *c, const Src &src, const Schedule &s, int *out, int64_t *count_dev, int *cnt,
-             bool careful, int *gpid_next, bool zfresh, const unsigned char *skip_in = nullptr,
-             unsigned char *single_out = nullptr) {
-  const int n = (int)c->g.n;
-  if (n == 0) return 0;
+int launch_signatures(kbisim_ctx *c, const Src &src, const Schedule &s, bool zfresh, const unsigned char *skip_in) {
   const u64 tmask = table_mask<Src>(c);
-  int rc = advance(c, ADV_TABLE | ADV_CTABLE | ADV_ZERO | (s.ngchunks ? ADV_HUB : 0u), s);
-  if (rc) return rc;
+  int rc = 0;
   if ((rc = launch_ranges(c, src, s, zfresh ? 1 : 0, skip_in))) return rc;
   if (s.nhub) {
     const int *hubs = c->lists + s.hub_off;
@@ -941,18 +953,15 @@ int run_step(kbisim_ctx *c, const Src &src, const Schedule &s, int *out, int64_t
                                                                      skip_in);
     LAUNCH_CHECK();
   }
-  {
-    ProfScope ps(c, KBISIM_K_LOOKUP);
-    // after a call's first step only vertices with edges can change their
-    // representative (the others keep the one of that step)
-    const bool listed = !zfresh && s.nzv != nullptr;
-    const int count = listed ? (int)s.nonempty : n;
-    k_lookup<Src><<<blocks_for(std::max(count, 1), 256), 256, 0, c->stream>>>(
-        src, count, listed ? s.nzv : nullptr, c->H, c->DC, c->table, tmask, c->dep, c->rep,
-                                                             &cnt[0], c->vlist, &cnt[1], c->clA, c->err, c->zrep,
-                                                             zfresh ? 1 : 0, skip_in);
-    LAUNCH_CHECK();
-  }
+  return 0;
+}
+
+// After the lookup: exact checks of longer rows, one peeling round and, when
+// careful, host-driven peeling rounds until no collision is left.
+template <class Src>
+int settle_collisions(kbisim_ctx *c, const Src &src, const Schedule &s, int *cnt, bool careful) {
+  const int n = (int)c->g.n;
+  int rc = 0;
   {
     ProfScope ps(c, KBISIM_K_VERIFY);
     k_verify<Src><<<PERSIST_GRID, 256, 0, c->stream>>>(src, &cnt[0], c->vlist, c->DC, c->rep, &cnt[1], c->clA,
@@ -978,14 +987,46 @@ int run_step(kbisim_ctx *c, const Src &src, const Schedule &s, int *out, int64_t
       std::swap(in_list, out_list);
     }
   }
+  return 0;
+}
+
+template <class Src>
+int run_step(kbisim_ctx *c, const Src &src, const Schedule &s, int *out, int64_t *count_dev, int *cnt,
+             bool careful, int *gpid_next, bool zfresh, const unsigned char *skip_in = nullptr,
+             unsigned char *single_out = nullptr, int32_t *names_out = nullptr) {
+  const int n = (int)c->g.n;
+  if (n == 0) return 0;
+  const u64 tmask = table_mask<Src>(c);
+  int rc = advance(c, ADV_TABLE | ADV_CTABLE | ADV_ZERO | (s.ngchunks ? ADV_HUB : 0u), s);
+  if (rc) return rc;
+  if ((rc = launch_signatures(c, src, s, zfresh, skip_in))) return rc;
+  {
+    ProfScope ps(c, KBISIM_K_LOOKUP);
+    // after a call's first step only vertices with edges can change their
+    // representative (the others keep the one of that step)
+    const bool listed = !zfresh && s.nzv != nullptr;
+    const int count = listed ? (int)s.nonempty : n;
+    k_lookup<Src><<<blocks_for(std::max(count, 1), 256), 256, 0, c->stream>>>(
+        src, count, listed ? s.nzv : nullptr, c->H, c->DC, c->table, tmask, c->dep, c->rep,
+                                                             &cnt[0], c->vlist, &cnt[1], c->clA, c->err, c->zrep,
+                                                             zfresh ? 1 : 0, skip_in, nullptr, nullptr);
+    LAUNCH_CHECK();
+  }
+  if ((rc = settle_collisions(c, src, s, cnt, careful))) return rc;
   {
     ProfScope ps(c, KBISIM_K_SCAN);
     if ((rc = numbering_scan(c, n, out, count_dev))) return rc;
   }
   {
     ProfScope ps(c, KBISIM_K_ASSIGN);
-    k_assign<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, c->rep, out, gpid_next ? c->rank : nullptr, gpid_next,
-                                                        single_out ? c->multi : nullptr, c->dep);
+    if (names_out) {
+      k_assign_names<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, c->rep, out, names_out,
+                                                                gpid_next ? c->rank : nullptr, gpid_next, nullptr,
+                                                                nullptr, nullptr);
+    } else {
+      k_assign<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, c->rep, out, gpid_next ? c->rank : nullptr, gpid_next,
+                                                          single_out ? c->multi : nullptr, c->dep);
+    }
     LAUNCH_CHECK();
     if (single_out) {
       k_singletons<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, c->rep, c->multi, c->dep, single_out);
@@ -1016,9 +1057,13 @@ int enqueue_steps(kbisim_ctx *c, const int32_t *prev, int i0, int k, int32_t *co
     // work-efficient mode: singletons of P_i (flags of step i-1) are not refined
     const unsigned char *skip_in = (c->work_eff && i > 0) ? c->single[(i - 1) & 1] : nullptr;
     unsigned char *single_out = c->work_eff ? c->single[i & 1] : nullptr;
+    // with a cached chain (incremental updates) the next step names blocks by
+    // their minimum vertex, written into the cache
+    const bool cache = c->incr && !batch;
+    int32_t *names_out = cache ? c->is.MVc + (size_t)i * (size_t)n : nullptr;
     auto step = [&](auto src) {
       return run_step(c, src, c->sched, dst, &c->dcounts[i], c->counters + CNT_STRIDE * i, careful,
-                      c->gpid[(i + 1) & 1], i == 0, skip_in, single_out);
+                      c->gpid[(i + 1) & 1], i == 0, skip_in, single_out, names_out);
     };
     const int32_t *lab = separate_labels(c) ? sep_labels(c) : nullptr;
     if (c->hashed) {
@@ -1039,7 +1084,17 @@ int enqueue_steps(kbisim_ctx *c, const int32_t *prev, int i0, int k, int32_t *co
                                                                             dst, &c->dcounts[i], cstride, i, c->bcounts);
       LAUNCH_CHECK();
     }
-    prev = dst;
+    if (names_out) {
+      const unsigned g = std::min<unsigned>(blocks_for(2 * (int64_t)n, 256), 65536);
+      k_copy_i32<<<g, 256, 0, c->stream>>>(reinterpret_cast<int *>(c->is.Hc + (size_t)i * (size_t)n),
+                                           reinterpret_cast<const int *>(c->H), 2 * (int64_t)n);
+      k_copy_i32<<<g, 256, 0, c->stream>>>(reinterpret_cast<int *>(c->is.DCc + (size_t)i * (size_t)n),
+                                           reinterpret_cast<const int *>(c->DC), (int64_t)n);
+      LAUNCH_CHECK();
+      prev = names_out;
+    } else {
+      prev = dst;
+    }
   }
   return 0;
 }
@@ -1116,6 +1171,7 @@ int refine_impl(kbisim_ctx *c, const int32_t *start, int k, int32_t *const *out,
     return KBISIM_OK;
   }
   if (c->work_eff) return refine_we(c, start, k, out, counts);
+  if (c->incr) c->incr_k = 0;  // until this call completes
   const int32_t *p0 = start ? start : c->p0;
   int rc = 0;
   const bool graphed = c->use_graphs && !c->prof;
@@ -1165,6 +1221,7 @@ int refine_impl(kbisim_ctx *c, const int32_t *start, int k, int32_t *const *out,
     }
   if (first_bad >= 0) {
     const int32_t *prev = first_bad == 0 ? p0 : (batch ? c->ibuf[(first_bad - 1) & 1] : out[first_bad - 1]);
+    if (c->incr && !batch && first_bad > 0) prev = c->is.MVc + (size_t)(first_bad - 1) * (size_t)n;
     if ((rc = enqueue_steps(c, prev, first_bad, k, out, true, k))) return rc;
     HIP_TRY(hipMemcpyAsync(&err, c->err, sizeof err, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
@@ -1177,6 +1234,227 @@ int refine_impl(kbisim_ctx *c, const int32_t *start, int k, int32_t *const *out,
     HIP_TRY(hipMemcpyAsync(counts, c->dcounts, 8 * (size_t)k, hipMemcpyDeviceToHost, c->stream));
   }
   HIP_TRY(hipStreamSynchronize(c->stream));
+  if (c->incr && !batch) c->incr_k = start ? 0 : k;  // the cache holds a chain from P0
+  return KBISIM_OK;
+}
+
+// ---------------------------------------------------------------- incremental updates
+// The cached chain lives in a caller buffer: per step the key hash, distinct
+// count and minimum-vertex block name of every vertex, plus the in-rows of
+// the cached graph (to find the vertices whose targets' names changed) and
+// per-update scratch.
+struct IncrPlan {
+  size_t off_hc, off_dcc, off_mvc, off_tptr, off_tcol, off_names, off_edited, off_flag, off_dirty, off_skip,
+      off_small, off_large, off_changed, off_cnt, total;
+};
+IncrPlan incr_plan(int64_t n, int64_t m, int kmax) {
+  IncrPlan p{};
+  size_t at = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = at;
+    at = align_up(at + std::max<size_t>(bytes, 1));
+    return o;
+  };
+  const size_t N = (size_t)std::max<int64_t>(n, 1), K = (size_t)std::max(kmax, 1);
+  p.off_hc = take(8 * N * K);
+  p.off_dcc = take(4 * N * K);
+  p.off_mvc = take(4 * N * K);
+  p.off_tptr = take(8 * (N + 1));
+  p.off_tcol = take(4 * (size_t)std::max<int64_t>(m, 1));
+  p.off_names = take(8 * N);
+  p.off_edited = take(N);
+  p.off_flag = take(N);
+  p.off_dirty = take(N);
+  p.off_skip = take(N);
+  p.off_small = take(4 * N);
+  p.off_large = take(4 * N);
+  p.off_changed = take(4 * N);
+  p.off_cnt = take(64);
+  p.total = at;
+  return p;
+}
+
+constexpr int LIST_GRID_SMALL = 2048, LIST_GRID_LARGE = 1024, MARK_GRID = 2048;
+
+// One update step: P'_{i+1} from names_prev (P0 for i = 0, else the minimum
+// vertices of P'_i).  Vertices flagged dirty had their key inputs changed:
+// those with an edited row are read from the edited graph (list kernels),
+// the others from the cached graph's tiers (all but them skipped); the rest
+// take their cached key hash.  Grouping, exact checks (rows of the edited
+// graph), numbering and names then cover every vertex.
+template <class K, class TierSrc, class ListSrc>
+int update_step(kbisim_ctx *c, const TierSrc &tsrc, const ListSrc &lsrc, int i, const int32_t *names_prev,
+                int32_t *out, int64_t *count_dev, int *cnt) {
+  const int n = (int)c->g.n;
+  const size_t at = (size_t)i * (size_t)n;
+  auto &S = c->is;
+  const u64 tmask = c->tmask_steps;
+  const Schedule &s = c->sched;
+  int rc = advance(c, ADV_TABLE | ADV_CTABLE | ADV_ZERO | (s.ngchunks ? ADV_HUB : 0u), s);
+  if (rc) return rc;
+  if ((rc = launch_signatures(c, tsrc, s, true, S.skip))) return rc;
+  k_sig_list_small<ListSrc, K><<<LIST_GRID_SMALL, 256, 0, c->stream>>>(lsrc, &S.cnt[0], S.small, c->H, c->DC,
+                                                                       c->table, tmask, c->dep, c->hmask, c->zrep);
+  LAUNCH_CHECK();
+  k_sig_list_large<ListSrc, K><<<LIST_GRID_LARGE, 256, 0, c->stream>>>(lsrc, &S.cnt[1], S.large, c->H, c->DC,
+                                                                       c->table, tmask, c->dep, c->hmask, c->zrep,
+                                                                       c->err);
+  LAUNCH_CHECK();
+  k_insert_cached<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, S.dirty, S.Hc + at, S.DCc + at, names_prev, c->H,
+                                                              c->DC, c->table, tmask, c->dep, c->zrep);
+  LAUNCH_CHECK();
+  k_lookup<ListSrc><<<blocks_for(n, 256), 256, 0, c->stream>>>(lsrc, n, nullptr, c->H, c->DC, c->table, tmask, c->dep,
+                                                               c->rep, &cnt[0], c->vlist, &cnt[1], c->clA, c->err,
+                                                               c->zrep, 1, nullptr, S.dirty, S.MVc + at);
+  LAUNCH_CHECK();
+  if ((rc = settle_collisions(c, lsrc, s, cnt, true))) return rc;
+  if ((rc = numbering_scan(c, n, out, count_dev))) return rc;
+  k_assign_names<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, c->rep, out, S.names[i & 1], c->rank,
+                                                            c->gpid[(i + 1) & 1], S.MVc + at, &cnt[6], S.changed);
+  LAUNCH_CHECK();
+  k_mark_in_neighbours<<<MARK_GRID, 256, 0, c->stream>>>(&cnt[6], S.changed, S.tptr, S.tcol, S.flag);
+  LAUNCH_CHECK();
+  return 0;
+}
+
+template <bool HK, class K>
+int update_steps_t(kbisim_ctx *c, const kbisim_graph *gn, int k, int32_t *const *out) {
+  const int n = (int)c->g.n;
+  auto &S = c->is;
+  const int32_t *lab = separate_labels(c) ? sep_labels(c) : nullptr;
+  int rc = 0;
+  for (int i = 0; i < k; ++i) {
+    const int32_t *names_prev = i == 0 ? c->p0 : S.names[(i - 1) & 1];
+    int *cnt = c->counters + CNT_STRIDE * i;
+    if ((rc = fill_i32(c, cnt, CNT_STRIDE, 0))) return rc;
+    k_update_flags<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, S.edited, S.flag, S.dirty, S.skip);
+    LAUNCH_CHECK();
+    if ((rc = fill_i32(c, reinterpret_cast<int *>(S.flag), (n + 3) / 4, 0))) return rc;
+    const PlainSrcT<HK> lsrc{gn->row_ptr, gn->col, gn->elabel, names_prev, c->pb, c->kmask};
+    if (lab)
+      rc = update_step<K>(c, GraphSrcT<true, HK>{c->g.row_ptr, c->gcol, lab, c->gpid[i & 1], names_prev, c->pb,
+                                                 c->rbits, c->kmask},
+                          lsrc, i, names_prev, out[i], &c->dcounts[i], cnt);
+    else
+      rc = update_step<K>(c, GraphSrcT<false, HK>{c->g.row_ptr, c->gcol, nullptr, c->gpid[i & 1], names_prev, c->pb,
+                                                  c->rbits, c->kmask},
+                          lsrc, i, names_prev, out[i], &c->dcounts[i], cnt);
+    if (rc) return rc;
+  }
+  return 0;
+}
+
+int update_impl(kbisim_ctx *c, const kbisim_graph *gn, const int32_t *rows, int64_t nrows, int k,
+                int32_t *const *out, int64_t *counts) {
+  if (!c || !gn || !c->incr || c->num_graphs > 0) return KBISIM_EINVAL;
+  if (k < 0 || k > c->incr_k) return KBISIM_EINVAL;
+  if (k == 0) return KBISIM_OK;
+  if (!out || !counts) return KBISIM_EINVAL;
+  const int64_t n = c->g.n;
+  if (gn->n != n || gn->m < 0 || (gn->elabel == nullptr) != (c->g.elabel == nullptr)) return KBISIM_EINVAL;
+  if (gn->m >= (int64_t(1) << 62)) return KBISIM_ERANGE;
+  if (nrows < 0 || nrows > n || (nrows > 0 && !rows)) return KBISIM_EINVAL;
+  if (n == 0) {
+    for (int i = 0; i < k; ++i) counts[i] = 0;
+    return KBISIM_OK;
+  }
+  for (int i = 0; i < k; ++i)
+    if (!out[i]) return KBISIM_EINVAL;
+  if (!gn->row_ptr || (gn->m > 0 && !gn->col)) return KBISIM_EINVAL;
+  auto &S = c->is;
+  int rc = 0;
+  // the edited graph: row offsets, every target and label (any row is read by
+  // the exact checks), the listed vertices
+  if ((rc = fill_i32(c, (int *)c->err, 1, 0))) return rc;
+  k_validate_rows<<<blocks_for(n + 1, 256), 256, 0, c->stream>>>(n, gn->m, gn->row_ptr, c->err, ERR_GRAPH_ROWPTR);
+  if (gn->m > 0) {
+    k_validate_vals<<<blocks_for(gn->m, 256), 256, 0, c->stream>>>(gn->m, gn->col, n, c->err, ERR_GRAPH_COL);
+    if (gn->elabel)
+      k_validate_vals<<<blocks_for(gn->m, 256), 256, 0, c->stream>>>(gn->m, gn->elabel, (int64_t)c->max_label + 1,
+                                                                      c->err, ERR_GRAPH_ELABEL);
+  }
+  if (nrows) k_validate_vals<<<blocks_for(nrows, 256), 256, 0, c->stream>>>(nrows, rows, n, c->err, ERR_BAD_PID);
+  LAUNCH_CHECK();
+  u32 err = 0;
+  if ((rc = read_err(c, &err))) return rc;
+  if (err & ERR_BAD_PID) return KBISIM_EINVAL;
+  if (err) return KBISIM_EGRAPH;
+  // flags and the edited rows, split by length
+  if ((rc = fill_i32(c, reinterpret_cast<int *>(S.edited), (n + 3) / 4, 0))) return rc;
+  if ((rc = fill_i32(c, reinterpret_cast<int *>(S.flag), (n + 3) / 4, 0))) return rc;
+  if ((rc = fill_i32(c, S.cnt, 16, 0))) return rc;
+  if ((rc = fill_i32(c, S.cnt + 2, 1, (int)nrows))) return rc;
+  if (nrows) {
+    k_set_flags<<<std::min<unsigned>(blocks_for(nrows, 256), 65536), 256, 0, c->stream>>>(S.cnt + 2, rows, S.edited);
+    k_split_list<<<blocks_for(nrows, 256), 256, 0, c->stream>>>((int)nrows, rows, gn->row_ptr, &S.cnt[0], S.small,
+                                                                  &S.cnt[1], S.large);
+    LAUNCH_CHECK();
+  }
+  k_scatter_rank<<<blocks_for(n, 256), 256, 0, c->stream>>>((int)n, c->p0, c->rank, c->gpid[0]);
+  LAUNCH_CHECK();
+  // every vertex may carry a key in an update (edited rows can gain entries)
+  const u64 tmask_saved = c->tmask_steps;
+  c->tmask_steps = c->plan.tslots - 1;
+  if (c->hashed) rc = update_steps_t<true, u32>(c, gn, k, out);
+  else if (c->narrow) rc = update_steps_t<false, u32>(c, gn, k, out);
+  else rc = update_steps_t<false, u64>(c, gn, k, out);
+  c->tmask_steps = tmask_saved;
+  if (rc) return rc;
+  HIP_TRY(hipMemcpyAsync(&err, c->err, sizeof err, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipMemcpyAsync(counts, c->dcounts, 8 * (size_t)k, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  prof_collect(c);
+  if (err) return KBISIM_EINTERNAL;
+  return KBISIM_OK;
+}
+
+int incr_enable_impl(kbisim_ctx *c, void *state, size_t bytes) {
+  if (!c || c->num_graphs > 0 || c->work_eff || c->kmax < 1 || !state) return KBISIM_EINVAL;
+  const int64_t n = c->g.n, m = c->g.m;
+  const IncrPlan p = incr_plan(n, m, c->kmax);
+  if (bytes < p.total) return KBISIM_ENOSPACE;
+  char *w = (char *)state;
+  auto &S = c->is;
+  S.Hc = (u64 *)(w + p.off_hc);
+  S.DCc = (u32 *)(w + p.off_dcc);
+  S.MVc = (int32_t *)(w + p.off_mvc);
+  S.tptr = (int64_t *)(w + p.off_tptr);
+  S.tcol = (int32_t *)(w + p.off_tcol);
+  S.names[0] = (int32_t *)(w + p.off_names);
+  S.names[1] = S.names[0] + std::max<int64_t>(n, 1);
+  S.edited = (unsigned char *)(w + p.off_edited);
+  S.flag = (unsigned char *)(w + p.off_flag);
+  S.dirty = (unsigned char *)(w + p.off_dirty);
+  S.skip = (unsigned char *)(w + p.off_skip);
+  S.small = (int *)(w + p.off_small);
+  S.large = (int *)(w + p.off_large);
+  S.changed = (int *)(w + p.off_changed);
+  S.cnt = (int *)(w + p.off_cnt);
+  if (n > 0) {
+    // in-rows of the cached graph: count per target, offsets, scatter
+    int *cnt = S.names[0];
+    auto *cursor = reinterpret_cast<unsigned long long *>(S.Hc);
+    auto *tiles = reinterpret_cast<int64_t *>(S.small);
+    const int64_t nt = (n + SCAN_TILE - 1) / SCAN_TILE;
+    int rc = fill_i32(c, cnt, n, 0);
+    if (rc) return rc;
+    if (m > 0)
+      k_indegree<<<(unsigned)std::min<int64_t>(blocks_for(m, INDEG_CHUNK), 65536), 256, 0, c->stream>>>(m, c->g.col,
+                                                                                                       cnt);
+    k_sum_tiles64<<<(unsigned)nt, 256, 0, c->stream>>>(n, cnt, tiles);
+    k_scan_tiles64<<<1, 256, 0, c->stream>>>(nt, tiles);
+    k_write_ptr64<<<(unsigned)nt, 256, 0, c->stream>>>(n, cnt, tiles, S.tptr, cursor);
+    if (m > 0)
+      k_transpose_scatter<<<(unsigned)std::min<int64_t>(blocks_for(n * WAVE, 256), 65536), 256, 0, c->stream>>>(
+          n, c->g.row_ptr, c->g.col, nullptr, cursor, S.tcol, nullptr);
+    LAUNCH_CHECK();
+    HIP_TRY(hipStreamSynchronize(c->stream));
+  }
+  // loops captured before did not cache their steps
+  for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+  c->graphs.clear();
+  c->incr = true;
+  c->incr_k = 0;
   return KBISIM_OK;
 }
 
@@ -1499,6 +1777,7 @@ int step_async_impl(kbisim_ctx *c, int i, const int32_t *prev, int32_t *out) {
   if (!out || (!batch && i > 0 && !prev) || (const int32_t *)out == prev) return KBISIM_EINVAL;
   const int32_t *p = i == 0 ? c->p0 : (batch ? c->ibuf[(i - 1) & 1] : prev);
   int rc = 0;
+  if (c->incr) c->incr_k = 0;  // single steps do not keep a chain for updates
   if (i == 0 && (rc = fill_i32(c, (int *)c->err, 1, 0))) return rc;
   if ((rc = fill_i32(c, c->counters + CNT_STRIDE * i, CNT_STRIDE, 0))) return rc;
   std::vector<int32_t *> o((size_t)i + 1, out);  // indexed by step number
@@ -1550,6 +1829,7 @@ int kbisim_step_result(kbisim_ctx *c, int i, const int32_t *prev, int32_t *out, 
 
 int kbisim_work_efficient(kbisim_ctx *c, int enable, int *last_steps) {
   if (!c) return KBISIM_EINVAL;
+  if (enable > 0 && c->incr) return KBISIM_EINVAL;  // updates need every step of the chain cached
   if (last_steps) *last_steps = c->we_steps;
   if (enable >= 0) c->work_eff = enable != 0;
   return KBISIM_OK;
@@ -1575,6 +1855,21 @@ int kbisim_set_stream(kbisim_ctx *c, void *stream) {
   if (r != hipSuccess) return hip_fail(r);
   c->stream = s;
   return KBISIM_OK;
+}
+
+int kbisim_incr_state_bytes(const kbisim_graph *g, int kmax, size_t *bytes) {
+  int rc = check_sizes(g);
+  if (rc) return rc;
+  if (!bytes || kmax < 1 || kmax > (1 << 20)) return KBISIM_EINVAL;
+  *bytes = incr_plan(g->n, g->m, kmax).total;
+  return KBISIM_OK;
+}
+
+int kbisim_incr_enable(kbisim_ctx *c, void *state, size_t bytes) { return incr_enable_impl(c, state, bytes); }
+
+int kbisim_incr_update(kbisim_ctx *c, const kbisim_graph *g_new, const int32_t *rows, int64_t nrows, int k,
+                       int32_t *const *out_block_ids, int64_t *out_counts) {
+  return update_impl(c, g_new, rows, nrows, k, out_block_ids, out_counts);
 }
 
 int kbisim_destroy(kbisim_ctx *c) {

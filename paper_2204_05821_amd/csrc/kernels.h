@@ -1095,13 +1095,18 @@ __global__ void k_hub_final(Src src, const int *__restrict__ hubs, int nhub, u64
 // to a verification list (k_verify).  Mismatches (hash collisions) go to the
 // collision list with rep = -1.  Lists are appended with one atomic per
 // wave; they stay short, since device-wide atomics on one counter serialise.
+// Updates (dirty != NULL): a vertex and its candidate that are both clean
+// (key inputs unchanged) and shared a block in the cached chain (same cached
+// name mvc) still have equal keys, so they are accepted without the check.
 template <class Src>
 __global__ void __launch_bounds__(256) k_lookup(Src src, int count, const int *__restrict__ list,
                                                 const u64 *__restrict__ H, const u32 *__restrict__ DC,
                                                 const u64 *table, u64 tmask, const u32 *__restrict__ dep,
                                                 int *__restrict__ rep, int *vcount, int *vlist, int *ccount,
                                                 int *clist, u32 *err, const u64 *zrep, int zfresh,
-                                                const unsigned char *__restrict__ skip) {
+                                                const unsigned char *__restrict__ skip,
+                                                const unsigned char *__restrict__ dirty,
+                                                const int32_t *__restrict__ mvc) {
   const u32 epoch = dep[EP_TABLE], zep = dep[EP_ZERO];
   const int i = blockIdx.x * 256 + threadIdx.x;
   const bool act = i < count;
@@ -1133,6 +1138,8 @@ __global__ void __launch_bounds__(256) k_lookup(Src src, int count, const int *_
       } else if (src.own(v) != src.own(r) || dcv != DC[r]) {
         rep[v] = -1;
         collided = true;
+      } else if (dirty && !dirty[v] && !dirty[r] && mvc[v] == mvc[r]) {
+        rep[v] = r;
       } else {
         const int64_t bv = src.begin(v), ev = src.end(v);
         const int64_t br = src.begin(r), er = src.end(r);
@@ -1929,6 +1936,282 @@ __global__ void k_quotient_write(int64_t m, const u64 *__restrict__ keys, const 
     out_lab[o] = q.lb ? (int32_t)((k >> q.db) & ((1ULL << q.lb) - 1ULL)) : 0;
     out_src[o] = (int32_t)(k >> (q.db + q.lb));
   }
+}
+
+// ---------------------------------------------------------------- incremental updates
+// After edits to a graph, P'_1..P'_k are recomputed from the signatures of the
+// vertices whose key inputs changed, with the cached key hashes of the others
+// (the paper names incremental computation on evolving graphs as future
+// work, Sec. "Discussion").  Blocks are named by their minimum vertex inside
+// such chains (a name does not move when other blocks appear or vanish), so
+// the key hash of a vertex whose own name and targets' names are unchanged is
+// unchanged.  Dense first-vertex ids are still produced for every output.
+
+// A graph read straight from its CSR, with the previous block name of every
+// vertex in vertex order: the rows of edited vertices in the edited graph.
+template <bool HK>
+struct PlainSrcT {
+  static constexpr bool GRAPH = true;
+  static constexpr bool HASHED = HK;
+  const int64_t *row_ptr;
+  const int32_t *col;
+  const int32_t *elabel;  // null: every edge has label 0
+  const int32_t *names;   // previous block name of every vertex
+  u32 pb;
+  u32 kmask = 0xFFFFFFFFu;
+  __device__ inline int64_t begin(int v) const { return row_ptr[v]; }
+  __device__ inline int64_t end(int v) const { return row_ptr[v + 1]; }
+  __device__ inline u32 pmask() const { return pb >= 31 ? 0x7FFFFFFFu : (1u << pb) - 1u; }
+  __device__ inline u32 label(int64_t e) const { return elabel ? (u32)elabel[e] : 0u; }
+  __device__ inline u64 pair(int64_t e) const {
+    return ((u64)label(e) << 31) | (u64)((u32)names[col[e]] & pmask());
+  }
+  __device__ inline u32 own(int v) const { return (u32)names[v]; }
+  __device__ inline u32 hkey(u64 p) const { return pair_key32(p) & kmask; }
+  // the same key forms as GraphSrcT: exact (label << pb) | block, or a hash of the pair
+  __device__ inline u32 key32(int64_t e) const {
+    if constexpr (HK) return hkey(pair(e));
+    else return (label(e) << pb) | ((u32)names[col[e]] & pmask());
+  }
+  __device__ inline u64 mixin(u32 q) const {
+    if constexpr (HK) return (u64)q;
+    else return ((u64)(q >> pb) << 31) | (u64)(q & pmask());
+  }
+};
+
+constexpr int LIST_SMALL = 64;          // rows up to this many entries: one wave per vertex
+constexpr int LIST_SET_BYTES = 32768;   // LDS set of the workgroup-per-vertex kernel
+
+// Split a vertex list by row length (rows of `row_ptr`): <= LIST_SMALL entries
+// to small[], longer ones to large[].  Counters start at zero.
+__global__ void k_split_list(int count, const int *__restrict__ list, const int64_t *__restrict__ row_ptr,
+                             int *nsmall, int *small, int *nlarge, int *large) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool act = i < count;
+  const int v = act ? list[i] : 0;
+  const int64_t d = act ? row_ptr[v + 1] - row_ptr[v] : 0;
+  wave_append(nsmall, small, act && d <= LIST_SMALL, v);
+  wave_append(nlarge, large, act && d > LIST_SMALL, v);
+}
+
+// Key hash of the listed vertices with short rows: one wave per vertex, an
+// LDS set of 2 * LIST_SMALL slots per wave.  Writes H and DC and inserts the
+// key into the grouping table (or the empty-signature representatives).
+template <class Src, class K>
+__global__ void __launch_bounds__(256) k_sig_list_small(Src src, const int *__restrict__ count,
+                                                        const int *__restrict__ list, u64 *__restrict__ H,
+                                                        u32 *__restrict__ DC, u64 *table, u64 tmask,
+                                                        const u32 *__restrict__ dep, u64 hmask, u64 *zrep) {
+  typedef Keys<K> KO;
+  constexpr int SL = 2 * LIST_SMALL;
+  __shared__ K set[4][SL];
+  const u32 epoch = dep[EP_TABLE], zep = dep[EP_ZERO];
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x >> 6;
+  const int total = *count;
+  const int waves = gridDim.x * 4;
+  for (int item = blockIdx.x * 4 + w; item < total; item += waves) {
+    const int v = list[item];
+    const int64_t b = src.begin(v);
+    const int d = (int)(src.end(v) - b);
+    set[w][lane] = KO::EMPTY;
+    set[w][lane + WAVE] = KO::EMPTY;
+    __builtin_amdgcn_wave_barrier();
+    u64 a = 0;
+    u32 c = 0;
+    if (lane < d) {
+      const K p = KO::load(src, b + lane);
+      u32 sl = KO::hash(p) & (SL - 1);
+      while (true) {
+        const K old = atomicCAS(&set[w][sl], KO::EMPTY, p);
+        if (old == KO::EMPTY) { a = mix_pair(KO::mixin(src, p)); c = 1; break; }
+        if (old == p) break;
+        sl = (sl + 1) & (SL - 1);
+      }
+    }
+    a = wave_sum_u64(a);
+    c = wave_sum_u32(c);
+    if (lane == 0) {
+      const u32 own = src.own(v);
+      const u64 h = finalize_key(a, c, own) & hmask;
+      H[v] = h;
+      DC[v] = c;
+      key_insert(table, tmask, zrep, h, c, own, (u32)v, epoch, zep);
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+// The same for longer rows: one workgroup per vertex.  The row's distinct keys
+// go through an LDS set in Q passes (keys of sub-partition q in pass q), Q a
+// power of two doubled whenever a pass fills the set beyond 3/4 (the
+// partition is then redone), so any row length works.
+template <class Src, class K>
+__global__ void __launch_bounds__(256) k_sig_list_large(Src src, const int *__restrict__ count,
+                                                        const int *__restrict__ list, u64 *__restrict__ H,
+                                                        u32 *__restrict__ DC, u64 *table, u64 tmask,
+                                                        const u32 *__restrict__ dep, u64 hmask, u64 *zrep,
+                                                        u32 *err) {
+  typedef Keys<K> KO;
+  constexpr int PS = LIST_SET_BYTES / (int)sizeof(K);
+  __shared__ K set[PS];
+  __shared__ u64 sh_acc[4];
+  __shared__ u32 sh_cnt[4];
+  __shared__ u32 sh_fill[2];
+  const u32 epoch = dep[EP_TABLE], zep = dep[EP_ZERO];
+  const int total = *count;
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    const int v = list[item];
+    const int64_t b = src.begin(v), e = src.end(v);
+    const int64_t d = e - b;
+    u32 Q = 1;
+    while ((int64_t)Q * (PS / 2) < d && Q < (1u << 20)) Q <<= 1;
+    u64 acc = 0;
+    u32 cnt = 0;
+    for (int i = threadIdx.x; i < PS; i += 256) set[i] = KO::EMPTY;
+    for (u32 q = 0; q < Q;) {
+      if (threadIdx.x == 0) { sh_fill[0] = 0; sh_fill[1] = 0; }
+      __syncthreads();
+      u64 pacc = 0;
+      u32 pcnt = 0;
+      for (int64_t j = b + threadIdx.x; j < e; j += 256) {
+        const K p = KO::load(src, j);
+        if (Q > 1 && (sub_hash((u64)p) & (Q - 1)) != q) continue;
+        u32 sl = KO::hash(p) & (PS - 1);
+        while (true) {
+          const K cur = set[sl];
+          if (cur == p) break;
+          if (cur == KO::EMPTY) {
+            if (sh_fill[1]) break;  // overflowed: the pass is redone with more sub-partitions
+            const K old = atomicCAS(&set[sl], KO::EMPTY, p);
+            if (old == KO::EMPTY) {
+              pacc += mix_pair(KO::mixin(src, p));
+              ++pcnt;
+              if (atomicAdd(&sh_fill[0], 1u) + 1u >= (u32)(PS / 4 * 3)) sh_fill[1] = 1u;
+              break;
+            }
+            if (old == p) break;
+          }
+          sl = (sl + 1) & (PS - 1);
+        }
+      }
+      __syncthreads();
+      const bool over = sh_fill[1] != 0;
+      __syncthreads();
+      for (int i = threadIdx.x; i < PS; i += 256) set[i] = KO::EMPTY;
+      if (over) {
+        if (Q >= (1u << 24)) {
+          if (threadIdx.x == 0) atomicOr(err, ERR_VERIFY_OVERFLOW);
+          break;
+        }
+        Q <<= 1;
+        q = 0;
+        acc = 0;
+        cnt = 0;
+      } else {
+        acc += pacc;
+        cnt += pcnt;
+        ++q;
+      }
+      __syncthreads();
+    }
+    block_reduce_2(acc, cnt, sh_acc, sh_cnt);
+    if (threadIdx.x == 0) {
+      const u32 own = src.own(v);
+      const u64 h = finalize_key(acc, cnt, own) & hmask;
+      H[v] = h;
+      DC[v] = cnt;
+      key_insert(table, tmask, zrep, h, cnt, own, (u32)v, epoch, zep);
+    }
+    __syncthreads();
+  }
+}
+
+// Vertices whose key inputs did not change take their cached key hash and
+// distinct count and are inserted like the others (empty signatures by
+// their own block name, one atomic per distinct name in a wave).
+__global__ void __launch_bounds__(256) k_insert_cached(int n, const unsigned char *__restrict__ dirty,
+                                                       const u64 *__restrict__ Hc, const u32 *__restrict__ DCc,
+                                                       const int32_t *__restrict__ names, u64 *__restrict__ H,
+                                                       u32 *__restrict__ DC, u64 *table, u64 tmask,
+                                                       const u32 *__restrict__ dep, u64 *zrep) {
+  const u32 epoch = dep[EP_TABLE], zep = dep[EP_ZERO];
+  const int v = blockIdx.x * 256 + threadIdx.x;
+  const bool act = v < n && !dirty[v];
+  bool zero = false;
+  u32 own = 0;
+  if (act) {
+    const u32 c = DCc[v];
+    own = (u32)names[v];
+    DC[v] = c;
+    if (c) {
+      const u64 h = Hc[v];
+      H[v] = h;
+      table_insert(table, tmask, h, (u32)v, epoch);
+    } else {
+      zero = true;
+    }
+  }
+  zero_insert_wave(zrep, zero, own, (u32)v, zep);
+}
+
+// Every vertex: dense id from its representative (k_scan_write left the
+// heads' ids), its new block name (the representative: the block's minimum
+// vertex) in vertex order and, for the next gather, in rank order.  With
+// old_names (an update): vertices whose name differs from the cached chain's
+// are listed in changed[].
+__global__ void k_assign_names(int n, const int *__restrict__ rep, int *out, int32_t *__restrict__ names_out,
+                               const int *__restrict__ rank, int *__restrict__ gpid_next,
+                               const int32_t *__restrict__ old_names, int *nchanged, int *changed) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool act = v < n;
+  bool moved = false;
+  if (act) {
+    const int r = rep[v];
+    if (r != v) out[v] = r >= 0 ? out[r] : -1;
+    names_out[v] = r;
+    if (rank) {
+      const int rk = rank[v];
+      if (rk >= 0) gpid_next[rk] = r;
+    }
+    moved = old_names && old_names[v] != r;
+  }
+  if (old_names) wave_append(nchanged, changed, moved, v);
+}
+
+// Flags for the next step of an update: a vertex whose name changed, and every
+// vertex with an edge into it (in-rows of the cached graph; an edge that an
+// edit added starts at an edited row, which is recomputed at every step
+// anyway).  One wave per changed vertex.
+__global__ void __launch_bounds__(256) k_mark_in_neighbours(const int *__restrict__ count, const int *__restrict__ list,
+                                                            const int64_t *__restrict__ tptr,
+                                                            const int32_t *__restrict__ tcol,
+                                                            unsigned char *flag) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int total = *count;
+  const int waves = (int)((gridDim.x * blockDim.x) >> 6);
+  for (int item = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6); item < total; item += waves) {
+    const int w = list[item];
+    if (lane == 0) flag[w] = 1;
+    for (int64_t j = tptr[w] + lane; j < tptr[w + 1]; j += WAVE) flag[tcol[j]] = 1;
+  }
+}
+
+// Per vertex of an update step: dirty = its key inputs may have changed
+// (edited row, or flagged by the previous step); skip = not refined by the
+// tier kernels (clean, or edited: edited rows are read from the edited graph
+// by the list kernels).
+__global__ void k_update_flags(int n, const unsigned char *__restrict__ edited, const unsigned char *__restrict__ flag,
+                               unsigned char *__restrict__ dirty, unsigned char *__restrict__ skip) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const bool ed = edited[v] != 0, fl = flag[v] != 0;
+  dirty[v] = (ed || fl) ? 1 : 0;
+  skip[v] = (fl && !ed) ? 0 : 1;
+}
+
+__global__ void k_set_flags(const int *__restrict__ count, const int *__restrict__ list, unsigned char *flag) {
+  const int total = *count;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) flag[list[i]] = 1;
 }
 
 // ---------------------------------------------------------------- epochs
