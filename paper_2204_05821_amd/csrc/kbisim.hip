@@ -232,7 +232,9 @@ struct kbisim_ctx {
     int32_t *tcol;
     int32_t *names[2];
     unsigned char *edited, *flag, *dirty, *skip;
-    int *small, *large, *changed, *cnt;
+    int *small, *large, *psmall, *plarge, *changed, *cnt;
+    int32_t *bname;   // block names of an update step, by representative
+    u64 *zrep;        // empty-signature representatives by block name (names reach 2n)
   } is{};
 };
 
@@ -775,7 +777,7 @@ int build_rank(kbisim_ctx *c) {
       k_scan_tiles64<<<1, 256, 0, c->stream>>>(nt, tiles);
       k_write_ptr64<<<(unsigned)nt, 256, 0, c->stream>>>(hist_n, hist, tiles, offs, nullptr);
       LAUNCH_CHECK();
-      k_radix_scatter<<<(unsigned)rtiles, 256, 0, c->stream>>>(n, ka, shift, rtiles, offs, kb);
+      k_radix_scatter<<<(unsigned)rtiles, 256, 0, c->stream>>>(n, ka, shift, rtiles, offs, hist, kb);
       LAUNCH_CHECK();
       std::swap(ka, kb);
     }
@@ -840,9 +842,10 @@ int launch_range_kernel(kbisim_ctx *c, const Src &src, const Schedule &s, u64 tm
 
 // skip: singleton flags of the previous partition (work-efficient mode), or NULL.
 template <class Src, class K>
-int launch_ranges_k(kbisim_ctx *c, const Src &src, const Schedule &s, int zfresh, const unsigned char *skip) {
+int launch_ranges_k(kbisim_ctx *c, const Src &src, const Schedule &s, int zfresh, const unsigned char *skip,
+                    bool range_tier = true) {
   const u64 tmask = table_mask<Src>(c);
-  if (s.nranges) {
+  if (s.nranges && range_tier) {
     int rc = 0;
     if constexpr (Src::GRAPH) {
       rc = skip ? launch_range_kernel<Src, K, true>(c, src, s, tmask, zfresh, skip)
@@ -877,14 +880,15 @@ int launch_ranges_k(kbisim_ctx *c, const Src &src, const Schedule &s, int zfresh
 }
 
 template <class Src>
-int launch_ranges(kbisim_ctx *c, const Src &src, const Schedule &s, int zfresh, const unsigned char *skip) {
+int launch_ranges(kbisim_ctx *c, const Src &src, const Schedule &s, int zfresh, const unsigned char *skip,
+                  bool range_tier = true) {
   if constexpr (Src::HASHED) {
-    return launch_ranges_k<Src, u32>(c, src, s, zfresh, skip);
+    return launch_ranges_k<Src, u32>(c, src, s, zfresh, skip, range_tier);
   } else {
     if constexpr (Src::GRAPH) {
-      if (c->narrow) return launch_ranges_k<Src, u32>(c, src, s, zfresh, skip);
+      if (c->narrow) return launch_ranges_k<Src, u32>(c, src, s, zfresh, skip, range_tier);
     }
-    return launch_ranges_k<Src, u64>(c, src, s, zfresh, skip);
+    return launch_ranges_k<Src, u64>(c, src, s, zfresh, skip, range_tier);
   }
 }
 
@@ -924,10 +928,11 @@ int launch_hub_staged(kbisim_ctx *c, const Src &src, const Schedule &s, const in
 // Signatures of every vertex not flagged in skip_in (all tiers): key hash,
 // distinct count and the insertion into the grouping table.
 template <class Src>
-int launch_signatures(kbisim_ctx *c, const Src &src, const Schedule &s, bool zfresh, const unsigned char *skip_in) {
+int launch_signatures(kbisim_ctx *c, const Src &src, const Schedule &s, bool zfresh, const unsigned char *skip_in,
+                      bool range_tier = true) {
   const u64 tmask = table_mask<Src>(c);
   int rc = 0;
-  if ((rc = launch_ranges(c, src, s, zfresh ? 1 : 0, skip_in))) return rc;
+  if ((rc = launch_ranges(c, src, s, zfresh ? 1 : 0, skip_in, range_tier))) return rc;
   if (s.nhub) {
     const int *hubs = c->lists + s.hub_off;
     if (s.nchunks) {
@@ -1022,7 +1027,7 @@ int run_step(kbisim_ctx *c, const Src &src, const Schedule &s, int *out, int64_t
     if (names_out) {
       k_assign_names<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, c->rep, out, names_out,
                                                                 gpid_next ? c->rank : nullptr, gpid_next, nullptr,
-                                                                nullptr, nullptr);
+                                                                nullptr, nullptr, nullptr);
     } else {
       k_assign<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, c->rep, out, gpid_next ? c->rank : nullptr, gpid_next,
                                                           single_out ? c->multi : nullptr, c->dep);
@@ -1245,7 +1250,7 @@ int refine_impl(kbisim_ctx *c, const int32_t *start, int k, int32_t *const *out,
 // per-update scratch.
 struct IncrPlan {
   size_t off_hc, off_dcc, off_mvc, off_tptr, off_tcol, off_names, off_edited, off_flag, off_dirty, off_skip,
-      off_small, off_large, off_changed, off_cnt, total;
+      off_small, off_large, off_psmall, off_plarge, off_changed, off_bname, off_zrep, off_cnt, total;
 };
 IncrPlan incr_plan(int64_t n, int64_t m, int kmax) {
   IncrPlan p{};
@@ -1268,7 +1273,11 @@ IncrPlan incr_plan(int64_t n, int64_t m, int kmax) {
   p.off_skip = take(N);
   p.off_small = take(4 * N);
   p.off_large = take(4 * N);
+  p.off_psmall = take(4 * N);
+  p.off_plarge = take(4 * N);
   p.off_changed = take(4 * N);
+  p.off_bname = take(4 * N);
+  p.off_zrep = take(16 * N);
   p.off_cnt = take(64);
   p.total = at;
   return p;
@@ -1276,15 +1285,17 @@ IncrPlan incr_plan(int64_t n, int64_t m, int kmax) {
 
 constexpr int LIST_GRID_SMALL = 2048, LIST_GRID_LARGE = 1024, MARK_GRID = 2048;
 
-// One update step: P'_{i+1} from names_prev (P0 for i = 0, else the minimum
-// vertices of P'_i).  Vertices flagged dirty had their key inputs changed:
-// those with an edited row are read from the edited graph (list kernels),
-// the others from the cached graph's tiers (all but them skipped); the rest
-// take their cached key hash.  Grouping, exact checks (rows of the edited
-// graph), numbering and names then cover every vertex.
+// One update step: P'_{i+1} from names_prev (P0 for i = 0, else the block
+// names of P'_i).  Vertices flagged dirty had their key inputs changed: the
+// edited rows are read from the edited graph (list kernels); the others whose
+// targets' names changed are signed by the list kernels too when they are few
+// (prop_lists), else by the cached graph's tiers with every other vertex
+// skipped; all remaining vertices take their cached key hash.  Grouping,
+// exact checks (rows of the edited graph) and numbering then cover every
+// vertex; block names follow k_block_names_*.
 template <class K, class TierSrc, class ListSrc>
 int update_step(kbisim_ctx *c, const TierSrc &tsrc, const ListSrc &lsrc, int i, const int32_t *names_prev,
-                int32_t *out, int64_t *count_dev, int *cnt) {
+                int32_t *out, int64_t *count_dev, int *cnt, bool prop_lists, int nbig) {
   const int n = (int)c->g.n;
   const size_t at = (size_t)i * (size_t)n;
   auto &S = c->is;
@@ -1292,14 +1303,26 @@ int update_step(kbisim_ctx *c, const TierSrc &tsrc, const ListSrc &lsrc, int i, 
   const Schedule &s = c->sched;
   int rc = advance(c, ADV_TABLE | ADV_CTABLE | ADV_ZERO | (s.ngchunks ? ADV_HUB : 0u), s);
   if (rc) return rc;
-  if ((rc = launch_signatures(c, tsrc, s, true, S.skip))) return rc;
-  k_sig_list_small<ListSrc, K><<<LIST_GRID_SMALL, 256, 0, c->stream>>>(lsrc, &S.cnt[0], S.small, c->H, c->DC,
-                                                                       c->table, tmask, c->dep, c->hmask, c->zrep);
-  LAUNCH_CHECK();
-  k_sig_list_large<ListSrc, K><<<LIST_GRID_LARGE, 256, 0, c->stream>>>(lsrc, &S.cnt[1], S.large, c->H, c->DC,
-                                                                       c->table, tmask, c->dep, c->hmask, c->zrep,
-                                                                       c->err);
-  LAUNCH_CHECK();
+  auto lists = [&](int *count, int *small, int *large) -> int {
+    k_sig_list_small<ListSrc, K><<<LIST_GRID_SMALL, 256, 0, c->stream>>>(lsrc, count, small, c->H, c->DC, c->table,
+                                                                         tmask, c->dep, c->hmask, c->zrep);
+    LAUNCH_CHECK();
+    k_sig_list_large<ListSrc, K><<<LIST_GRID_LARGE, 256, 0, c->stream>>>(lsrc, count + 1, large, c->H, c->DC,
+                                                                         c->table, tmask, c->dep, c->hmask, c->zrep,
+                                                                         c->err);
+    LAUNCH_CHECK();
+    return 0;
+  };
+  if (prop_lists) {
+    // short and medium rows from lists, long ones by the row and hub tiers
+    if ((rc = lists(&cnt[8], S.psmall, S.plarge))) return rc;
+    if (nbig && (rc = launch_signatures(c, tsrc, s, true, S.skip, false))) return rc;
+  } else {
+    k_skip_all_flagged<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, S.edited, S.dirty, S.skip);
+    LAUNCH_CHECK();
+    if ((rc = launch_signatures(c, tsrc, s, true, S.skip))) return rc;
+  }
+  if ((rc = lists(&S.cnt[0], S.small, S.large))) return rc;
   k_insert_cached<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, S.dirty, S.Hc + at, S.DCc + at, names_prev, c->H,
                                                               c->DC, c->table, tmask, c->dep, c->zrep);
   LAUNCH_CHECK();
@@ -1309,8 +1332,11 @@ int update_step(kbisim_ctx *c, const TierSrc &tsrc, const ListSrc &lsrc, int i, 
   LAUNCH_CHECK();
   if ((rc = settle_collisions(c, lsrc, s, cnt, true))) return rc;
   if ((rc = numbering_scan(c, n, out, count_dev))) return rc;
+  k_block_names_fresh<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, c->rep, S.bname);
+  k_block_names_clean<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, c->rep, S.dirty, S.MVc + at, S.bname);
   k_assign_names<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, c->rep, out, S.names[i & 1], c->rank,
-                                                            c->gpid[(i + 1) & 1], S.MVc + at, &cnt[6], S.changed);
+                                                            c->gpid[(i + 1) & 1], S.bname, S.MVc + at, &cnt[6],
+                                                            S.changed);
   LAUNCH_CHECK();
   k_mark_in_neighbours<<<MARK_GRID, 256, 0, c->stream>>>(&cnt[6], S.changed, S.tptr, S.tcol, S.flag);
   LAUNCH_CHECK();
@@ -1327,18 +1353,24 @@ int update_steps_t(kbisim_ctx *c, const kbisim_graph *gn, int k, int32_t *const 
     const int32_t *names_prev = i == 0 ? c->p0 : S.names[(i - 1) & 1];
     int *cnt = c->counters + CNT_STRIDE * i;
     if ((rc = fill_i32(c, cnt, CNT_STRIDE, 0))) return rc;
-    k_update_flags<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, S.edited, S.flag, S.dirty, S.skip);
+    k_update_flags<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, S.edited, S.flag, S.dirty, S.skip, gn->row_ptr,
+                                                              cnt + 8, S.psmall, S.plarge);
     LAUNCH_CHECK();
     if ((rc = fill_i32(c, reinterpret_cast<int *>(S.flag), (n + 3) / 4, 0))) return rc;
+    // few vertices flagged by the previous step: sign them from lists
+    int np[3] = {0, 0, 0};
+    HIP_TRY(hipMemcpyAsync(np, cnt + 8, sizeof np, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    const bool prop_lists = (int64_t)np[0] + np[1] + np[2] <= std::max<int64_t>(n / 8, 1);
     const PlainSrcT<HK> lsrc{gn->row_ptr, gn->col, gn->elabel, names_prev, c->pb, c->kmask};
     if (lab)
       rc = update_step<K>(c, GraphSrcT<true, HK>{c->g.row_ptr, c->gcol, lab, c->gpid[i & 1], names_prev, c->pb,
                                                  c->rbits, c->kmask},
-                          lsrc, i, names_prev, out[i], &c->dcounts[i], cnt);
+                          lsrc, i, names_prev, out[i], &c->dcounts[i], cnt, prop_lists, np[2]);
     else
       rc = update_step<K>(c, GraphSrcT<false, HK>{c->g.row_ptr, c->gcol, nullptr, c->gpid[i & 1], names_prev, c->pb,
                                                   c->rbits, c->kmask},
-                          lsrc, i, names_prev, out[i], &c->dcounts[i], cnt);
+                          lsrc, i, names_prev, out[i], &c->dcounts[i], cnt, prop_lists, np[2]);
     if (rc) return rc;
   }
   return 0;
@@ -1392,13 +1424,17 @@ int update_impl(kbisim_ctx *c, const kbisim_graph *gn, const int32_t *rows, int6
   }
   k_scatter_rank<<<blocks_for(n, 256), 256, 0, c->stream>>>((int)n, c->p0, c->rank, c->gpid[0]);
   LAUNCH_CHECK();
-  // every vertex may carry a key in an update (edited rows can gain entries)
+  // every vertex may carry a key in an update (edited rows can gain entries),
+  // and empty signatures are grouped by block names below 2n
   const u64 tmask_saved = c->tmask_steps;
+  u64 *zrep_saved = c->zrep;
   c->tmask_steps = c->plan.tslots - 1;
+  c->zrep = S.zrep;
   if (c->hashed) rc = update_steps_t<true, u32>(c, gn, k, out);
   else if (c->narrow) rc = update_steps_t<false, u32>(c, gn, k, out);
   else rc = update_steps_t<false, u64>(c, gn, k, out);
   c->tmask_steps = tmask_saved;
+  c->zrep = zrep_saved;
   if (rc) return rc;
   HIP_TRY(hipMemcpyAsync(&err, c->err, sizeof err, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipMemcpyAsync(counts, c->dcounts, 8 * (size_t)k, hipMemcpyDeviceToHost, c->stream));
@@ -1411,6 +1447,7 @@ int update_impl(kbisim_ctx *c, const kbisim_graph *gn, const int32_t *rows, int6
 int incr_enable_impl(kbisim_ctx *c, void *state, size_t bytes) {
   if (!c || c->num_graphs > 0 || c->work_eff || c->kmax < 1 || !state) return KBISIM_EINVAL;
   const int64_t n = c->g.n, m = c->g.m;
+  if (n >= (int64_t(1) << 30)) return KBISIM_ERANGE;  // update block names reach 2n
   const IncrPlan p = incr_plan(n, m, c->kmax);
   if (bytes < p.total) return KBISIM_ENOSPACE;
   char *w = (char *)state;
@@ -1428,8 +1465,13 @@ int incr_enable_impl(kbisim_ctx *c, void *state, size_t bytes) {
   S.skip = (unsigned char *)(w + p.off_skip);
   S.small = (int *)(w + p.off_small);
   S.large = (int *)(w + p.off_large);
+  S.psmall = (int *)(w + p.off_psmall);
+  S.plarge = (int *)(w + p.off_plarge);
   S.changed = (int *)(w + p.off_changed);
+  S.bname = (int32_t *)(w + p.off_bname);
+  S.zrep = (u64 *)(w + p.off_zrep);
   S.cnt = (int *)(w + p.off_cnt);
+  int rc0 = 0;
   if (n > 0) {
     // in-rows of the cached graph: count per target, offsets, scatter
     int *cnt = S.names[0];
@@ -1449,6 +1491,17 @@ int incr_enable_impl(kbisim_ctx *c, void *state, size_t bytes) {
           n, c->g.row_ptr, c->g.col, nullptr, cursor, S.tcol, nullptr);
     LAUNCH_CHECK();
     HIP_TRY(hipStreamSynchronize(c->stream));
+  }
+  if ((rc0 = fill_u64(c, S.zrep, 2 * std::max<int64_t>(n, 1), ~0ULL))) return rc0;
+  // Update steps name blocks below 2n, so pairs keep one more bit of block
+  // name; a pair's value (label << 31 | name) does not depend on that width,
+  // only whether exact 32-bit keys still fit does.
+  {
+    u32 pb = 1, lb = 0;
+    while (pb < 31 && (int64_t(1) << pb) < 2 * n) ++pb;
+    while (lb < 32 && (c->max_label >> lb) != 0) ++lb;
+    c->pb = pb;
+    c->hashed = c->narrow && (c->tune.key_bits == 32 || pb + lb > 31);
   }
   // loops captured before did not cache their steps
   for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
@@ -2115,10 +2168,10 @@ int kbisim_transpose(int64_t n, int64_t m, const int64_t *row_ptr, const int32_t
 
 namespace {
 struct QuotientPlan {
-  size_t off_a, off_b, off_hist, off_offs, off_tiles, off_flag, off_pos, off_word, total;
+  size_t off_a, off_b, off_hist, off_offs, off_tiles, off_flag, off_pos, off_word, off_tgt, total;
   int64_t rtiles, hist_n, htiles, mtiles;
 };
-QuotientPlan quotient_plan(int64_t m) {
+QuotientPlan quotient_plan(int64_t n, int64_t m) {
   QuotientPlan p{};
   size_t at = 0;
   auto take = [&](size_t bytes) {
@@ -2139,8 +2192,32 @@ QuotientPlan quotient_plan(int64_t m) {
   p.off_flag = take(4 * (size_t)M);
   p.off_pos = take(8 * (size_t)(M + 1));
   p.off_word = take(16);
+  p.off_tgt = take(4 * (size_t)std::max<int64_t>(n, 1));
   p.total = at;
   return p;
+}
+
+// One summary key per CSR entry, over the degree schedule of the context.
+extern "C++" template <class Src>
+int quotient_keys(kbisim_ctx *c, const Src &src, const int32_t *src_pid, const int32_t *tgt, QKey q, u64 *keys) {
+  const Schedule &S = c->sched;
+  hipStream_t st = c->stream;
+  if (S.nranges) {
+    if (S.range_edges == 1024)
+      k_quotient_range<Src, 1024><<<(unsigned)S.nranges, 256, 0, st>>>(src, c->ranges, src_pid, tgt, q, keys);
+    else
+      k_quotient_range<Src, 2048><<<(unsigned)S.nranges, 256, 0, st>>>(src, c->ranges, src_pid, tgt, q, keys);
+  }
+  const int nrows = S.nbig + S.nrow8 + S.nrow20;
+  if (nrows) k_quotient_rows<Src><<<(unsigned)nrows, 256, 0, st>>>(src, c->ranges + S.nranges, src_pid, tgt, q, keys);
+  const int *hubs = c->lists + S.hub_off;
+  if (S.nchunks)
+    k_quotient_hubs<Src, HubChunk><<<(unsigned)S.nchunks, 256, 0, st>>>(src, c->chunks, hubs, src_pid, tgt, q, keys);
+  if (S.ngchunks)
+    k_quotient_hubs<Src, HubGChunk><<<(unsigned)S.ngchunks, 256, 0, st>>>(src, c->gchunks, hubs, src_pid, tgt, q,
+                                                                          keys);
+  HIP_TRY(hipGetLastError());
+  return 0;
 }
 
 // Exclusive scan of cnt[0..len) into out[0..len] (64-bit), on `s`.
@@ -2156,7 +2233,7 @@ int scan64(hipStream_t s, int64_t len, const int *cnt, int64_t *tiles, int64_t *
 
 int kbisim_quotient_workspace_bytes(kbisim_ctx *c, size_t *bytes) {
   if (!c || !bytes || c->num_graphs > 0) return KBISIM_EINVAL;
-  *bytes = quotient_plan(c->g.m).total;
+  *bytes = quotient_plan(c->g.n, c->g.m).total;
   return KBISIM_OK;
 }
 
@@ -2167,7 +2244,7 @@ int kbisim_quotient(kbisim_ctx *c, const int32_t *src_pid, const int32_t *dst_pi
   *out_count = 0;
   if (m == 0) return KBISIM_OK;
   if (!out_src || !out_label || !out_dst) return KBISIM_EINVAL;
-  const QuotientPlan p = quotient_plan(m);
+  const QuotientPlan p = quotient_plan(n, m);
   if (!workspace || ws_bytes < p.total) return KBISIM_ENOSPACE;
   hipStream_t s = c->stream;
   char *w = (char *)workspace;
@@ -2195,14 +2272,21 @@ int kbisim_quotient(kbisim_ctx *c, const int32_t *src_pid, const int32_t *dst_pi
   const int sbits = std::max(1, bit_width(hw[1]));
   const int total_bits = sbits + (int)q.lb + (int)q.db;
   if (total_bits > 64) return KBISIM_ERANGE;
-  k_quotient_keys<<<(unsigned)std::min<int64_t>(blocks_for(n * WAVE, 256), 65536), 256, 0, s>>>(
-      n, c->g.row_ptr, c->g.col, c->g.elabel, src_pid, dst_pid, q, ka);
+  // target blocks in rank order, then one key per entry over the schedule
+  int32_t *tgt = (int32_t *)(w + p.off_tgt);
+  k_scatter_rank<<<blocks_for(n, 256), 256, 0, s>>>((int)n, dst_pid, c->rank, tgt);
   HIP_TRY(hipGetLastError());
+  const int32_t *lab = separate_labels(c) ? sep_labels(c) : nullptr;
+  if (lab) rc = quotient_keys(c, GraphSrcT<true>{c->g.row_ptr, c->gcol, lab, tgt, src_pid, c->pb, c->rbits}, src_pid,
+                             tgt, q, ka);
+  else rc = quotient_keys(c, GraphSrcT<false>{c->g.row_ptr, c->gcol, nullptr, tgt, src_pid, c->pb, c->rbits}, src_pid,
+                         tgt, q, ka);
+  if (rc) return rc;
   for (int shift = 0; shift < total_bits; shift += 8) {
     k_radix_hist<<<(unsigned)p.rtiles, 256, 0, s>>>(m, ka, shift, p.rtiles, hist);
     HIP_TRY(hipGetLastError());
     if ((rc = scan64(s, p.hist_n, hist, tiles, offs))) return rc;
-    k_radix_scatter<<<(unsigned)p.rtiles, 256, 0, s>>>(m, ka, shift, p.rtiles, offs, kb);
+    k_radix_scatter<<<(unsigned)p.rtiles, 256, 0, s>>>(m, ka, shift, p.rtiles, offs, hist, kb);
     HIP_TRY(hipGetLastError());
     std::swap(ka, kb);
   }

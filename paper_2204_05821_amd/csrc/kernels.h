@@ -1814,19 +1814,86 @@ struct QKey {
   u32 lb, db;  // bits of the label and target-block fields
 };
 
-__global__ void k_quotient_keys(int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
-                                const int32_t *__restrict__ elabel, const int32_t *__restrict__ src_pid,
-                                const int32_t *__restrict__ dst_pid, QKey q, u64 *keys) {
-  const int lane = threadIdx.x & (WAVE - 1);
-  const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-  for (int64_t v = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; v < n; v += waves) {
-    const u64 sb = (u64)(u32)src_pid[v] << (q.lb + q.db);
-    const int64_t b = row_ptr[v], e = row_ptr[v + 1];
-    for (int64_t i = b + lane; i < e; i += WAVE) {
-      const u64 l = elabel ? (u64)(u32)elabel[i] : 0ULL;
-      keys[i] = sb | (l << q.db) | (u64)(u32)dst_pid[col[i]];
+// Keys are built from the context's gather layout: the target's rank (and
+// packed or sorted label) per entry, and the target blocks copied into rank
+// order, so the per-entry gather runs over the hot-first array of the
+// signature kernels.  One workgroup per range of the degree schedule (owner
+// of each entry by a max-scan over row starts, as in k_sig_range), one per
+// single-row range, and one per hub chunk; consecutive entries give
+// consecutive keys.
+template <class Src>
+__device__ inline u64 quotient_key(const Src &src, const int32_t *__restrict__ tgt, QKey q, u64 sb, int64_t e) {
+  u32 l, r;
+  src.entry(e, l, r);
+  return sb | ((u64)l << q.db) | (u64)(u32)tgt[r];
+}
+
+template <class Src, int EMAX>
+__global__ void __launch_bounds__(256) k_quotient_range(Src src, const Range *__restrict__ ranges,
+                                                        const int32_t *__restrict__ src_pid,
+                                                        const int32_t *__restrict__ tgt, QKey q, u64 *keys) {
+  __shared__ int roff[RANGE_VERTS + 1];
+  __shared__ unsigned char owner[EMAX];
+  __shared__ u64 sbk[RANGE_VERTS];
+  __shared__ u32 wmax[4];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const Range rg = ranges[blockIdx.x];
+  const int V = rg.v1 - rg.v0;
+  for (int i = t; i <= V; i += 256) roff[i] = (int)(src.begin_lo(rg.v0 + i) - (u32)rg.e0);  // V may be 256
+  if (t < V) sbk[t] = (u64)(u32)src_pid[rg.v0 + t] << (q.lb + q.db);
+  for (int i = t; i < EMAX; i += 256) owner[i] = 0;
+  __syncthreads();
+  for (int i = t; i < V; i += 256)
+    if (roff[i + 1] > roff[i]) owner[roff[i]] = (unsigned char)i;
+  __syncthreads();
+  {
+    constexpr int PER = EMAX / 256;
+    u32 run = 0;
+    const int j0 = t * PER;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) run = max(run, (u32)owner[j0 + k]);
+    u32 x = run;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const u32 y = __shfl_up(x, o, WAVE);
+      if (lane >= o) x = max(x, y);
     }
+    if (lane == 63) wmax[w] = x;
+    __syncthreads();
+    u32 carry = __shfl_up(x, 1, WAVE);
+    if (lane == 0) carry = 0;
+    for (int i = 0; i < w; ++i) carry = max(carry, wmax[i]);
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      carry = max(carry, (u32)owner[j0 + k]);
+      owner[j0 + k] = (unsigned char)carry;
+    }
+    __syncthreads();
   }
+  for (int j = t; j < rg.ne; j += 256) keys[rg.e0 + j] = quotient_key(src, tgt, q, sbk[owner[j]], rg.e0 + j);
+}
+
+// Entry segments of one row each: single-row ranges (v0, e0, ne) ...
+template <class Src>
+__global__ void __launch_bounds__(256) k_quotient_rows(Src src, const Range *__restrict__ rows,
+                                                       const int32_t *__restrict__ src_pid,
+                                                       const int32_t *__restrict__ tgt, QKey q, u64 *keys) {
+  const Range rw = rows[blockIdx.x];
+  const u64 sb = (u64)(u32)src_pid[rw.v0] << (q.lb + q.db);
+  for (int j = threadIdx.x; j < rw.ne; j += 256) keys[rw.e0 + j] = quotient_key(src, tgt, q, sb, rw.e0 + j);
+}
+
+// ... and hub chunks (entries [b, e) of the hub's row).
+template <class Src, class Chunk>
+__global__ void __launch_bounds__(256) k_quotient_hubs(Src src, const Chunk *__restrict__ chunks,
+                                                       const int *__restrict__ hubs,
+                                                       const int32_t *__restrict__ src_pid,
+                                                       const int32_t *__restrict__ tgt, QKey q, u64 *keys) {
+  const Chunk c = chunks[blockIdx.x];
+  const int v = hubs[c.hub];
+  const u64 sb = (u64)(u32)src_pid[v] << (q.lb + q.db);
+  const int64_t row = src.begin(v);
+  for (int64_t e = row + c.b + threadIdx.x; e < row + c.e; e += 256) keys[e] = quotient_key(src, tgt, q, sb, e);
 }
 
 constexpr int RADIX_ITEMS = 16;                  // keys per thread per tile
@@ -1848,24 +1915,38 @@ __global__ void __launch_bounds__(256) k_radix_hist(int64_t m, const u64 *__rest
   hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
 }
 
-// Stable scatter of a tile: keys are ranked chunk by chunk (256 keys, in
+// Stable scatter of a tile.  Keys are ranked chunk by chunk (256 keys, in
 // index order); inside a chunk, lanes with equal digits are found with one
-// ballot per digit bit, and waves are ordered through per-digit counts.
+// ballot per digit bit, and waves are ordered through per-digit counts.  Each
+// key first goes to its digit-sorted place inside the tile, in LDS; then the
+// tile is written out in that order, so the keys of one digit leave as one
+// run of consecutive addresses (whole lines) instead of one scattered key
+// per lane.  hist holds the tile's digit counts (k_radix_hist).
 __global__ void __launch_bounds__(256) k_radix_scatter(int64_t m, const u64 *__restrict__ keys, int shift,
                                                        int64_t ntiles, const int64_t *__restrict__ offs,
-                                                       u64 *__restrict__ out) {
-  __shared__ int64_t base[256];     // next output position per digit
-  __shared__ int wcnt[4][256];      // per-wave digit counts of the current chunk
+                                                       const int *__restrict__ hist, u64 *__restrict__ out) {
+  __shared__ u64 sk[RADIX_TILE];     // the tile in digit order
+  __shared__ int64_t base[256];      // global position of the tile's first key of each digit
+  __shared__ int tstart[256];        // tile position of the first key of each digit
+  __shared__ int run[256];           // keys of each digit placed so far
+  __shared__ int wcnt[4][256];       // per-wave digit counts of the current chunk
+  __shared__ u32 sh_w[4];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   base[t] = offs[(int64_t)t * ntiles + blockIdx.x];
+  {
+    u32 total;
+    tstart[t] = (int)block_exclusive_scan((u32)hist[(int64_t)t * ntiles + blockIdx.x], sh_w, &total);
+  }
+  run[t] = 0;
   const int64_t tile0 = (int64_t)blockIdx.x * RADIX_TILE;
+  const int cnt = (int)min<int64_t>(m - tile0, RADIX_TILE);
   const u64 lt = (1ULL << lane) - 1ULL;
   for (int j = 0; j < RADIX_ITEMS; ++j) {
     for (int q = 0; q < 4; ++q) wcnt[q][t] = 0;
     __syncthreads();
-    const int64_t i = tile0 + j * 256 + t;
-    const bool valid = i < m;
-    const u64 key = valid ? keys[i] : 0ULL;
+    const int i = j * 256 + t;
+    const bool valid = i < cnt;
+    const u64 key = valid ? keys[tile0 + i] : 0ULL;
     const u32 d = (u32)(key >> shift) & 255u;
     u64 peers = __ballot(valid);
 #pragma unroll
@@ -1879,12 +1960,16 @@ __global__ void __launch_bounds__(256) k_radix_scatter(int64_t m, const u64 *__r
     if (valid) {
       int before = 0;
       for (int q = 0; q < w; ++q) before += wcnt[q][d];
-      out[base[d] + before + rank] = key;
+      sk[tstart[d] + run[d] + before + rank] = key;
     }
     __syncthreads();
-    // advance the per-digit bases by this chunk's counts
-    base[t] += wcnt[0][t] + wcnt[1][t] + wcnt[2][t] + wcnt[3][t];
-    __syncthreads();
+    run[t] += wcnt[0][t] + wcnt[1][t] + wcnt[2][t] + wcnt[3][t];
+  }
+  __syncthreads();
+  for (int i = t; i < cnt; i += 256) {
+    const u64 key = sk[i];
+    const u32 d = (u32)(key >> shift) & 255u;
+    out[base[d] + (i - tstart[d])] = key;
   }
 }
 
@@ -2155,27 +2240,47 @@ __global__ void __launch_bounds__(256) k_insert_cached(int n, const unsigned cha
 }
 
 // Every vertex: dense id from its representative (k_scan_write left the
-// heads' ids), its new block name (the representative: the block's minimum
-// vertex) in vertex order and, for the next gather, in rank order.  With
-// old_names (an update): vertices whose name differs from the cached chain's
-// are listed in changed[].
+// heads' ids), its new block name in vertex order and, for the next gather,
+// in rank order.  The name is the representative (the block's minimum
+// vertex), or with bname (an update) the name bname[] gives the
+// representative's block; vertices whose name differs from the cached
+// chain's (old_names) are then listed in changed[].
 __global__ void k_assign_names(int n, const int *__restrict__ rep, int *out, int32_t *__restrict__ names_out,
                                const int *__restrict__ rank, int *__restrict__ gpid_next,
-                               const int32_t *__restrict__ old_names, int *nchanged, int *changed) {
+                               const int32_t *__restrict__ bname, const int32_t *__restrict__ old_names,
+                               int *nchanged, int *changed) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   const bool act = v < n;
   bool moved = false;
   if (act) {
     const int r = rep[v];
     if (r != v) out[v] = r >= 0 ? out[r] : -1;
-    names_out[v] = r;
+    const int nm = bname ? (r >= 0 ? bname[r] : -1) : r;
+    names_out[v] = nm;
     if (rank) {
       const int rk = rank[v];
-      if (rk >= 0) gpid_next[rk] = r;
+      if (rk >= 0) gpid_next[rk] = nm;
     }
-    moved = old_names && old_names[v] != r;
+    moved = old_names && old_names[v] != nm;
   }
   if (old_names) wave_append(nchanged, changed, moved, v);
+}
+
+// Block names of an update step.  A new block that keeps an unchanged
+// (clean) member takes that member's cached name: clean members of one new
+// block shared their cached block (their keys did not change), and no other
+// new block holds a member of it, so such names stay distinct.  A block of
+// changed vertices only is named n + its minimum vertex, above every cached
+// name.  Clean vertices therefore never change names, and renaming does not
+// spread through blocks that only gained or lost a few members.
+__global__ void k_block_names_fresh(int n, const int *__restrict__ rep, int32_t *__restrict__ bname) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n && rep[v] == v) bname[v] = n + v;
+}
+__global__ void k_block_names_clean(int n, const int *__restrict__ rep, const unsigned char *__restrict__ dirty,
+                                    const int32_t *__restrict__ old_names, int32_t *__restrict__ bname) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n && !dirty[v]) bname[rep[v]] = old_names[v];
 }
 
 // Flags for the next step of an update: a vertex whose name changed, and every
@@ -2200,13 +2305,38 @@ __global__ void __launch_bounds__(256) k_mark_in_neighbours(const int *__restric
 // (edited row, or flagged by the previous step); skip = not refined by the
 // tier kernels (clean, or edited: edited rows are read from the edited graph
 // by the list kernels).
+constexpr int LIST_BIG = 4096;  // longer flagged rows go to the row and hub tiers
+
+// The flagged vertices whose rows were not edited are also listed, split by
+// row length (as k_split_list), so that few of them can be signed by the list
+// kernels instead of the tier kernels: counts at cnt[0] (short) and cnt[1]
+// (up to LIST_BIG entries); longer rows are counted at cnt[2] and left to
+// the row and hub tiers (skip[v] = 0 for exactly them).
 __global__ void k_update_flags(int n, const unsigned char *__restrict__ edited, const unsigned char *__restrict__ flag,
-                               unsigned char *__restrict__ dirty, unsigned char *__restrict__ skip) {
+                               unsigned char *__restrict__ dirty, unsigned char *__restrict__ skip,
+                               const int64_t *__restrict__ row_ptr, int *cnt, int *small, int *large) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= n) return;
-  const bool ed = edited[v] != 0, fl = flag[v] != 0;
-  dirty[v] = (ed || fl) ? 1 : 0;
-  skip[v] = (fl && !ed) ? 0 : 1;
+  const bool act = v < n;
+  bool prop = false;
+  int64_t d = 0;
+  if (act) {
+    const bool ed = edited[v] != 0, fl = flag[v] != 0;
+    dirty[v] = (ed || fl) ? 1 : 0;
+    prop = fl && !ed;
+    if (prop) d = row_ptr[v + 1] - row_ptr[v];
+    skip[v] = (prop && d > LIST_BIG) ? 0 : 1;
+  }
+  wave_append(&cnt[0], small, prop && d <= LIST_SMALL, v);
+  wave_append(&cnt[1], large, prop && d > LIST_SMALL && d <= LIST_BIG, v);
+  const u64 big = __ballot(prop && d > LIST_BIG);
+  if ((threadIdx.x & (WAVE - 1)) == 0 && big) atomicAdd(&cnt[2], (int)__popcll(big));
+}
+
+// Skip flags when every flagged unedited vertex goes to the tier kernels.
+__global__ void k_skip_all_flagged(int n, const unsigned char *__restrict__ edited, const unsigned char *__restrict__ flag_dirty,
+                                   unsigned char *__restrict__ skip) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n) skip[v] = (flag_dirty[v] && !edited[v]) ? 0 : 1;
 }
 
 __global__ void k_set_flags(const int *__restrict__ count, const int *__restrict__ list, unsigned char *flag) {

@@ -61,6 +61,27 @@ def test_chain_summaries_match_reference(make):
     r.close()
 
 
+@pytest.mark.parametrize("kbits", [0, 64])
+def test_summaries_over_every_tier(kbits):
+    """Keys are built over the degree schedule: ranges, single-row ranges, staged hub chunks and
+    the global-set hubs (rows past the staged limit); labels packed, separate and sorted with
+    their rows."""
+    kb = _kb()
+    from tests.test_gpu_parity import giant_hub_graph, tier_graph
+    wide = tier_graph(seed=14, labels=50, shared_targets=2000)
+    wide.elabel = (((1 << 30) + 7) * (wide.elabel.astype(np.int64) + 1) % ((1 << 31) - 1)).astype(np.int32)
+    seen = {"range": 0, "workgroup": 0, "hub": 0, "hub_global": 0}
+    for g in [tier_graph(seed=12, labels=50, shared_targets=2000), wide, giant_hub_graph()]:
+        ids, _ = oracle.refine(g, 2)
+        r = kb.Refiner(*kb.to_device(g), kmax=2, tuning=kb.tuning(key_bits=kbits))
+        for tier, v in r.schedule_info().items():
+            seen[tier] += v["vertices"]
+        exp = quotient.summary_graph(g, ids[1], ids[0])
+        assert np.array_equal(gpu_summary(r, ids[1], ids[0]), exp), g.name
+        r.close()
+    assert all(v > 0 for v in seen.values()), seen
+
+
 def test_singletons_and_random_small_graphs():
     kb = _kb()
     rng = random.Random(5)
