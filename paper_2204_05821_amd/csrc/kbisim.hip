@@ -234,6 +234,17 @@ struct kbisim_ctx {
     unsigned char *edited, *flag, *dirty, *skip;
     int *small, *large, *psmall, *plarge, *changed, *cnt;
     int32_t *bname;   // block names of an update step, by representative
+    int32_t *keep;    // cached names kept by blocks of changed vertices, by representative
+    unsigned char *claimed;  // cached names taken by blocks with an unchanged member
+    int *heavy;       // changed vertices with long in-rows
+    // edited rows longer than LIST_BIG: one global set each (chunks of HUB_GCHUNK)
+    int *huge;
+    HubGChunk *huge_chunks;
+    u64 *huge_acc;
+    u32 *huge_cnt;
+    int nhuge = 0, nhuge_chunks = 0;
+    int64_t huge_set_begin = 0, huge_set_slots = 0;
+    int64_t huge_cap = 0, huge_chunk_cap = 0;
     u64 *zrep;        // empty-signature representatives by block name (names reach 2n)
   } is{};
 };
@@ -1027,7 +1038,7 @@ int run_step(kbisim_ctx *c, const Src &src, const Schedule &s, int *out, int64_t
     if (names_out) {
       k_assign_names<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, c->rep, out, names_out,
                                                                 gpid_next ? c->rank : nullptr, gpid_next, nullptr,
-                                                                nullptr, nullptr, nullptr);
+                                                                nullptr, nullptr, nullptr, nullptr);
     } else {
       k_assign<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, c->rep, out, gpid_next ? c->rank : nullptr, gpid_next,
                                                           single_out ? c->multi : nullptr, c->dep);
@@ -1250,7 +1261,9 @@ int refine_impl(kbisim_ctx *c, const int32_t *start, int k, int32_t *const *out,
 // per-update scratch.
 struct IncrPlan {
   size_t off_hc, off_dcc, off_mvc, off_tptr, off_tcol, off_names, off_edited, off_flag, off_dirty, off_skip,
-      off_small, off_large, off_psmall, off_plarge, off_changed, off_bname, off_zrep, off_cnt, total;
+      off_small, off_large, off_psmall, off_plarge, off_changed, off_bname, off_keep, off_claimed, off_heavy, off_zrep,
+      off_huge, off_hchunks, off_hacc, off_hcnt, off_cnt, total;
+  int64_t huge_cap, huge_chunk_cap;
 };
 IncrPlan incr_plan(int64_t n, int64_t m, int kmax) {
   IncrPlan p{};
@@ -1277,7 +1290,16 @@ IncrPlan incr_plan(int64_t n, int64_t m, int kmax) {
   p.off_plarge = take(4 * N);
   p.off_changed = take(4 * N);
   p.off_bname = take(4 * N);
+  p.off_keep = take(4 * N);
+  p.off_claimed = take(N);
+  p.off_heavy = take(4 * N);
   p.off_zrep = take(16 * N);
+  p.huge_cap = std::max<int64_t>(m, 0) / LIST_BIG + 1;
+  p.huge_chunk_cap = std::max<int64_t>(m, 0) / HUB_GCHUNK + p.huge_cap + 1;
+  p.off_huge = take(4 * (size_t)p.huge_cap);
+  p.off_hchunks = take(sizeof(HubGChunk) * (size_t)p.huge_chunk_cap);
+  p.off_hacc = take(8 * (size_t)p.huge_cap);
+  p.off_hcnt = take(4 * (size_t)p.huge_cap);
   p.off_cnt = take(64);
   p.total = at;
   return p;
@@ -1301,7 +1323,8 @@ int update_step(kbisim_ctx *c, const TierSrc &tsrc, const ListSrc &lsrc, int i, 
   auto &S = c->is;
   const u64 tmask = c->tmask_steps;
   const Schedule &s = c->sched;
-  int rc = advance(c, ADV_TABLE | ADV_CTABLE | ADV_ZERO | (s.ngchunks ? ADV_HUB : 0u), s);
+  // the hub epoch starts at 0 and must be in 1..3 before any global set is used
+  int rc = advance(c, ADV_TABLE | ADV_CTABLE | ADV_ZERO | (s.ngchunks || S.nhuge ? ADV_HUB : 0u), s);
   if (rc) return rc;
   auto lists = [&](int *count, int *small, int *large) -> int {
     k_sig_list_small<ListSrc, K><<<LIST_GRID_SMALL, 256, 0, c->stream>>>(lsrc, count, small, c->H, c->DC, c->table,
@@ -1323,8 +1346,20 @@ int update_step(kbisim_ctx *c, const TierSrc &tsrc, const ListSrc &lsrc, int i, 
     if ((rc = launch_signatures(c, tsrc, s, true, S.skip))) return rc;
   }
   if ((rc = lists(&S.cnt[0], S.small, S.large))) return rc;
-  k_insert_cached<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, S.dirty, S.Hc + at, S.DCc + at, names_prev, c->H,
-                                                              c->DC, c->table, tmask, c->dep, c->zrep);
+  if (S.nhuge) {
+    // edited rows too long for one workgroup: global hash sets in the spare hub-set space
+    if ((rc = fill_u64(c, c->hubsets + S.huge_set_begin, S.huge_set_slots, 0))) return rc;
+    k_sig_hub_global<ListSrc><<<(unsigned)S.nhuge_chunks, 256, 0, c->stream>>>(
+        lsrc, S.huge_chunks, S.huge, c->hubsets + S.huge_set_begin, S.huge_acc, S.huge_cnt, c->dep, nullptr);
+    LAUNCH_CHECK();
+    k_hub_final<ListSrc><<<blocks_for(S.nhuge, 256), 256, 0, c->stream>>>(lsrc, S.huge, S.nhuge, S.huge_acc,
+                                                                          S.huge_cnt, c->H, c->DC, c->table, tmask,
+                                                                          c->dep, c->hmask, c->zrep, nullptr);
+    LAUNCH_CHECK();
+  }
+  k_insert_cached<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, S.dirty, S.Hc + at, S.DCc + at, S.MVc + at,
+                                                              names_prev, c->H, c->DC, c->table, tmask, c->dep,
+                                                              c->zrep);
   LAUNCH_CHECK();
   k_lookup<ListSrc><<<blocks_for(n, 256), 256, 0, c->stream>>>(lsrc, n, nullptr, c->H, c->DC, c->table, tmask, c->dep,
                                                                c->rep, &cnt[0], c->vlist, &cnt[1], c->clA, c->err,
@@ -1332,13 +1367,19 @@ int update_step(kbisim_ctx *c, const TierSrc &tsrc, const ListSrc &lsrc, int i, 
   LAUNCH_CHECK();
   if ((rc = settle_collisions(c, lsrc, s, cnt, true))) return rc;
   if ((rc = numbering_scan(c, n, out, count_dev))) return rc;
-  k_block_names_fresh<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, c->rep, S.bname);
-  k_block_names_clean<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, c->rep, S.dirty, S.MVc + at, S.bname);
+  if ((rc = fill_i32(c, reinterpret_cast<int *>(S.claimed), (n + 3) / 4, 0))) return rc;
+  k_block_names_fresh<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, c->rep, S.bname, S.keep);
+  k_block_names_clean<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, c->rep, S.dirty, S.MVc + at, S.bname,
+                                                                  S.claimed);
+  k_block_names_keep<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, c->rep, S.dirty, S.MVc + at, S.bname, S.claimed,
+                                                                 S.keep);
   k_assign_names<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, c->rep, out, S.names[i & 1], c->rank,
-                                                            c->gpid[(i + 1) & 1], S.bname, S.MVc + at, &cnt[6],
-                                                            S.changed);
+                                                            c->gpid[(i + 1) & 1], S.bname, S.keep, S.MVc + at,
+                                                            &cnt[6], S.changed);
   LAUNCH_CHECK();
-  k_mark_in_neighbours<<<MARK_GRID, 256, 0, c->stream>>>(&cnt[6], S.changed, S.tptr, S.tcol, S.flag);
+  k_mark_in_neighbours<<<MARK_GRID, 256, 0, c->stream>>>(&cnt[6], S.changed, S.tptr, S.tcol, S.flag, &cnt[7],
+                                                         S.heavy);
+  k_mark_heavy<<<MARK_GRID, 256, 0, c->stream>>>(&cnt[7], S.heavy, S.tptr, S.tcol, S.flag);
   LAUNCH_CHECK();
   return 0;
 }
@@ -1416,11 +1457,70 @@ int update_impl(kbisim_ctx *c, const kbisim_graph *gn, const int32_t *rows, int6
   if ((rc = fill_i32(c, reinterpret_cast<int *>(S.flag), (n + 3) / 4, 0))) return rc;
   if ((rc = fill_i32(c, S.cnt, 16, 0))) return rc;
   if ((rc = fill_i32(c, S.cnt + 2, 1, (int)nrows))) return rc;
+  S.nhuge = 0;
+  S.nhuge_chunks = 0;
   if (nrows) {
     k_set_flags<<<std::min<unsigned>(blocks_for(nrows, 256), 65536), 256, 0, c->stream>>>(S.cnt + 2, rows, S.edited);
+    // edited rows longer than LIST_BIG take global sets when the spare hub-set
+    // space holds them (else they stay with the multi-pass list kernel)
+    const int64_t free_begin = c->sched.gset_end;
+    const int64_t free_end = c->glab ? (int64_t)(reinterpret_cast<const u64 *>(c->glab) - c->hubsets)
+                                     : c->plan.hubset_slots;
+    const bool room = free_end - free_begin > 2 * LIST_BIG;
     k_split_list<<<blocks_for(nrows, 256), 256, 0, c->stream>>>((int)nrows, rows, gn->row_ptr, &S.cnt[0], S.small,
-                                                                  &S.cnt[1], S.large);
+                                                                  &S.cnt[1], S.large,
+                                                                  room ? (int64_t)LIST_BIG : (int64_t)1 << 62,
+                                                                  &S.cnt[3], S.huge);
     LAUNCH_CHECK();
+    if (room) {
+      int nh = 0;
+      HIP_TRY(hipMemcpyAsync(&nh, &S.cnt[3], sizeof nh, hipMemcpyDeviceToHost, c->stream));
+      HIP_TRY(hipStreamSynchronize(c->stream));
+      if (nh > 0) {
+        std::vector<int> hv((size_t)nh);
+        std::vector<int64_t> b((size_t)nh), e((size_t)nh);
+        HIP_TRY(hipMemcpyAsync(hv.data(), S.huge, 4 * (size_t)nh, hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        for (int i = 0; i < nh; ++i) {
+          HIP_TRY(hipMemcpyAsync(&b[(size_t)i], gn->row_ptr + hv[(size_t)i], 8, hipMemcpyDeviceToHost, c->stream));
+          HIP_TRY(hipMemcpyAsync(&e[(size_t)i], gn->row_ptr + hv[(size_t)i] + 1, 8, hipMemcpyDeviceToHost, c->stream));
+        }
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        std::vector<HubGChunk> ch;
+        std::vector<int> keep_list;
+        int64_t at = free_begin;
+        for (int i = 0; i < nh; ++i) {
+          const int64_t d = e[(size_t)i] - b[(size_t)i];
+          if (at + 2 * d > free_end || (int64_t)ch.size() + d / HUB_GCHUNK + 1 > S.huge_chunk_cap) {
+            keep_list.push_back(hv[(size_t)i]);  // no room: back to the list kernel
+            continue;
+          }
+          const int idx = (int)(i - (int)keep_list.size());
+          for (int64_t x = 0; x < d; x += HUB_GCHUNK)
+            ch.push_back(HubGChunk{idx, 0, x, std::min<int64_t>(d, x + HUB_GCHUNK), at - free_begin, 2 * d});
+          hv[(size_t)idx] = hv[(size_t)i];
+          at += 2 * d;
+        }
+        S.nhuge = nh - (int)keep_list.size();
+        S.nhuge_chunks = (int)ch.size();
+        S.huge_set_begin = free_begin;
+        S.huge_set_slots = at - free_begin;
+        if (S.nhuge) {
+          HIP_TRY(hipMemcpyAsync(S.huge, hv.data(), 4 * (size_t)S.nhuge, hipMemcpyHostToDevice, c->stream));
+          HIP_TRY(hipMemcpyAsync(S.huge_chunks, ch.data(), sizeof(HubGChunk) * ch.size(), hipMemcpyHostToDevice,
+                                 c->stream));
+        }
+        if (!keep_list.empty()) {  // append to the large list (its count is on the device)
+          int nl = 0;
+          HIP_TRY(hipMemcpyAsync(&nl, &S.cnt[1], sizeof nl, hipMemcpyDeviceToHost, c->stream));
+          HIP_TRY(hipStreamSynchronize(c->stream));
+          HIP_TRY(hipMemcpyAsync(S.large + nl, keep_list.data(), 4 * keep_list.size(), hipMemcpyHostToDevice,
+                                 c->stream));
+          if ((rc = fill_i32(c, &S.cnt[1], 1, nl + (int)keep_list.size()))) return rc;
+        }
+        HIP_TRY(hipStreamSynchronize(c->stream));
+      }
+    }
   }
   k_scatter_rank<<<blocks_for(n, 256), 256, 0, c->stream>>>((int)n, c->p0, c->rank, c->gpid[0]);
   LAUNCH_CHECK();
@@ -1469,6 +1569,15 @@ int incr_enable_impl(kbisim_ctx *c, void *state, size_t bytes) {
   S.plarge = (int *)(w + p.off_plarge);
   S.changed = (int *)(w + p.off_changed);
   S.bname = (int32_t *)(w + p.off_bname);
+  S.keep = (int32_t *)(w + p.off_keep);
+  S.claimed = (unsigned char *)(w + p.off_claimed);
+  S.heavy = (int *)(w + p.off_heavy);
+  S.huge = (int *)(w + p.off_huge);
+  S.huge_chunks = (HubGChunk *)(w + p.off_hchunks);
+  S.huge_acc = (u64 *)(w + p.off_hacc);
+  S.huge_cnt = (u32 *)(w + p.off_hcnt);
+  S.huge_cap = p.huge_cap;
+  S.huge_chunk_cap = p.huge_chunk_cap;
   S.zrep = (u64 *)(w + p.off_zrep);
   S.cnt = (int *)(w + p.off_cnt);
   int rc0 = 0;
@@ -1493,6 +1602,8 @@ int incr_enable_impl(kbisim_ctx *c, void *state, size_t bytes) {
     HIP_TRY(hipStreamSynchronize(c->stream));
   }
   if ((rc0 = fill_u64(c, S.zrep, 2 * std::max<int64_t>(n, 1), ~0ULL))) return rc0;
+  if ((rc0 = fill_u64(c, S.huge_acc, S.huge_cap, 0))) return rc0;
+  if ((rc0 = fill_i32(c, (int *)S.huge_cnt, S.huge_cap, 0))) return rc0;
   // Update steps name blocks below 2n, so pairs keep one more bit of block
   // name; a pair's value (label << 31 | name) does not depend on that width,
   // only whether exact 32-bit keys still fit does.

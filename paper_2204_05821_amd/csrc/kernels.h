@@ -1027,6 +1027,10 @@ struct HubGChunk {
   int64_t set_size;
 };
 
+// Set slots hold key | epoch << 62 and count as empty unless their epoch is
+// the current one, so dep[EP_HUB] must be 1..3 (advanced at least once; a
+// zeroed set with epoch 0 would have no empty slot) and each set must hold
+// more slots than its row has entries.
 template <class Src>
 __global__ void __launch_bounds__(256) k_sig_hub_global(Src src, const HubGChunk *__restrict__ chunks,
                                                         const int *__restrict__ hubs, u64 *sets, u64 *hub_acc,
@@ -2067,16 +2071,21 @@ struct PlainSrcT {
 constexpr int LIST_SMALL = 64;          // rows up to this many entries: one wave per vertex
 constexpr int LIST_SET_BYTES = 32768;   // LDS set of the workgroup-per-vertex kernel
 
+constexpr int LIST_BIG = 4096;  // longer rows go to the row and hub tiers, or a global set
+
 // Split a vertex list by row length (rows of `row_ptr`): <= LIST_SMALL entries
-// to small[], longer ones to large[].  Counters start at zero.
+// to small[], up to huge_min to large[], longer ones to huge[].  Counters
+// start at zero.
 __global__ void k_split_list(int count, const int *__restrict__ list, const int64_t *__restrict__ row_ptr,
-                             int *nsmall, int *small, int *nlarge, int *large) {
+                             int *nsmall, int *small, int *nlarge, int *large, int64_t huge_min, int *nhuge,
+                             int *huge) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const bool act = i < count;
   const int v = act ? list[i] : 0;
   const int64_t d = act ? row_ptr[v + 1] - row_ptr[v] : 0;
   wave_append(nsmall, small, act && d <= LIST_SMALL, v);
-  wave_append(nlarge, large, act && d > LIST_SMALL, v);
+  wave_append(nlarge, large, act && d > LIST_SMALL && d <= huge_min, v);
+  wave_append(nhuge, huge, act && d > huge_min, v);
 }
 
 // Key hash of the listed vertices with short rows: one wave per vertex, an
@@ -2212,10 +2221,16 @@ __global__ void __launch_bounds__(256) k_sig_list_large(Src src, const int *__re
 }
 
 // Vertices whose key inputs did not change take their cached key hash and
-// distinct count and are inserted like the others (empty signatures by
-// their own block name, one atomic per distinct name in a wave).
+// distinct count.  Only some of them are inserted: a clean vertex that headed
+// its cached block (mvc[v] == v), and every clean member of a cached block
+// whose head changed.  Clean members of one cached block stay together with
+// equal keys, so every new block's minimum vertex is inserted (its head if
+// clean, else all its clean members; changed vertices insert themselves),
+// and the table ends with the same minimum per slot as if all were inserted.
+// Empty signatures go by their own block name, the same way.
 __global__ void __launch_bounds__(256) k_insert_cached(int n, const unsigned char *__restrict__ dirty,
                                                        const u64 *__restrict__ Hc, const u32 *__restrict__ DCc,
+                                                       const int32_t *__restrict__ mvc,
                                                        const int32_t *__restrict__ names, u64 *__restrict__ H,
                                                        u32 *__restrict__ DC, u64 *table, u64 tmask,
                                                        const u32 *__restrict__ dep, u64 *zrep) {
@@ -2226,14 +2241,16 @@ __global__ void __launch_bounds__(256) k_insert_cached(int n, const unsigned cha
   u32 own = 0;
   if (act) {
     const u32 c = DCc[v];
-    own = (u32)names[v];
     DC[v] = c;
+    const int head = mvc[v];
+    const bool ins = head == v || dirty[head];
     if (c) {
       const u64 h = Hc[v];
       H[v] = h;
-      table_insert(table, tmask, h, (u32)v, epoch);
-    } else {
+      if (ins) table_insert(table, tmask, h, (u32)v, epoch);
+    } else if (ins) {
       zero = true;
+      own = (u32)names[v];
     }
   }
   zero_insert_wave(zrep, zero, own, (u32)v, zep);
@@ -2247,15 +2264,19 @@ __global__ void __launch_bounds__(256) k_insert_cached(int n, const unsigned cha
 // chain's (old_names) are then listed in changed[].
 __global__ void k_assign_names(int n, const int *__restrict__ rep, int *out, int32_t *__restrict__ names_out,
                                const int *__restrict__ rank, int *__restrict__ gpid_next,
-                               const int32_t *__restrict__ bname, const int32_t *__restrict__ old_names,
-                               int *nchanged, int *changed) {
+                               const int32_t *__restrict__ bname, const int32_t *__restrict__ keep,
+                               const int32_t *__restrict__ old_names, int *nchanged, int *changed) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   const bool act = v < n;
   bool moved = false;
   if (act) {
     const int r = rep[v];
     if (r != v) out[v] = r >= 0 ? out[r] : -1;
-    const int nm = bname ? (r >= 0 ? bname[r] : -1) : r;
+    int nm = r;
+    if (bname) {
+      nm = r >= 0 ? bname[r] : -1;
+      if (nm >= n && keep[r] < n) nm = keep[r];
+    }
     names_out[v] = nm;
     if (rank) {
       const int rk = rank[v];
@@ -2273,31 +2294,75 @@ __global__ void k_assign_names(int n, const int *__restrict__ rep, int *out, int
 // changed vertices only is named n + its minimum vertex, above every cached
 // name.  Clean vertices therefore never change names, and renaming does not
 // spread through blocks that only gained or lost a few members.
-__global__ void k_block_names_fresh(int n, const int *__restrict__ rep, int32_t *__restrict__ bname) {
+// A block of changed vertices only that holds the vertex which named a cached
+// block (old_names[v] == v), and whose cached name no clean member claimed,
+// keeps that name (the smallest such vertex, so the choice is
+// deterministic): a block whose members all changed keys but stayed
+// together, e.g. a singleton, is not renamed.  No other new block can hold
+// that vertex, so the name stays distinct.
+__global__ void k_block_names_fresh(int n, const int *__restrict__ rep, int32_t *__restrict__ bname,
+                                    int32_t *__restrict__ keep) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v < n && rep[v] == v) bname[v] = n + v;
+  if (v < n && rep[v] == v) {
+    bname[v] = n + v;
+    keep[v] = 0x7FFFFFFF;
+  }
 }
 __global__ void k_block_names_clean(int n, const int *__restrict__ rep, const unsigned char *__restrict__ dirty,
-                                    const int32_t *__restrict__ old_names, int32_t *__restrict__ bname) {
+                                    const int32_t *__restrict__ old_names, int32_t *__restrict__ bname,
+                                    unsigned char *__restrict__ claimed) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v < n && !dirty[v]) bname[rep[v]] = old_names[v];
+  if (v < n && !dirty[v]) {
+    const int32_t nm = old_names[v];
+    bname[rep[v]] = nm;
+    claimed[nm] = 1;
+  }
+}
+__global__ void k_block_names_keep(int n, const int *__restrict__ rep, const unsigned char *__restrict__ dirty,
+                                   const int32_t *__restrict__ old_names, const int32_t *__restrict__ bname,
+                                   const unsigned char *__restrict__ claimed, int32_t *keep) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n && dirty[v] && old_names[v] == v && !claimed[v]) {
+    const int r = rep[v];
+    if (bname[r] >= n) atomicMin(&keep[r], v);
+  }
 }
 
 // Flags for the next step of an update: a vertex whose name changed, and every
 // vertex with an edge into it (in-rows of the cached graph; an edge that an
 // edit added starts at an edited row, which is recomputed at every step
 // anyway).  One wave per changed vertex.
+constexpr int MARK_LIGHT = 4096;  // in-rows up to this long are marked by one wave
+
 __global__ void __launch_bounds__(256) k_mark_in_neighbours(const int *__restrict__ count, const int *__restrict__ list,
                                                             const int64_t *__restrict__ tptr,
                                                             const int32_t *__restrict__ tcol,
-                                                            unsigned char *flag) {
+                                                            unsigned char *flag, int *nheavy, int *heavy) {
   const int lane = threadIdx.x & (WAVE - 1);
   const int total = *count;
   const int waves = (int)((gridDim.x * blockDim.x) >> 6);
   for (int item = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6); item < total; item += waves) {
     const int w = list[item];
-    if (lane == 0) flag[w] = 1;
-    for (int64_t j = tptr[w] + lane; j < tptr[w + 1]; j += WAVE) flag[tcol[j]] = 1;
+    const int64_t b = tptr[w], e = tptr[w + 1];
+    if (lane == 0) {
+      flag[w] = 1;
+      if (e - b > MARK_LIGHT) heavy[atomicAdd(nheavy, 1)] = w;
+    }
+    if (e - b <= MARK_LIGHT)
+      for (int64_t j = b + lane; j < e; j += WAVE) flag[tcol[j]] = 1;
+  }
+}
+
+// In-rows longer than MARK_LIGHT: every workgroup takes its share of each.
+__global__ void __launch_bounds__(256) k_mark_heavy(const int *__restrict__ nheavy, const int *__restrict__ heavy,
+                                                    const int64_t *__restrict__ tptr,
+                                                    const int32_t *__restrict__ tcol, unsigned char *flag) {
+  const int total = *nheavy;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int h = 0; h < total; ++h) {
+    const int w = heavy[h];
+    for (int64_t j = tptr[w] + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < tptr[w + 1]; j += stride)
+      flag[tcol[j]] = 1;
   }
 }
 
@@ -2305,8 +2370,6 @@ __global__ void __launch_bounds__(256) k_mark_in_neighbours(const int *__restric
 // (edited row, or flagged by the previous step); skip = not refined by the
 // tier kernels (clean, or edited: edited rows are read from the edited graph
 // by the list kernels).
-constexpr int LIST_BIG = 4096;  // longer flagged rows go to the row and hub tiers
-
 // The flagged vertices whose rows were not edited are also listed, split by
 // row length (as k_split_list), so that few of them can be signed by the list
 // kernels instead of the tier kernels: counts at cnt[0] (short) and cnt[1]

@@ -28,9 +28,10 @@ def _kb():
     return kb
 
 
-def edited(g, rng, n_del, n_ins, empty_rows=(), fill_rows=()):
+def edited(g, rng, n_del, n_ins, empty_rows=(), fill_rows=(), touch_rows=()):
     """g with n_del random entries deleted, n_ins random edges inserted (labels drawn from g's),
-    every entry of empty_rows deleted and a few edges added to each of fill_rows.
+    every entry of empty_rows deleted, a few edges added to each of fill_rows and, in each of
+    touch_rows, one entry deleted and one edge added.
     Returns (edited graph, the vertices whose rows changed)."""
     src = np.repeat(np.arange(g.n, dtype=np.int64), np.diff(g.row_ptr))
     keep = np.ones(g.m, dtype=bool)
@@ -38,9 +39,12 @@ def edited(g, rng, n_del, n_ins, empty_rows=(), fill_rows=()):
         keep[rng.choice(g.m, size=n_del, replace=False)] = False
     for v in empty_rows:
         keep[g.row_ptr[v]:g.row_ptr[v + 1]] = False
+    for v in touch_rows:
+        keep[int(rng.integers(g.row_ptr[v], g.row_ptr[v + 1]))] = False
     ins_src = list(rng.integers(0, g.n, size=n_ins))
     for v in fill_rows:
         ins_src += [v] * 3
+    ins_src += list(touch_rows)
     ins_src = np.asarray(ins_src, dtype=np.int64)
     ins_dst = rng.integers(0, g.n, size=len(ins_src))
     labs = g.elabel if g.elabel is not None else None
@@ -174,6 +178,41 @@ def test_update_with_wide_labels_and_hub_tiers():
         for n_del, n_ins in [(5, 5), (3000, 3000)]:
             g2, rows = edited(g, rng, n_del, n_ins)
             check_update(c, g2, rows, f"wide-tiers -{n_del}+{n_ins}")
+    finally:
+        c.close()
+
+
+@pytest.mark.parametrize("kbits", [0, 64])
+def test_edited_long_rows(kbits):
+    """Edited rows past 4096 entries (each one a global hash set of its own, or the list kernel's
+    passes where no spare set space is left), with their twins left unedited."""
+    kb = _kb()
+    from tests.test_gpu_parity import tier_graph
+    g = tier_graph(seed=17, labels=4, shared_targets=500)
+    deg = np.diff(g.row_ptr)
+    long_rows = [int(v) for v in np.nonzero(deg > 4096)[0] if v % 2 == 0]
+    assert len(long_rows) >= 4
+    t = kb.tuning(key_bits=kbits)
+    c = Cached(g, 4, tuning=t)
+    rng = np.random.default_rng(40 + kbits)
+    try:
+        g2, rows = edited(g, rng, 3, 3, touch_rows=long_rows)
+        check_update(c, g2, rows, f"long rows keys{kbits}", tuning=t)
+        g3, rows3 = edited(g, rng, 0, 0, empty_rows=long_rows[:1], touch_rows=long_rows[1:])
+        check_update(c, g3, rows3, f"long rows emptied keys{kbits}", tuning=t)
+    finally:
+        c.close()
+
+
+def test_edited_giant_hub_rows():
+    """Edits to rows of 4.5M entries."""
+    from tests.test_gpu_parity import giant_hub_graph
+    g = giant_hub_graph()
+    c = Cached(g, 3)
+    rng = np.random.default_rng(77)
+    try:
+        g2, rows = edited(g, rng, 5, 5, touch_rows=[1, 2])
+        check_update(c, g2, rows, "giant hubs", with_ref=False)
     finally:
         c.close()
 
