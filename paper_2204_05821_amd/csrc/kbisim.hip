@@ -237,6 +237,9 @@ struct kbisim_ctx {
     int32_t *keep;    // cached names kept by blocks of changed vertices, by representative
     unsigned char *claimed;  // cached names taken by blocks with an unchanged member
     int *heavy;       // changed vertices with long in-rows
+    unsigned char *touch;  // cached blocks (by minimum vertex) that can change in this step
+    int *lk;               // the dirty vertices, then these and the clean members of touched blocks
+    u32 *filter;           // bit filter of the dirty keys
     // edited rows longer than LIST_BIG: one global set each (chunks of HUB_GCHUNK)
     int *huge;
     HubGChunk *huge_chunks;
@@ -245,6 +248,7 @@ struct kbisim_ctx {
     int nhuge = 0, nhuge_chunks = 0;
     int64_t huge_set_begin = 0, huge_set_slots = 0;
     int64_t huge_cap = 0, huge_chunk_cap = 0;
+    int64_t nrows = 0;  // edited rows listed by the caller
     u64 *zrep;        // empty-signature representatives by block name (names reach 2n)
   } is{};
 };
@@ -1261,8 +1265,8 @@ int refine_impl(kbisim_ctx *c, const int32_t *start, int k, int32_t *const *out,
 // per-update scratch.
 struct IncrPlan {
   size_t off_hc, off_dcc, off_mvc, off_tptr, off_tcol, off_names, off_edited, off_flag, off_dirty, off_skip,
-      off_small, off_large, off_psmall, off_plarge, off_changed, off_bname, off_keep, off_claimed, off_heavy, off_zrep,
-      off_huge, off_hchunks, off_hacc, off_hcnt, off_cnt, total;
+      off_small, off_large, off_psmall, off_plarge, off_changed, off_bname, off_keep, off_claimed, off_heavy, off_touch,
+      off_lk, off_filter, off_zrep, off_huge, off_hchunks, off_hacc, off_hcnt, off_cnt, total;
   int64_t huge_cap, huge_chunk_cap;
 };
 IncrPlan incr_plan(int64_t n, int64_t m, int kmax) {
@@ -1293,6 +1297,9 @@ IncrPlan incr_plan(int64_t n, int64_t m, int kmax) {
   p.off_keep = take(4 * N);
   p.off_claimed = take(N);
   p.off_heavy = take(4 * N);
+  p.off_touch = take(N);
+  p.off_lk = take(4 * N);
+  p.off_filter = take(4 * FILTER_WORDS);
   p.off_zrep = take(16 * N);
   p.huge_cap = std::max<int64_t>(m, 0) / LIST_BIG + 1;
   p.huge_chunk_cap = std::max<int64_t>(m, 0) / HUB_GCHUNK + p.huge_cap + 1;
@@ -1307,21 +1314,33 @@ IncrPlan incr_plan(int64_t n, int64_t m, int kmax) {
 
 constexpr int LIST_GRID_SMALL = 2048, LIST_GRID_LARGE = 1024, MARK_GRID = 2048;
 
+// Grouping-table mask for about `keys` keys at a load of at most 1/4 (a
+// small table stays in the caches), within the allocated table.
+u64 mask_for_keys(const kbisim_ctx *c, int64_t keys) {
+  return std::min<u64>(pow2_at_least((uint64_t)std::max<int64_t>(4 * keys, 4096)), c->plan.tslots) - 1;
+}
+
 // One update step: P'_{i+1} from names_prev (P0 for i = 0, else the block
 // names of P'_i).  Vertices flagged dirty had their key inputs changed: the
 // edited rows are read from the edited graph (list kernels); the others whose
 // targets' names changed are signed by the list kernels too when they are few
 // (prop_lists), else by the cached graph's tiers with every other vertex
-// skipped; all remaining vertices take their cached key hash.  Grouping,
-// exact checks (rows of the edited graph) and numbering then cover every
-// vertex; block names follow k_block_names_*.
+// skipped.  With few dirty vertices (prop_lists; at most ndirty of them) only
+// the touched cached blocks are regrouped (k_classify), in a
+// table sized for them, and every other vertex keeps its cached block and
+// name; otherwise all vertices take their cached key hashes and go through
+// the table.  Exact checks read the edited graph; numbering covers every
+// vertex; block names follow k_block_names_*.  Returns in *gpid_written
+// whether the names were also written in rank order for the next step.
 template <class K, class TierSrc, class ListSrc>
 int update_step(kbisim_ctx *c, const TierSrc &tsrc, const ListSrc &lsrc, int i, const int32_t *names_prev,
-                int32_t *out, int64_t *count_dev, int *cnt, bool prop_lists, int nbig) {
+                int32_t *out, int64_t *count_dev, int *cnt, bool prop_lists, int nbig, int64_t ndirty,
+                bool *gpid_written) {
   const int n = (int)c->g.n;
   const size_t at = (size_t)i * (size_t)n;
   auto &S = c->is;
-  const u64 tmask = c->tmask_steps;
+  c->tmask_steps = prop_lists ? mask_for_keys(c, ndirty) : c->plan.tslots - 1;
+  u64 tmask = c->tmask_steps;
   const Schedule &s = c->sched;
   // the hub epoch starts at 0 and must be in 1..3 before any global set is used
   int rc = advance(c, ADV_TABLE | ADV_CTABLE | ADV_ZERO | (s.ngchunks || S.nhuge ? ADV_HUB : 0u), s);
@@ -1357,26 +1376,75 @@ int update_step(kbisim_ctx *c, const TierSrc &tsrc, const ListSrc &lsrc, int i, 
                                                                           c->dep, c->hmask, c->zrep, nullptr);
     LAUNCH_CHECK();
   }
-  k_insert_cached<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, S.dirty, S.Hc + at, S.DCc + at, S.MVc + at,
-                                                              names_prev, c->H, c->DC, c->table, tmask, c->dep,
-                                                              c->zrep);
-  LAUNCH_CHECK();
-  k_lookup<ListSrc><<<blocks_for(n, 256), 256, 0, c->stream>>>(lsrc, n, nullptr, c->H, c->DC, c->table, tmask, c->dep,
-                                                               c->rep, &cnt[0], c->vlist, &cnt[1], c->clA, c->err,
-                                                               c->zrep, 1, nullptr, S.dirty, S.MVc + at);
-  LAUNCH_CHECK();
+  int nlk = 0;
+  if (prop_lists) {
+    // touched blocks: the cached blocks of dirty vertices (k_update_flags) and
+    // those whose key a dirty vertex now has (k_classify)
+    if ((rc = fill_i32(c, (int *)S.filter, FILTER_WORDS, 0))) return rc;
+    if (ndirty > 0) {
+      // the dirty vertices were listed by k_update_flags (count at cnt[12])
+      k_build_filter<<<blocks_for(ndirty, 256), 256, 0, c->stream>>>(&cnt[12], S.lk, c->H, c->DC, names_prev,
+                                                                      S.filter);
+      LAUNCH_CHECK();
+    }
+    k_classify<<<(unsigned)std::min<int64_t>(CLASSIFY_GRID, blocks_for(n, 256)), 256, 0, c->stream>>>(
+        n, S.MVc + at, S.dirty, S.touch, S.Hc + at, S.DCc + at, names_prev, S.filter, c->table, tmask, c->dep, c->zrep,
+        c->H, c->DC, c->rep, S.names[i & 1], &cnt[11], S.lk);
+    LAUNCH_CHECK();
+    HIP_TRY(hipMemcpyAsync(&nlk, &cnt[11], sizeof nlk, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (2 * (int64_t)nlk > (int64_t)tmask + 1) {
+      // more keys than the dirty-sized table holds: a larger one, all listed keys again
+      if ((rc = advance(c, ADV_TABLE, s))) return rc;
+      c->tmask_steps = tmask = mask_for_keys(c, nlk);
+    }
+    if (nlk) {
+      k_insert_list<<<blocks_for(nlk, 256), 256, 0, c->stream>>>(nlk, S.lk, c->H, c->DC, names_prev, c->table, tmask,
+                                                                  c->dep, c->zrep);
+      k_lookup<ListSrc><<<blocks_for(nlk, 256), 256, 0, c->stream>>>(
+          lsrc, nlk, S.lk, c->H, c->DC, c->table, tmask, c->dep, c->rep, &cnt[0], c->vlist, &cnt[1], c->clA, c->err,
+          c->zrep, 1, nullptr, S.dirty, S.MVc + at);
+      LAUNCH_CHECK();
+    }
+  } else {
+    k_insert_cached<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, S.dirty, S.Hc + at, S.DCc + at, S.MVc + at,
+                                                                names_prev, c->H, c->DC, c->table, tmask, c->dep,
+                                                                c->zrep);
+    LAUNCH_CHECK();
+    k_lookup<ListSrc><<<blocks_for(n, 256), 256, 0, c->stream>>>(lsrc, n, nullptr, c->H, c->DC, c->table, tmask,
+                                                                 c->dep, c->rep, &cnt[0], c->vlist, &cnt[1], c->clA,
+                                                                 c->err, c->zrep, 1, nullptr, S.dirty, S.MVc + at);
+    LAUNCH_CHECK();
+  }
   if ((rc = settle_collisions(c, lsrc, s, cnt, true))) return rc;
   if ((rc = numbering_scan(c, n, out, count_dev))) return rc;
   if ((rc = fill_i32(c, reinterpret_cast<int *>(S.claimed), (n + 3) / 4, 0))) return rc;
-  k_block_names_fresh<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, c->rep, S.bname, S.keep);
-  k_block_names_clean<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, c->rep, S.dirty, S.MVc + at, S.bname,
-                                                                  S.claimed);
-  k_block_names_keep<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, c->rep, S.dirty, S.MVc + at, S.bname, S.claimed,
-                                                                 S.keep);
-  k_assign_names<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, c->rep, out, S.names[i & 1], c->rank,
-                                                            c->gpid[(i + 1) & 1], S.bname, S.keep, S.MVc + at,
-                                                            &cnt[6], S.changed);
-  LAUNCH_CHECK();
+  if (prop_lists) {
+    k_assign_out<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, c->rep, out);
+    LAUNCH_CHECK();
+    if (nlk) {
+      const unsigned g = blocks_for(nlk, 256);
+      k_block_names_fresh<<<g, 256, 0, c->stream>>>(n, c->rep, S.bname, S.keep, nlk, S.lk);
+      k_block_names_clean<<<g, 256, 0, c->stream>>>(n, c->rep, S.dirty, S.MVc + at, S.bname, S.claimed, nlk, S.lk);
+      k_block_names_keep<<<g, 256, 0, c->stream>>>(n, c->rep, S.dirty, S.MVc + at, S.bname, S.claimed, S.keep, nlk,
+                                                   S.lk);
+      k_assign_names<<<g, 256, 0, c->stream>>>(n, c->rep, nullptr, S.names[i & 1], nullptr, nullptr, S.bname, S.keep,
+                                               S.MVc + at, &cnt[6], S.changed, nlk, S.lk);
+      LAUNCH_CHECK();
+    }
+    *gpid_written = false;
+  } else {
+    k_block_names_fresh<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, c->rep, S.bname, S.keep);
+    k_block_names_clean<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, c->rep, S.dirty, S.MVc + at, S.bname,
+                                                                    S.claimed);
+    k_block_names_keep<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, c->rep, S.dirty, S.MVc + at, S.bname,
+                                                                   S.claimed, S.keep);
+    k_assign_names<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, c->rep, out, S.names[i & 1], c->rank,
+                                                              c->gpid[(i + 1) & 1], S.bname, S.keep, S.MVc + at,
+                                                              &cnt[6], S.changed);
+    LAUNCH_CHECK();
+    *gpid_written = true;
+  }
   k_mark_in_neighbours<<<MARK_GRID, 256, 0, c->stream>>>(&cnt[6], S.changed, S.tptr, S.tcol, S.flag, &cnt[7],
                                                          S.heavy);
   k_mark_heavy<<<MARK_GRID, 256, 0, c->stream>>>(&cnt[7], S.heavy, S.tptr, S.tcol, S.flag);
@@ -1390,28 +1458,38 @@ int update_steps_t(kbisim_ctx *c, const kbisim_graph *gn, int k, int32_t *const 
   auto &S = c->is;
   const int32_t *lab = separate_labels(c) ? sep_labels(c) : nullptr;
   int rc = 0;
+  bool gpid_ok = true;  // gpid[i & 1] holds names_prev in rank order (P0 for the first step)
   for (int i = 0; i < k; ++i) {
     const int32_t *names_prev = i == 0 ? c->p0 : S.names[(i - 1) & 1];
     int *cnt = c->counters + CNT_STRIDE * i;
     if ((rc = fill_i32(c, cnt, CNT_STRIDE, 0))) return rc;
+    if ((rc = fill_i32(c, reinterpret_cast<int *>(S.touch), (n + 3) / 4, 0))) return rc;
     k_update_flags<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, S.edited, S.flag, S.dirty, S.skip, gn->row_ptr,
-                                                              cnt + 8, S.psmall, S.plarge);
+                                                              cnt + 8, S.psmall, S.plarge, S.MVc + (size_t)i * n,
+                                                              S.touch, S.lk);
     LAUNCH_CHECK();
     if ((rc = fill_i32(c, reinterpret_cast<int *>(S.flag), (n + 3) / 4, 0))) return rc;
     // few vertices flagged by the previous step: sign them from lists
     int np[3] = {0, 0, 0};
     HIP_TRY(hipMemcpyAsync(np, cnt + 8, sizeof np, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
-    const bool prop_lists = (int64_t)np[0] + np[1] + np[2] <= std::max<int64_t>(n / 8, 1);
+    const int64_t nprop = (int64_t)np[0] + np[1] + np[2];
+    const bool prop_lists = nprop <= std::max<int64_t>(n / 8, 1);
+    if ((!prop_lists || np[2] > 0) && !gpid_ok) {
+      // the tier kernels read the previous names in rank order
+      k_scatter_rank<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, names_prev, c->rank, c->gpid[i & 1]);
+      LAUNCH_CHECK();
+    }
     const PlainSrcT<HK> lsrc{gn->row_ptr, gn->col, gn->elabel, names_prev, c->pb, c->kmask};
+    const int64_t ndirty = nprop + S.nrows;
     if (lab)
       rc = update_step<K>(c, GraphSrcT<true, HK>{c->g.row_ptr, c->gcol, lab, c->gpid[i & 1], names_prev, c->pb,
                                                  c->rbits, c->kmask},
-                          lsrc, i, names_prev, out[i], &c->dcounts[i], cnt, prop_lists, np[2]);
+                          lsrc, i, names_prev, out[i], &c->dcounts[i], cnt, prop_lists, np[2], ndirty, &gpid_ok);
     else
       rc = update_step<K>(c, GraphSrcT<false, HK>{c->g.row_ptr, c->gcol, nullptr, c->gpid[i & 1], names_prev, c->pb,
                                                   c->rbits, c->kmask},
-                          lsrc, i, names_prev, out[i], &c->dcounts[i], cnt, prop_lists, np[2]);
+                          lsrc, i, names_prev, out[i], &c->dcounts[i], cnt, prop_lists, np[2], ndirty, &gpid_ok);
     if (rc) return rc;
   }
   return 0;
@@ -1459,6 +1537,7 @@ int update_impl(kbisim_ctx *c, const kbisim_graph *gn, const int32_t *rows, int6
   if ((rc = fill_i32(c, S.cnt + 2, 1, (int)nrows))) return rc;
   S.nhuge = 0;
   S.nhuge_chunks = 0;
+  S.nrows = nrows;
   if (nrows) {
     k_set_flags<<<std::min<unsigned>(blocks_for(nrows, 256), 65536), 256, 0, c->stream>>>(S.cnt + 2, rows, S.edited);
     // edited rows longer than LIST_BIG take global sets when the spare hub-set
@@ -1478,19 +1557,19 @@ int update_impl(kbisim_ctx *c, const kbisim_graph *gn, const int32_t *rows, int6
       HIP_TRY(hipStreamSynchronize(c->stream));
       if (nh > 0) {
         std::vector<int> hv((size_t)nh);
-        std::vector<int64_t> b((size_t)nh), e((size_t)nh);
+        std::vector<int64_t> be(2 * (size_t)nh);
+        // extents staged in the chunk buffer (rewritten below)
+        int64_t *be_dev = reinterpret_cast<int64_t *>(S.huge_chunks);
+        k_row_extents<<<blocks_for(nh, 256), 256, 0, c->stream>>>(nh, S.huge, gn->row_ptr, be_dev);
+        LAUNCH_CHECK();
         HIP_TRY(hipMemcpyAsync(hv.data(), S.huge, 4 * (size_t)nh, hipMemcpyDeviceToHost, c->stream));
-        HIP_TRY(hipStreamSynchronize(c->stream));
-        for (int i = 0; i < nh; ++i) {
-          HIP_TRY(hipMemcpyAsync(&b[(size_t)i], gn->row_ptr + hv[(size_t)i], 8, hipMemcpyDeviceToHost, c->stream));
-          HIP_TRY(hipMemcpyAsync(&e[(size_t)i], gn->row_ptr + hv[(size_t)i] + 1, 8, hipMemcpyDeviceToHost, c->stream));
-        }
+        HIP_TRY(hipMemcpyAsync(be.data(), be_dev, 16 * (size_t)nh, hipMemcpyDeviceToHost, c->stream));
         HIP_TRY(hipStreamSynchronize(c->stream));
         std::vector<HubGChunk> ch;
         std::vector<int> keep_list;
         int64_t at = free_begin;
         for (int i = 0; i < nh; ++i) {
-          const int64_t d = e[(size_t)i] - b[(size_t)i];
+          const int64_t d = be[2 * (size_t)i + 1] - be[2 * (size_t)i];
           if (at + 2 * d > free_end || (int64_t)ch.size() + d / HUB_GCHUNK + 1 > S.huge_chunk_cap) {
             keep_list.push_back(hv[(size_t)i]);  // no room: back to the list kernel
             continue;
@@ -1572,6 +1651,9 @@ int incr_enable_impl(kbisim_ctx *c, void *state, size_t bytes) {
   S.keep = (int32_t *)(w + p.off_keep);
   S.claimed = (unsigned char *)(w + p.off_claimed);
   S.heavy = (int *)(w + p.off_heavy);
+  S.touch = (unsigned char *)(w + p.off_touch);
+  S.lk = (int *)(w + p.off_lk);
+  S.filter = (u32 *)(w + p.off_filter);
   S.huge = (int *)(w + p.off_huge);
   S.huge_chunks = (HubGChunk *)(w + p.off_hchunks);
   S.huge_acc = (u64 *)(w + p.off_hacc);

@@ -2262,16 +2262,19 @@ __global__ void __launch_bounds__(256) k_insert_cached(int n, const unsigned cha
 // vertex), or with bname (an update) the name bname[] gives the
 // representative's block; vertices whose name differs from the cached
 // chain's (old_names) are then listed in changed[].
+// list != NULL: only the `count` listed vertices (out may then be NULL).
 __global__ void k_assign_names(int n, const int *__restrict__ rep, int *out, int32_t *__restrict__ names_out,
                                const int *__restrict__ rank, int *__restrict__ gpid_next,
                                const int32_t *__restrict__ bname, const int32_t *__restrict__ keep,
-                               const int32_t *__restrict__ old_names, int *nchanged, int *changed) {
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool act = v < n;
+                               const int32_t *__restrict__ old_names, int *nchanged, int *changed,
+                               int count = 0, const int *__restrict__ list = nullptr) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool act = t < (list ? count : n);
+  const int v = act ? (list ? list[t] : t) : 0;
   bool moved = false;
   if (act) {
     const int r = rep[v];
-    if (r != v) out[v] = r >= 0 ? out[r] : -1;
+    if (out && r != v) out[v] = r >= 0 ? out[r] : -1;
     int nm = r;
     if (bname) {
       nm = r >= 0 ? bname[r] : -1;
@@ -2287,6 +2290,122 @@ __global__ void k_assign_names(int n, const int *__restrict__ rep, int *out, int
   if (old_names) wave_append(nchanged, changed, moved, v);
 }
 
+// Update steps with few dirty vertices group only the blocks that can have
+// changed.  Clean members of a cached block keep equal keys, so a cached
+// block B keeps exactly its members (and its minimum vertex and name) unless
+// it holds a dirty vertex (touch[minimum vertex], set by k_update_flags) or a
+// dirty vertex now has B's key.  The second is found by each clean vertex
+// looking its own cached key up among the dirty keys already inserted (the
+// table, or zrep for an empty signature, whose key is the own name alone):
+// every member of B asks with the same key and gets the same answer; a hash
+// match whose keys differ only costs work, the exact check sorts it out.
+// Dirty vertices and the clean members of such "touched" blocks are listed
+// (the clean ones take their cached key hash and distinct count); every other
+// vertex keeps its cached block: representative and name = the cached
+// minimum vertex.
+// A bit filter of the dirty keys lets most clean vertices skip the table
+// probe: FILTER_BITS bits for key hashes (bits 36.. of the hash, as the
+// table's slot tags), as many for the names of empty signatures.  Copied to
+// LDS by every workgroup of k_classify, so the grid strides over vertices.
+constexpr int FILTER_BITS = 1 << 16;
+constexpr int FILTER_WORDS = 2 * FILTER_BITS / 32;
+constexpr int CLASSIFY_GRID = 2048;
+__device__ inline u32 filter_key_bit(u64 h) { return (u32)(h >> 36) & (FILTER_BITS - 1); }
+__device__ inline u32 filter_name_bit(u32 name) { return FILTER_BITS + ((name * 0x9E3779B1u) >> 16); }
+
+__global__ void k_build_filter(const int *__restrict__ count, const int *__restrict__ dlist,
+                               const u64 *__restrict__ H, const u32 *__restrict__ DC,
+                               const int32_t *__restrict__ names, u32 *filter) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= *count) return;
+  const int d = dlist[i];
+  const u32 b = DC[d] ? filter_key_bit(H[d]) : filter_name_bit((u32)names[d]);
+  atomicOr(&filter[b >> 5], 1u << (b & 31));
+}
+
+__global__ void __launch_bounds__(256) k_classify(int n, const int32_t *__restrict__ mvc,
+                                                  const unsigned char *__restrict__ dirty,
+                                                  const unsigned char *__restrict__ touch, const u64 *__restrict__ Hc,
+                                                  const u32 *__restrict__ DCc, const int32_t *__restrict__ names,
+                                                  const u32 *__restrict__ filter, const u64 *table, u64 tmask,
+                                                  const u32 *__restrict__ dep, const u64 *__restrict__ zrep,
+                                                  u64 *__restrict__ H, u32 *__restrict__ DC, int *__restrict__ rep,
+                                                  int32_t *__restrict__ names_out, int *count, int *list) {
+  __shared__ u32 fl[FILTER_WORDS];
+  for (int i = threadIdx.x; i < FILTER_WORDS; i += 256) fl[i] = filter[i];
+  __syncthreads();
+  const u32 epoch = dep[EP_TABLE], zep = dep[EP_ZERO];
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t base = (int64_t)blockIdx.x * 256; base < n; base += stride) {
+    const int v = (int)(base + threadIdx.x);
+    const bool act = v < n;
+    bool listed = false;
+    if (act) {
+      if (dirty[v]) {
+        listed = true;
+      } else {
+        const int h = mvc[v];
+        const u32 dc = DCc[v];
+        const u64 hv = Hc[v];
+        bool hit = touch[h] != 0;
+        if (!hit) {
+          if (dc == 0) {
+            const u32 nm = (u32)names[v];
+            const u32 b = filter_name_bit(nm);
+            hit = (fl[b >> 5] >> (b & 31)) & 1u;
+            if (hit) hit = (u32)(zrep[nm] >> 32) == ~zep;
+          } else {
+            const u32 b = filter_key_bit(hv);
+            hit = (fl[b >> 5] >> (b & 31)) & 1u;
+            if (hit) hit = table_lookup(table, tmask, hv, epoch) >= 0;
+          }
+        }
+        if (hit) {
+          H[v] = hv;
+          DC[v] = dc;
+          listed = true;
+        } else {
+          rep[v] = h;
+          names_out[v] = h;
+        }
+      }
+    }
+    wave_append(count, list, listed, v);
+  }
+}
+
+// Inserts the listed vertices' keys (table, or zrep for empty signatures).
+__global__ void __launch_bounds__(256) k_insert_list(int count, const int *__restrict__ list,
+                                                     const u64 *__restrict__ H, const u32 *__restrict__ DC,
+                                                     const int32_t *__restrict__ names, u64 *table, u64 tmask,
+                                                     const u32 *__restrict__ dep, u64 *zrep) {
+  const u32 epoch = dep[EP_TABLE], zep = dep[EP_ZERO];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const bool act = i < count;
+  const int v = act ? list[i] : 0;
+  const u32 dc = act ? DC[v] : 0;
+  if (act && dc) table_insert(table, tmask, H[v], (u32)v, epoch);
+  zero_insert_wave(zrep, act && dc == 0, act ? (u32)names[v] : 0u, (u32)v, zep);
+}
+
+// Row extents (begin, end) of listed vertices.
+__global__ void k_row_extents(int count, const int *__restrict__ list, const int64_t *__restrict__ row_ptr,
+                              int64_t *__restrict__ be) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const int v = list[i];
+  be[2 * i] = row_ptr[v];
+  be[2 * i + 1] = row_ptr[v + 1];
+}
+
+// Dense ids of the vertices that are not heads: the id of their representative.
+__global__ void k_assign_out(int n, const int *__restrict__ rep, int *out) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const int r = rep[v];
+  if (r != v) out[v] = r >= 0 ? out[r] : -1;
+}
+
 // Block names of an update step.  A new block that keeps an unchanged
 // (clean) member takes that member's cached name: clean members of one new
 // block shared their cached block (their keys did not change), and no other
@@ -2300,19 +2419,30 @@ __global__ void k_assign_names(int n, const int *__restrict__ rep, int *out, int
 // deterministic): a block whose members all changed keys but stayed
 // together, e.g. a singleton, is not renamed.  No other new block can hold
 // that vertex, so the name stays distinct.
+// Each runs over every vertex, or over the `count` listed ones (list != NULL:
+// the vertices of the blocks that can have changed; every other block keeps
+// its members and its cached name).
+__device__ inline int name_item(int n, int count, const int *list, bool &act) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  act = t < (list ? count : n);
+  return act ? (list ? list[t] : t) : 0;
+}
 __global__ void k_block_names_fresh(int n, const int *__restrict__ rep, int32_t *__restrict__ bname,
-                                    int32_t *__restrict__ keep) {
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v < n && rep[v] == v) {
+                                    int32_t *__restrict__ keep, int count = 0, const int *__restrict__ list = nullptr) {
+  bool act;
+  const int v = name_item(n, count, list, act);
+  if (act && rep[v] == v) {
     bname[v] = n + v;
     keep[v] = 0x7FFFFFFF;
   }
 }
 __global__ void k_block_names_clean(int n, const int *__restrict__ rep, const unsigned char *__restrict__ dirty,
                                     const int32_t *__restrict__ old_names, int32_t *__restrict__ bname,
-                                    unsigned char *__restrict__ claimed) {
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v < n && !dirty[v]) {
+                                    unsigned char *__restrict__ claimed, int count = 0,
+                                    const int *__restrict__ list = nullptr) {
+  bool act;
+  const int v = name_item(n, count, list, act);
+  if (act && !dirty[v]) {
     const int32_t nm = old_names[v];
     bname[rep[v]] = nm;
     claimed[nm] = 1;
@@ -2320,9 +2450,11 @@ __global__ void k_block_names_clean(int n, const int *__restrict__ rep, const un
 }
 __global__ void k_block_names_keep(int n, const int *__restrict__ rep, const unsigned char *__restrict__ dirty,
                                    const int32_t *__restrict__ old_names, const int32_t *__restrict__ bname,
-                                   const unsigned char *__restrict__ claimed, int32_t *keep) {
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v < n && dirty[v] && old_names[v] == v && !claimed[v]) {
+                                   const unsigned char *__restrict__ claimed, int32_t *keep, int count = 0,
+                                   const int *__restrict__ list = nullptr) {
+  bool act;
+  const int v = name_item(n, count, list, act);
+  if (act && dirty[v] && old_names[v] == v && !claimed[v]) {
     const int r = rep[v];
     if (bname[r] >= n) atomicMin(&keep[r], v);
   }
@@ -2375,9 +2507,12 @@ __global__ void __launch_bounds__(256) k_mark_heavy(const int *__restrict__ nhea
 // kernels instead of the tier kernels: counts at cnt[0] (short) and cnt[1]
 // (up to LIST_BIG entries); longer rows are counted at cnt[2] and left to
 // the row and hub tiers (skip[v] = 0 for exactly them).
+// touch[mvc[v]] is set for every dirty v: its cached block may lose members;
+// the dirty vertices are listed in dlist (count at cnt[4]).
 __global__ void k_update_flags(int n, const unsigned char *__restrict__ edited, const unsigned char *__restrict__ flag,
                                unsigned char *__restrict__ dirty, unsigned char *__restrict__ skip,
-                               const int64_t *__restrict__ row_ptr, int *cnt, int *small, int *large) {
+                               const int64_t *__restrict__ row_ptr, int *cnt, int *small, int *large,
+                               const int32_t *__restrict__ mvc, unsigned char *__restrict__ touch, int *dlist) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   const bool act = v < n;
   bool prop = false;
@@ -2385,12 +2520,14 @@ __global__ void k_update_flags(int n, const unsigned char *__restrict__ edited, 
   if (act) {
     const bool ed = edited[v] != 0, fl = flag[v] != 0;
     dirty[v] = (ed || fl) ? 1 : 0;
+    if (ed || fl) touch[mvc[v]] = 1;
     prop = fl && !ed;
     if (prop) d = row_ptr[v + 1] - row_ptr[v];
     skip[v] = (prop && d > LIST_BIG) ? 0 : 1;
   }
   wave_append(&cnt[0], small, prop && d <= LIST_SMALL, v);
   wave_append(&cnt[1], large, prop && d > LIST_SMALL && d <= LIST_BIG, v);
+  wave_append(&cnt[4], dlist, act && dirty[v], v);
   const u64 big = __ballot(prop && d > LIST_BIG);
   if ((threadIdx.x & (WAVE - 1)) == 0 && big) atomicAdd(&cnt[2], (int)__popcll(big));
 }
