@@ -286,8 +286,9 @@ int kbisim_profile_read(kbisim_ctx *c, double *ms, int64_t *launches);
 const char *kbisim_kernel_name(int kind);
 
 /* Static degree schedule of the graph rows (host int64 [8]): vertices and
- * CSR entries in the range tier (degree <= 512), the workgroup tier (<= 4096),
- * the staged hub tier and the global-set hub tier, in that order.          */
+ * CSR entries in the range tier (rows up to the range capacity, 1024 or 2048
+ * entries), the workgroup tiers (up to 8192 entries, or 19456 with 32-bit
+ * set keys), the staged hub tier and the global-set hub tier, in that order. */
 int kbisim_schedule_info(kbisim_ctx *c, int64_t *info);
 
 /* Plain device-to-device copy of `bytes` bytes (a multiple of 16) with the
