@@ -10,7 +10,11 @@ The search is coordinate-wise: starting from the defaults, one knob at a
 time takes each of its values, keeping the others at the best found so far.
 For one knob every value is timed in ``rounds`` interleaved rounds, the order
 of the values rotating from round to round, and the median decides, so a
-value is not favoured by where it falls in the sequence.  Every runner is
+value is not favoured by where it falls in the sequence.  The value in place
+(the default, or the start) is kept unless another one's median is lower by
+more than ``margin`` (a fraction of the kept value's median): differences
+within timing noise do not move the choice, so it does not depend on the
+order in which knobs or values are tried.  Every runner is
 built on the same workspace (the caller's ``make`` passes one buffer, sized
 for the input, to every candidate), so no candidate pays for allocator churn
 left by another.  Every candidate's partitions and counts must be
@@ -29,7 +33,8 @@ from typing import Callable, Dict, List, Optional, Sequence, Tuple
 import numpy as np
 
 DEFAULTS = dict(key_bits=0, range_edges=0, hub_chunk=2048, hub_part_target=2048, scan_items=16)
-KNOBS = [("key_bits", [0, 32, 64]), ("range_edges", [1024, 2048]), ("hub_chunk", [2048, 4096]),
+# range_edges 0 = by key width (2048 entries with 32-bit keys, 1024 with 64-bit keys)
+KNOBS = [("key_bits", [0, 32, 64]), ("range_edges", [0, 1024, 2048]), ("hub_chunk", [2048, 4096]),
          ("hub_part_target", [1024, 2048]), ("scan_items", [8, 16])]
 HUB_KNOBS = ("hub_chunk", "hub_part_target")
 
@@ -96,7 +101,7 @@ def autotune(make: Callable[[Dict], object], run: Callable[[object], Tuple[list,
              rounds: int = 3, reps: int = 1, knobs: Optional[Sequence[Tuple[str, List[int]]]] = None,
              start: Optional[Dict] = None, cache_path: Optional[str] = DEFAULT_CACHE,
              close: Callable[[object], None] = lambda r: r.close(), sync: Optional[Callable[[], None]] = None,
-             ) -> Tuple[Dict, Dict]:
+             margin: float = 0.01) -> Tuple[Dict, Dict]:
     """Pick the fastest tuning for `key`.
 
     make(tuning_dict) builds a runner (on the caller's shared workspace),
@@ -151,10 +156,15 @@ def autotune(make: Callable[[Dict], object], run: Callable[[object], Tuple[list,
                 times[v].append(ms)
                 samples.setdefault(json.dumps(cand, sort_keys=True), []).append(round(ms, 3))
         med = {v: statistics.median(t) for v, t in times.items()}
-        best[name] = min(values, key=lambda v: (med[v], values.index(v)))
+        cur = best[name] if best[name] in med else min(values, key=lambda v: (med[v], values.index(v)))
+        fastest = min(values, key=lambda v: (med[v], v))
+        if med[fastest] < med[cur] * (1.0 - margin):
+            cur = fastest
+        best[name] = cur
     ranked = sorted(((statistics.median(t), json.loads(c)) for c, t in samples.items()), key=lambda x: x[0])
     report = {"best": best, "ms": [[round(ms, 3), c] for ms, c in ranked], "samples": samples,
-              "rounds": rounds, "reps": reps, "search": "coordinate, interleaved rounds, median"}
+              "rounds": rounds, "reps": reps, "margin": margin,
+              "search": "coordinate, interleaved rounds, median; the value in place kept within the margin"}
     if cache_path:
         cache[full_key] = report
         save_cache(cache, cache_path)
