@@ -1460,6 +1460,23 @@ int update_steps_t(kbisim_ctx *c, const kbisim_graph *gn, int k, int32_t *const 
   int rc = 0;
   bool gpid_ok = true;  // gpid[i & 1] holds names_prev in rank order (P0 for the first step)
   for (int i = 0; i < k; ++i) {
+    if (i >= 2) {
+      // P'_{i-1} refines P'_{i-2}: with as many blocks it is the same
+      // partition, and so is every later one (a step depends on the previous
+      // partition alone): copies, no more steps
+      int64_t pc[2] = {0, 0};
+      HIP_TRY(hipMemcpyAsync(pc, &c->dcounts[i - 2], sizeof pc, hipMemcpyDeviceToHost, c->stream));
+      HIP_TRY(hipStreamSynchronize(c->stream));
+      if (pc[0] == pc[1]) {
+        for (int j = i; j < k; ++j) {
+          k_copy_i32<<<std::min<unsigned>(blocks_for(n, 256), 65536), 256, 0, c->stream>>>(out[j], out[i - 1], n);
+          LAUNCH_CHECK();
+          HIP_TRY(hipMemcpyAsync(&c->dcounts[j], &c->dcounts[i - 1], sizeof(int64_t), hipMemcpyDeviceToDevice,
+                                 c->stream));
+        }
+        return 0;
+      }
+    }
     const int32_t *names_prev = i == 0 ? c->p0 : S.names[(i - 1) & 1];
     int *cnt = c->counters + CNT_STRIDE * i;
     if ((rc = fill_i32(c, cnt, CNT_STRIDE, 0))) return rc;
