@@ -343,8 +343,6 @@ def run_plain(args, kb, torch, workload, g, cpu_job=None, extras=True):
     we_steps = r.work_efficient(None)
     we_same = we_counts == counts and all(torch.equal(a, b) for a, b in zip(outs, full))
     r.work_efficient(False)
-    incremental = None if args.no_incremental else incremental_leg(kb, torch, g, (rp, col, el, vl, vp), k,
-                                                                   ms_per_step, we_ms)
     # Summary graph of the chain's last step: source blocks P_k, target blocks P_{k-1}.
     r.quotient(full[k - 1], full[k - 2])
     torch.cuda.synchronize()
@@ -361,7 +359,13 @@ def run_plain(args, kb, torch, workload, g, cpu_job=None, extras=True):
                       "speedup_vs_full_work": ms_per_step / we_ms, "identical_outputs": bool(we_same),
                       "note": "singleton blocks skipped and the loop stopped at the fixpoint; not the headline value"}
     r.close()
-    del rp, col, el, vl, vp, outs, r
+    del outs, r
+    torch.cuda.empty_cache()
+    # after the main context is released: the leg holds a cached context, an edited copy of the
+    # targets and a fresh context for the check (about 3.5 workspaces on the 2B-edge graph)
+    incremental = None if args.no_incremental else incremental_leg(kb, torch, g, (rp, col, el, vl, vp), k,
+                                                                   ms_per_step, we_ms)
+    del rp, col, el, vl, vp
     torch.cuda.empty_cache()
 
     cpu = None
