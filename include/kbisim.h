@@ -333,15 +333,18 @@ int kbisim_destroy(kbisim_ctx *c);
  * block names did not change keeps its cached key hash; only the others are
  * re-signed: the edited rows at every step, and from step 2 on the vertices
  * whose name changed in the previous step and every vertex with an edge into
- * one (that set grows along in-edges from step to step).  Grouping, exact
- * checks and numbering cover every vertex, so the result is exactly the
- * refinement of the edited graph from scratch (ids numbered by first
- * vertex).
+ * one (that set grows along in-edges from step to step).  A cached block
+ * that holds none of them and whose key none of them takes keeps its
+ * members and name; only the others are regrouped, with exact checks on
+ * the edited rows, and dense ids cover every vertex, so the result is
+ * exactly the refinement of the edited graph from scratch (ids numbered by
+ * first vertex).  Once two consecutive partitions have equal block counts
+ * the later ones are copies (a fixpoint).
  *
  * Bytes of the caller buffer that holds the cached chain of a graph of
  * g->n vertices and g->m edges for up to kmax steps: per step a key hash, a
  * distinct count and a block name per vertex (16 bytes), the graph's in-rows
- * (8 (n+1) + 4 m) and scratch; about 16 kmax n + 4 m + 40 n bytes.  Host
+ * (8 (n+1) + 4 m) and scratch; about 16 kmax n + 4 m + 75 n bytes.  Host
  * only.  Errors: EINVAL (null, kmax < 1), ERANGE.                           */
 int kbisim_incr_state_bytes(const kbisim_graph *g, int kmax, size_t *bytes);
 
