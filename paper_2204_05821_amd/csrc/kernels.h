@@ -1910,11 +1910,16 @@ __global__ void __launch_bounds__(256) k_radix_hist(int64_t m, const u64 *__rest
   h[threadIdx.x] = 0;
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * RADIX_TILE;
+  // every key of the thread is requested before the first count
+  u64 kk[RADIX_ITEMS];
 #pragma unroll
   for (int j = 0; j < RADIX_ITEMS; ++j) {
     const int64_t i = base + j * 256 + threadIdx.x;
-    if (i < m) atomicAdd(&h[(keys[i] >> shift) & 255], 1);
+    kk[j] = i < m ? __builtin_nontemporal_load(&keys[i]) : 0ULL;
   }
+#pragma unroll
+  for (int j = 0; j < RADIX_ITEMS; ++j)
+    if (base + j * 256 + threadIdx.x < m) atomicAdd(&h[(kk[j] >> shift) & 255], 1);
   __syncthreads();
   hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
 }
@@ -1945,12 +1950,21 @@ __global__ void __launch_bounds__(256) k_radix_scatter(int64_t m, const u64 *__r
   const int64_t tile0 = (int64_t)blockIdx.x * RADIX_TILE;
   const int cnt = (int)min<int64_t>(m - tile0, RADIX_TILE);
   const u64 lt = (1ULL << lane) - 1ULL;
+  // the whole tile is requested at once, so its load latency is paid once
+  // instead of once per chunk
+  u64 kk[RADIX_ITEMS];
+#pragma unroll
+  for (int j = 0; j < RADIX_ITEMS; ++j) {
+    const int i = j * 256 + t;
+    kk[j] = i < cnt ? __builtin_nontemporal_load(&keys[tile0 + i]) : 0ULL;
+  }
+#pragma unroll
   for (int j = 0; j < RADIX_ITEMS; ++j) {
     for (int q = 0; q < 4; ++q) wcnt[q][t] = 0;
     __syncthreads();
     const int i = j * 256 + t;
     const bool valid = i < cnt;
-    const u64 key = valid ? keys[tile0 + i] : 0ULL;
+    const u64 key = kk[j];
     const u32 d = (u32)(key >> shift) & 255u;
     u64 peers = __ballot(valid);
 #pragma unroll
