@@ -572,6 +572,8 @@ def run_serve(args, kb, torch):
     def draw_jobs(count):
         return [(rnd.randrange(len(pool)), rnd.randint(1, 10)) for _ in range(count)]
 
+    whole = {"whole_edges": args.serve_whole_edges} if args.serve_whole_edges > 0 else {}
+
     def closed_loop(server_cls, jobs, **kw):
         be = serve.DeviceBackend(streams=4, keep_outputs=False)
         srv = server_cls(be, budget, **kw).start()
@@ -586,18 +588,18 @@ def run_serve(args, kb, torch):
         return wall, [j.counts for j in js], srv.stats()
 
     # warm-up (library load, allocator, first contexts)
-    closed_loop(serve.Server, draw_jobs(16))
+    closed_loop(serve.Server, draw_jobs(16), **whole)
     # capacity: the same job list through both servers
     jobs = draw_jobs(args.serve_capacity_jobs)
     ek = sum(pool_m[gi] * k for gi, k in jobs)
-    cont_s, cont_counts, cont_st = closed_loop(serve.Server, jobs)
+    cont_s, cont_counts, cont_st = closed_loop(serve.Server, jobs, **whole)
     fifo_s, fifo_counts, _ = closed_loop(serve.FifoServer, jobs)
     log(f"[serve] capacity on {len(jobs)} jobs: continuous {cont_s:.2f}s, one-at-a-time {fifo_s:.2f}s, "
         f"identical counts {cont_counts == fifo_counts}")
 
     # open loop: Poisson arrivals at the offered rate
     be = serve.DeviceBackend(streams=4, keep_outputs=False)
-    srv = serve.Server(be, budget).start()
+    srv = serve.Server(be, budget, **whole).start()
     t_end = time.perf_counter() + args.serve_seconds
     submitted = []
     nxt = time.perf_counter()
@@ -640,6 +642,7 @@ def run_serve(args, kb, torch):
                          "speedup": fifo_s / cont_s, "identical_counts": cont_counts == fifo_counts,
                          "mean_jobs_per_tick": cont_st["mean_jobs_per_tick"]},
             "pool": {"graphs": len(pool), "edges": sum(pool_m)},
+            "whole_edges": args.serve_whole_edges or None,
             "shape": ("as configured: 256 pool graphs, 60 s of arrivals" if len(pool) == 256 and
                       args.serve_seconds == 60 else f"reduced: {len(pool)} pool graphs, {args.serve_seconds:g} s "
                                                      "of arrivals (configured: 256 graphs, 60 s)"),
@@ -670,6 +673,9 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--serve-capacity-jobs", type=int, default=200)
+    ap.add_argument("--serve-whole-edges", type=int, default=2_000_001,
+                    help="jobs of at least this many edges (solo units) are refined in one call on a worker "
+                         "instead of one step per tick (0 = every unit steps per tick)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run the library's streaming copy kernel on this many MiB (bandwidth and counter "
                          "calibration) and print its rate")

@@ -286,12 +286,17 @@ class Server:
     budget_bytes bounds the summed footprint of admitted units; max_units
     bounds the number of units admitted at once (slots).  Jobs with at most
     cohort_edges edges that are admitted in the same tick share a cohort of
-    up to max_cohort jobs.  ``clock`` returns seconds.
+    up to max_cohort jobs.  With whole_edges set (and workers > 0), a job of
+    at least that many edges, which runs alone anyway, is refined in one call
+    on one of whole_workers threads as soon as it is prepared, overlapping the
+    ticks on the device, instead of one step per tick; it still holds its
+    slot and its memory until done.  ``clock`` returns seconds.
     """
 
     def __init__(self, backend, budget_bytes: int, max_units: int = 32, workers: int = 8,
                  cohort_edges: int = 2_000_000, max_cohort: int = 64,
-                 clock: Callable[[], float] = time.perf_counter):
+                 clock: Callable[[], float] = time.perf_counter, whole_edges: Optional[int] = None,
+                 whole_workers: int = 4):
         self.backend = backend
         self.budget = int(budget_bytes)
         self.max_units = max_units
@@ -311,6 +316,10 @@ class Server:
         self._jid = 0
         self._cv = threading.Condition()
         self._pool = cf.ThreadPoolExecutor(max_workers=workers) if workers > 0 else None
+        self.whole_edges = whole_edges
+        self._whole: Dict[int, Unit] = {}      # units refined in one call on a worker
+        self._whole_pool = (cf.ThreadPoolExecutor(max_workers=whole_workers)
+                            if whole_edges is not None and workers > 0 else None)
         self._ready: Deque[Unit] = collections.deque()
         self._stop = False
         self._thread: Optional[threading.Thread] = None
@@ -339,7 +348,7 @@ class Server:
 
     # ---------------------------------------------------------------- scheduling
     def _units_active(self) -> int:
-        return len(self.running) + len(self.preparing) + len(self._ready)
+        return len(self.running) + len(self.preparing) + len(self._ready) + len(self._whole)
 
     def _admit(self) -> None:
         """FIFO admission: the queue head is never overtaken, so no job starves."""
@@ -386,9 +395,38 @@ class Server:
         now = self.clock()
         for j in unit.jobs:
             j.ready = now
+        whole = (unit.error is None and self._whole_pool is not None and unit.solo and unit.kmax > 0
+                 and unit.jobs[0].m >= self.whole_edges)
         with self._cv:
             self.preparing.pop(unit.uid, None)
-            self._ready.append(unit)
+            if whole:
+                self._whole[unit.uid] = unit
+            else:
+                self._ready.append(unit)
+            self._cv.notify_all()
+        if whole:
+            self._whole_pool.submit(self._run_whole, unit)
+
+    def _run_whole(self, unit: Unit) -> None:
+        """Every step of a large solo unit in one call, then its job completes."""
+        start = self.clock()
+        for j in unit.jobs:
+            j.started = start
+        counts: List[int] = []
+        try:
+            counts = self.backend.run_all(unit)[0]
+        except BaseException as e:  # reported on the job, the loop goes on
+            unit.error = e
+        with self._cv:
+            now = self.clock()
+            job = unit.jobs[0]
+            if unit.error is None:
+                job.counts = [int(x) for x in counts[: job.k]]
+                unit.step = unit.kmax
+                self._complete(job, now)
+            self._whole.pop(unit.uid, None)
+            self._retire(unit, now)
+            self._admit()
             self._cv.notify_all()
 
     def _complete(self, job: Job, now: float) -> None:
@@ -478,7 +516,7 @@ class Server:
 
     def idle(self) -> bool:
         with self._cv:
-            return not (self.pending or self.preparing or self._ready or self.running)
+            return not (self.pending or self.preparing or self._ready or self.running or self._whole)
 
     # ---------------------------------------------------------------- loop
     def _loop(self) -> None:
@@ -486,7 +524,8 @@ class Server:
             n = self.tick()
             if n == 0:
                 with self._cv:
-                    if self._stop and not (self.pending or self.preparing or self._ready or self.running):
+                    if self._stop and not (self.pending or self.preparing or self._ready or self.running
+                                           or self._whole):
                         return
                     self._cv.wait(timeout=0.001)
 
@@ -504,6 +543,8 @@ class Server:
             self._thread.join()
         if self._pool is not None:
             self._pool.shutdown(wait=wait)
+        if self._whole_pool is not None:
+            self._whole_pool.shutdown(wait=wait)
 
     def run_until_idle(self, max_ticks: int = 1 << 30) -> None:
         """Drive the loop from the calling thread (no background thread)."""
@@ -512,7 +553,7 @@ class Server:
                 return
             if self.tick() == 0:
                 with self._cv:
-                    if self.preparing:
+                    if self.preparing or self._whole:
                         self._cv.wait(timeout=0.001)
         raise RuntimeError("server did not become idle")
 

@@ -57,14 +57,14 @@ def alone(g, k):
     return out, counts
 
 
-def run_mix(graphs, ks, budget, cohort_edges, pin=False, gap_s=0.002, seed=0, burst=6):
+def run_mix(graphs, ks, budget, cohort_edges, pin=False, gap_s=0.002, seed=0, burst=6, whole_edges=None):
     """The first `burst` jobs are queued before the loop starts (so they are admitted
     together and small ones share a cohort); the rest arrive with Poisson gaps while
     the earlier ones are on the device."""
     from paper_2204_05821_amd import serve
     be = serve.DeviceBackend(streams=4, keep_outputs=True)
     pool = [serve.DeviceBackend.pin(g) if pin else g for g in graphs]
-    srv = serve.Server(be, budget_bytes=budget, workers=4, cohort_edges=cohort_edges)
+    srv = serve.Server(be, budget_bytes=budget, workers=4, cohort_edges=cohort_edges, whole_edges=whole_edges)
     rnd = random.Random(seed)
     jobs = []
     for idx, (g, k) in enumerate(zip(pool, ks)):
@@ -105,6 +105,19 @@ def test_each_result_same_alone_and_in_the_mix():
     print(f"[serve] stats {st}", flush=True)
     assert st["units"] < len(graphs)          # some jobs shared a cohort
     check_jobs(graphs, ks, jobs, "mix")
+
+
+def test_large_jobs_refined_whole_beside_stepped_cohorts():
+    """Jobs above the cohort limit refined in one call on workers while the cohorts step per tick."""
+    graphs = job_pool()
+    rnd = random.Random(9)
+    ks = [rnd.randint(1, 10) for _ in graphs]
+    print(f"[serve] whole mix of {len(graphs)} jobs, k={ks}", flush=True)
+    srv, jobs = run_mix(graphs, ks, budget=200 << 30, cohort_edges=60_000, whole_edges=60_001, seed=4)
+    st = srv.stats()
+    print(f"[serve] stats {st}", flush=True)
+    assert any(g.m > 60_000 for g in graphs) and any(g.m <= 60_000 for g in graphs)
+    check_jobs(graphs, ks, jobs, "whole")
 
 
 def test_mix_from_pinned_pool_with_mixed_label_forms():

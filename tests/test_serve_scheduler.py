@@ -248,6 +248,26 @@ def test_threaded_loop_with_workers():
     assert srv.peak_used <= 30_000 and srv.used == 0
 
 
+def test_large_jobs_run_whole_on_workers():
+    """With whole_edges, a job of at least that many edges is refined in one call on a worker
+    (never stepped per tick) while smaller ones are still stepped in cohorts; every job gets its
+    own counts, and slots and memory are held until it is done."""
+    be = FakeBackend(FakeClock())
+    srv = serve.Server(be, budget_bytes=60_000, workers=4, cohort_edges=300, whole_edges=400).start()
+    rnd = random.Random(11)
+    jobs = [srv.submit(small_graph(i), rnd.randint(1, 10)) for i in range(40)]
+    srv.stop()
+    whole = {j.unit.uid for j in jobs if j.m >= 400}
+    assert whole and any(j.m < 400 for j in jobs)
+    stepped = {u for _, u, _ in be.steps_seen}
+    assert not (whole & stepped)
+    for j in jobs:
+        assert j.done.is_set()
+        assert j.error is None, j.error
+        assert j.counts == be.ref_counts(j.graph)[: j.k]
+    assert srv.peak_used <= 60_000 and srv.used == 0 and srv.idle()
+
+
 def test_latency_percentiles():
     srv = serve.Server(FakeBackend(FakeClock()), budget_bytes=1, workers=0)
     for i in range(100):
