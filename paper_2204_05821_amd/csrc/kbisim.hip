@@ -41,7 +41,8 @@ constexpr int CLEAR_GRID = 2048;
 constexpr int MIN_RANGE_EDGES = 1024;  // smallest tunable range capacity
 constexpr int MIN_HUB_CHUNK = 2048;    // smallest tunable hub chunk
 constexpr int MAX_GRAPH_CACHE = 8;
-constexpr int SCHED_CHUNKS = 16;  // the schedule is built over this many vertex chunks in parallel
+constexpr int SCHED_CHUNKS = 16;  // host-built schedules: this many vertex chunks packed in parallel
+constexpr int64_t SCHED_DEVICE_MIN = 4096;  // graphs of at least this many vertices: schedule built on the device
 
 inline size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
@@ -79,7 +80,7 @@ Plan make_plan(int64_t n, int64_t m, int64_t nl, int kmax, int64_t num_graphs) {
   // "next" once), when full of vertices, or at the end; rows above the
   // capacity form ranges of their own.  Bounds use the smallest capacity.
   p.max_ranges = big / (RANGE_DMAX + 1) + 2 * big / (MIN_RANGE_EDGES + 1) + 2 * big / MIN_RANGE_EDGES +
-                 (int64_t)N / RANGE_VERTS + 8 + SCHED_CHUNKS;
+                 (int64_t)N / RANGE_VERTS + 8 + SCHED_CHUNKS + (int64_t)N / SCHED_CHUNK_V + 1;
   p.max_lists = big / (RANGE_DMAX + 1) + 8;
   p.nhub_max = big / (BLOCK_MAX + 1) + 1;
   p.nchunk_max = big / MIN_HUB_CHUNK + p.nhub_max + 1;
@@ -529,12 +530,171 @@ struct HostRowsLease {
 // ranges, and hub chunks, partitions and staging areas.  Synchronises.
 // row_max: longest row with a workgroup of its own (longer rows are hubs);
 // staged_max: longest hub staged in partitions (longer hubs use a global set).
+// Hub plan (staged chunks and partitions, global-set chunks) of a schedule
+// whose range lists are already counted in s, and the uploads: the range
+// lists and the hub list when they were built on the host (host_ranges),
+// then the hub plan.  Synchronises.
+int plan_hubs(kbisim_ctx *c, Schedule &s, const std::vector<int> &hubs, const std::vector<int64_t> &hub_deg,
+              int64_t staged_max, const std::vector<Range> *host_ranges) {
+  const Tuning &t = c->tune;
+  const int64_t nranges_total = (int64_t)s.nranges + s.nbig + s.nrow8 + s.nrow20;
+  // hubs: staged (partitioned) unless very large or out of offset space
+  std::vector<HubChunk> chunks;
+  std::vector<HubPart> parts;
+  std::vector<HubGChunk> gchunks;
+  std::vector<char> is_staged(hubs.size(), 0);
+  int64_t stage_at = 0, poff_at = 0;
+  for (size_t i = 0; i < hubs.size(); ++i) {
+    const int64_t d = hub_deg[i];
+    const int64_t C = (d + t.hub_chunk - 1) / t.hub_chunk;
+    const int P = hub_parts_for(t, d);
+    const bool staged = d <= staged_max && C <= HUB_PMAX && poff_at + C * (P + 1) <= c->plan.npoff_max;
+    if (!staged) continue;
+    HubPart hp;
+    hp.hub = (int)i;
+    hp.chunk0 = (int)chunks.size();
+    hp.nchunks = (int)C;
+    for (int64_t k = 0; k < C; ++k) {
+      HubChunk hc;
+      hc.hub = (int)i;
+      hc.parts = P;
+      hc.b = k * t.hub_chunk;
+      hc.e = std::min<int64_t>(d, (k + 1) * t.hub_chunk);
+      hc.stage = stage_at;
+      hc.poff = poff_at;
+      stage_at += t.hub_chunk;
+      poff_at += P + 1;
+      chunks.push_back(hc);
+    }
+    for (int q = 0; q < P; ++q) {
+      hp.part = q;
+      parts.push_back(hp);
+    }
+    is_staged[i] = 1;
+    s.info[4] += 1;
+    s.info[5] += d;
+  }
+  // global sets of the remaining hubs follow the staging areas
+  s.gset_begin = stage_at;
+  int64_t gset_at = stage_at;
+  for (size_t i = 0; i < hubs.size(); ++i) {
+    if (is_staged[i]) continue;
+    const int64_t d = hub_deg[i];
+    const int64_t size = 2 * d;
+    for (int64_t b = 0; b < d; b += HUB_GCHUNK) {
+      HubGChunk g;
+      g.hub = (int)i;
+      g.pad = 0;
+      g.b = b;
+      g.e = std::min<int64_t>(d, b + HUB_GCHUNK);
+      g.set_off = gset_at;
+      g.set_size = size;
+      gchunks.push_back(g);
+    }
+    gset_at += size;
+    s.info[6] += 1;
+    s.info[7] += d;
+  }
+  s.gset_end = gset_at;
+  if (nranges_total > c->plan.max_ranges || gset_at > c->plan.hubset_slots ||
+      (int64_t)chunks.size() > c->plan.nchunk_max || (int64_t)parts.size() > c->plan.npart_max ||
+      (int64_t)gchunks.size() > c->plan.ngchunk_max || (int64_t)hubs.size() > c->plan.nhub_max ||
+      (int64_t)hubs.size() > c->plan.max_lists)
+    return KBISIM_EINTERNAL;
+  s.hub_off = 0;
+  s.nhub = (int)hubs.size();
+  s.nchunks = (int)chunks.size();
+  s.nparts = (int)parts.size();
+  s.ngchunks = (int)gchunks.size();
+  if (host_ranges && !host_ranges->empty())
+    HIP_TRY(hipMemcpyAsync(c->ranges, host_ranges->data(), sizeof(Range) * host_ranges->size(), hipMemcpyHostToDevice,
+                           c->stream));
+  if (host_ranges && !hubs.empty())
+    HIP_TRY(hipMemcpyAsync(c->lists, hubs.data(), 4 * hubs.size(), hipMemcpyHostToDevice, c->stream));
+  if (!chunks.empty())
+    HIP_TRY(hipMemcpyAsync(c->chunks, chunks.data(), sizeof(HubChunk) * chunks.size(), hipMemcpyHostToDevice,
+                           c->stream));
+  if (!parts.empty())
+    HIP_TRY(hipMemcpyAsync(c->parts, parts.data(), sizeof(HubPart) * parts.size(), hipMemcpyHostToDevice, c->stream));
+  if (!gchunks.empty())
+    HIP_TRY(hipMemcpyAsync(c->gchunks, gchunks.data(), sizeof(HubGChunk) * gchunks.size(), hipMemcpyHostToDevice,
+                           c->stream));
+  int rc = 0;
+  if (s.nhub) {
+    if ((rc = fill_u64(c, c->hacc, s.nhub, 0))) return rc;
+    if ((rc = fill_i32(c, (int *)c->hcnt, s.nhub, 0))) return rc;
+    if ((rc = fill_u64(c, c->hubsets + s.gset_begin, s.gset_end - s.gset_begin, 0))) return rc;
+  }
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return 0;
+}
+
+// The schedule of graph rows built on the device (k_sched_walk): two walks
+// over fixed vertex chunks, a host scan of the per-chunk counts in between;
+// only the counts, the hub list and the hubs' degrees come back to the host.
+// Scratch: c->vlist (4n bytes; n >= SCHED_DEVICE_MIN).
+int build_schedule_device(kbisim_ctx *c, const int64_t *ptr, Schedule &s, int range_edges, int64_t row_max,
+                          int64_t staged_max) {
+  const int64_t n = c->g.n;
+  const int nch = (int)((n + SCHED_CHUNK_V - 1) / SCHED_CHUNK_V);
+  int *cnt = c->vlist, *off = cnt + 5 * (size_t)nch, *base = off + 5 * (size_t)nch;
+  int64_t *sums = reinterpret_cast<int64_t *>(c->vlist) + (10 * (size_t)nch + 4 + 1) / 2 + 1;
+  if ((size_t)((char *)(sums + 5 * (size_t)nch) - (char *)c->vlist) > 4 * (size_t)n) return KBISIM_EINTERNAL;
+  const unsigned grid = blocks_for(nch, 64);
+  k_sched_walk<false><<<grid, 64, 0, c->stream>>>(ptr, n, nch, range_edges, row_max, cnt, sums, nullptr, nullptr,
+                                                  nullptr, nullptr);
+  LAUNCH_CHECK();
+  std::vector<int> hc(5 * (size_t)nch);
+  std::vector<int64_t> hs(5 * (size_t)nch);
+  HIP_TRY(hipMemcpyAsync(hc.data(), cnt, 4 * hc.size(), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipMemcpyAsync(hs.data(), sums, 8 * hs.size(), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  int64_t tot[5] = {0, 0, 0, 0, 0};
+  std::vector<int> ho(5 * (size_t)nch);
+  for (int l = 0; l < 5; ++l)
+    for (int ci = 0; ci < nch; ++ci) {
+      ho[(size_t)l * nch + ci] = (int)tot[l];
+      tot[l] += hc[(size_t)l * nch + ci];
+    }
+  for (int ci = 0; ci < nch; ++ci) {
+    for (int i = 0; i < 4; ++i) s.info[i] += hs[5 * (size_t)ci + i];
+    s.nonempty += hs[5 * (size_t)ci + 4];
+  }
+  if (tot[0] + tot[1] + tot[2] + tot[3] > c->plan.max_ranges || tot[4] > c->plan.nhub_max ||
+      tot[4] > c->plan.max_lists)
+    return KBISIM_EINTERNAL;
+  s.nranges = (int)tot[0];
+  s.nbig = (int)tot[1];
+  s.nrow8 = (int)tot[2];
+  s.nrow20 = (int)tot[3];
+  const int hb[4] = {0, (int)tot[0], (int)(tot[0] + tot[1]), (int)(tot[0] + tot[1] + tot[2])};
+  HIP_TRY(hipMemcpyAsync(off, ho.data(), 4 * ho.size(), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync(base, hb, sizeof hb, hipMemcpyHostToDevice, c->stream));
+  k_sched_walk<true><<<grid, 64, 0, c->stream>>>(ptr, n, nch, range_edges, row_max, nullptr, nullptr, off, base,
+                                                 c->ranges, c->lists);
+  LAUNCH_CHECK();
+  const int nh = (int)tot[4];
+  std::vector<int> hubs((size_t)nh);
+  std::vector<int64_t> hub_deg((size_t)nh);
+  if (nh > 0) {
+    // the hubs' degrees, in the key-hash array (8n bytes, unused at create time; nh <= n)
+    int64_t *deg = reinterpret_cast<int64_t *>(c->H);
+    k_row_degrees<<<blocks_for(nh, 256), 256, 0, c->stream>>>(nh, c->lists, ptr, deg);
+    LAUNCH_CHECK();
+    HIP_TRY(hipMemcpyAsync(hubs.data(), c->lists, 4 * (size_t)nh, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(hub_deg.data(), deg, 8 * (size_t)nh, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+  }
+  return plan_hubs(c, s, hubs, hub_deg, staged_max, nullptr);
+}
+
 int build_schedule(kbisim_ctx *c, const int64_t *ptr, Schedule &s, int range_edges, int64_t row_max,
                    int64_t staged_max) {
   const int64_t n = c->g.n;
   const Tuning &t = c->tune;
   s = Schedule{};
   s.range_edges = range_edges;
+  if (ptr && n >= SCHED_DEVICE_MIN) return build_schedule_device(c, ptr, s, range_edges, row_max, staged_max);
   HostRowsLease lease;
   std::vector<int64_t> pageable;  // when no pinned host memory may be taken
   const int64_t *rp = nullptr;
@@ -659,95 +819,9 @@ int build_schedule(kbisim_ctx *c, const int64_t *ptr, Schedule &s, int range_edg
   ranges.insert(ranges.end(), big_ranges.begin(), big_ranges.end());
   ranges.insert(ranges.end(), row8_ranges.begin(), row8_ranges.end());
   ranges.insert(ranges.end(), row20_ranges.begin(), row20_ranges.end());
-  // hubs: staged (partitioned) unless very large or out of offset space
-  std::vector<HubChunk> chunks;
-  std::vector<HubPart> parts;
-  std::vector<HubGChunk> gchunks;
-  std::vector<char> is_staged(hubs.size(), 0);
-  int64_t stage_at = 0, poff_at = 0;
-  for (size_t i = 0; i < hubs.size(); ++i) {
-    const int64_t d = deg(hubs[i]);
-    const int64_t C = (d + t.hub_chunk - 1) / t.hub_chunk;
-    const int P = hub_parts_for(t, d);
-    const bool staged = d <= staged_max && C <= HUB_PMAX && poff_at + C * (P + 1) <= c->plan.npoff_max;
-    if (!staged) continue;
-    HubPart hp;
-    hp.hub = (int)i;
-    hp.chunk0 = (int)chunks.size();
-    hp.nchunks = (int)C;
-    for (int64_t k = 0; k < C; ++k) {
-      HubChunk hc;
-      hc.hub = (int)i;
-      hc.parts = P;
-      hc.b = k * t.hub_chunk;
-      hc.e = std::min<int64_t>(d, (k + 1) * t.hub_chunk);
-      hc.stage = stage_at;
-      hc.poff = poff_at;
-      stage_at += t.hub_chunk;
-      poff_at += P + 1;
-      chunks.push_back(hc);
-    }
-    for (int q = 0; q < P; ++q) {
-      hp.part = q;
-      parts.push_back(hp);
-    }
-    is_staged[i] = 1;
-    s.info[4] += 1;
-    s.info[5] += d;
-  }
-  // global sets of the remaining hubs follow the staging areas
-  s.gset_begin = stage_at;
-  int64_t gset_at = stage_at;
-  for (size_t i = 0; i < hubs.size(); ++i) {
-    if (is_staged[i]) continue;
-    const int64_t d = deg(hubs[i]);
-    const int64_t size = 2 * d;
-    for (int64_t b = 0; b < d; b += HUB_GCHUNK) {
-      HubGChunk g;
-      g.hub = (int)i;
-      g.pad = 0;
-      g.b = b;
-      g.e = std::min<int64_t>(d, b + HUB_GCHUNK);
-      g.set_off = gset_at;
-      g.set_size = size;
-      gchunks.push_back(g);
-    }
-    gset_at += size;
-    s.info[6] += 1;
-    s.info[7] += d;
-  }
-  s.gset_end = gset_at;
-  if ((int64_t)ranges.size() > c->plan.max_ranges || gset_at > c->plan.hubset_slots ||
-      (int64_t)chunks.size() > c->plan.nchunk_max || (int64_t)parts.size() > c->plan.npart_max ||
-      (int64_t)gchunks.size() > c->plan.ngchunk_max || (int64_t)hubs.size() > c->plan.nhub_max ||
-      (int64_t)hubs.size() > c->plan.max_lists)
-    return KBISIM_EINTERNAL;
-  s.hub_off = 0;
-  s.nhub = (int)hubs.size();
-  s.nchunks = (int)chunks.size();
-  s.nparts = (int)parts.size();
-  s.ngchunks = (int)gchunks.size();
-  if (!ranges.empty())
-    HIP_TRY(hipMemcpyAsync(c->ranges, ranges.data(), sizeof(Range) * ranges.size(), hipMemcpyHostToDevice, c->stream));
-
-  if (!hubs.empty())
-    HIP_TRY(hipMemcpyAsync(c->lists, hubs.data(), 4 * hubs.size(), hipMemcpyHostToDevice, c->stream));
-  if (!chunks.empty())
-    HIP_TRY(hipMemcpyAsync(c->chunks, chunks.data(), sizeof(HubChunk) * chunks.size(), hipMemcpyHostToDevice,
-                           c->stream));
-  if (!parts.empty())
-    HIP_TRY(hipMemcpyAsync(c->parts, parts.data(), sizeof(HubPart) * parts.size(), hipMemcpyHostToDevice, c->stream));
-  if (!gchunks.empty())
-    HIP_TRY(hipMemcpyAsync(c->gchunks, gchunks.data(), sizeof(HubGChunk) * gchunks.size(), hipMemcpyHostToDevice,
-                           c->stream));
-  int rc = 0;
-  if (s.nhub) {
-    if ((rc = fill_u64(c, c->hacc, s.nhub, 0))) return rc;
-    if ((rc = fill_i32(c, (int *)c->hcnt, s.nhub, 0))) return rc;
-    if ((rc = fill_u64(c, c->hubsets + s.gset_begin, s.gset_end - s.gset_begin, 0))) return rc;
-  }
-  HIP_TRY(hipStreamSynchronize(c->stream));
-  return 0;
+  std::vector<int64_t> hub_deg(hubs.size());
+  for (size_t i = 0; i < hubs.size(); ++i) hub_deg[i] = deg(hubs[i]);
+  return plan_hubs(c, s, hubs, hub_deg, staged_max, &ranges);
 }
 
 // Bits needed for x (0 for 0).

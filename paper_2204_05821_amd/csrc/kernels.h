@@ -1991,6 +1991,94 @@ __global__ void __launch_bounds__(256) k_radix_scatter(int64_t m, const u64 *__r
   }
 }
 
+// ---------------------------------------------------------------- degree schedule
+// Rows are packed greedily into ranges of consecutive vertices: a range
+// closes before a row that would overflow it (range_edges entries), after
+// RANGE_VERTS vertices, before a longer row and at the end of its chunk of
+// SCHED_CHUNK_V vertices; longer rows go to the row tiers (up to RANGE_DMAX,
+// ROW_MAX and row_max entries) or are hubs.  One thread walks one chunk, so
+// the schedule depends on n and the degrees only.  The first walk counts per
+// chunk (cnt[list * nchunks + chunk], lists: ranges, up to RANGE_DMAX, up to
+// ROW_MAX, up to row_max, hubs; sums[5 * chunk + i]: range vertices and
+// entries, row-tier rows and entries, non-empty rows); the second writes at
+// the scanned offsets off[list * nchunks + chunk], the range lists one after
+// another in `ranges` (list starts in base[0..3]) and the hubs in `hubs`.
+constexpr int SCHED_CHUNK_V = 16384;
+
+template <bool WRITE>
+__global__ void k_sched_walk(const int64_t *__restrict__ ptr, int64_t n, int nchunks, int range_edges,
+                             int64_t row_max, int *__restrict__ cnt, int64_t *__restrict__ sums,
+                             const int *__restrict__ off, const int *__restrict__ base, Range *__restrict__ ranges,
+                             int *__restrict__ hubs) {
+  const int ci = blockIdx.x * blockDim.x + threadIdx.x;
+  if (ci >= nchunks) return;
+  const int64_t v0 = (int64_t)ci * SCHED_CHUNK_V, v1 = min(n, v0 + (int64_t)SCHED_CHUNK_V);
+  int c[5] = {0, 0, 0, 0, 0};
+  int o[5] = {0, 0, 0, 0, 0};
+  int b4[4] = {0, 0, 0, 0};
+  if constexpr (WRITE) {
+#pragma unroll
+    for (int l = 0; l < 5; ++l) o[l] = off[(int64_t)l * nchunks + ci];
+#pragma unroll
+    for (int l = 0; l < 4; ++l) b4[l] = base[l];
+  }
+  int64_t rv = 0, re = 0, rowv = 0, rowe = 0, nonempty = 0;
+  int64_t cur0 = -1, cur_e = 0, cur_b = 0;
+  auto emit = [&](int list, int64_t a, int64_t z, int64_t ne, int64_t e0) {
+    if constexpr (WRITE) ranges[b4[list] + o[list] + c[list]] = Range{(int)a, (int)z, (int)ne, 0, e0};
+    ++c[list];
+  };
+  auto close = [&](int64_t vend) {
+    if (cur0 >= 0) emit(0, cur0, vend, cur_e, cur_b);
+    cur0 = -1;
+    cur_e = 0;
+  };
+  constexpr int PF = 16;  // row ends requested together
+  int64_t prev = ptr[v0];
+  for (int64_t vb = v0; vb < v1; vb += PF) {
+    int64_t nx[PF];
+#pragma unroll
+    for (int j = 0; j < PF; ++j) nx[j] = vb + j < v1 ? ptr[vb + j + 1] : 0;
+#pragma unroll
+    for (int j = 0; j < PF; ++j) {
+      const int64_t v = vb + j;
+      if (v >= v1) break;
+      const int64_t b = prev, d = nx[j] - prev;
+      prev = nx[j];
+      nonempty += d > 0;
+      if (d > row_max) {
+        close(v);
+        if constexpr (WRITE) hubs[o[4] + c[4]] = (int)v;
+        ++c[4];
+      } else if (d > range_edges) {
+        close(v);
+        emit(d > ROW_MAX ? 3 : d > RANGE_DMAX ? 2 : 1, v, v + 1, d, b);
+        rowv += 1;
+        rowe += d;
+      } else {
+        if (cur0 >= 0 && (cur_e + d > range_edges || v - cur0 == RANGE_VERTS)) close(v);
+        if (cur0 < 0) {
+          cur0 = v;
+          cur_b = b;
+        }
+        cur_e += d;
+        rv += 1;
+        re += d;
+      }
+    }
+  }
+  close(v1);
+  if constexpr (!WRITE) {
+#pragma unroll
+    for (int l = 0; l < 5; ++l) cnt[(int64_t)l * nchunks + ci] = c[l];
+    sums[5 * (int64_t)ci + 0] = rv;
+    sums[5 * (int64_t)ci + 1] = re;
+    sums[5 * (int64_t)ci + 2] = rowv;
+    sums[5 * (int64_t)ci + 3] = rowe;
+    sums[5 * (int64_t)ci + 4] = nonempty;
+  }
+}
+
 // In-degree ranking: key[v] = (RANK_KEYMAX - min(indeg, RANK_KEYMAX)) << 32 | v;
 // a stable sort on the high field orders vertices by decreasing in-degree,
 // ties by vertex id.
@@ -2410,6 +2498,15 @@ __global__ void k_row_extents(int count, const int *__restrict__ list, const int
   const int v = list[i];
   be[2 * i] = row_ptr[v];
   be[2 * i + 1] = row_ptr[v + 1];
+}
+
+// Row lengths of listed vertices.
+__global__ void k_row_degrees(int count, const int *__restrict__ list, const int64_t *__restrict__ row_ptr,
+                              int64_t *__restrict__ deg) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const int v = list[i];
+  deg[i] = row_ptr[v + 1] - row_ptr[v];
 }
 
 // Dense ids of the vertices that are not heads: the id of their representative.
