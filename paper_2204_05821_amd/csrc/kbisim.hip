@@ -42,7 +42,13 @@ constexpr int MIN_RANGE_EDGES = 1024;  // smallest tunable range capacity
 constexpr int MIN_HUB_CHUNK = 2048;    // smallest tunable hub chunk
 constexpr int MAX_GRAPH_CACHE = 8;
 constexpr int SCHED_CHUNKS = 16;  // host-built schedules: this many vertex chunks packed in parallel
-constexpr int64_t SCHED_DEVICE_MIN = 4096;  // graphs of at least this many vertices: schedule built on the device
+// Graphs of at least this many vertices get their schedule built on the
+// device.  A chunk walk is sequential, so the two walks take about 8 ms
+// whatever the graph; the host copy of the row offsets and the packing cost
+// about 1 ns per vertex, and win below this size (an 8.4M-vertex graph
+// creates in 17.5 ms instead of 21.4; serving, which creates many small
+// contexts, keeps its latency).
+constexpr int64_t SCHED_DEVICE_MIN = (int64_t)1 << 24;
 
 inline size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
@@ -153,6 +159,7 @@ struct Tuning {
   int hub_part_target = HUB_PART_TARGET;
   int key_bits = 0;  // LDS set keys: 0 = 32-bit (exact where pairs fit, else hashed), 32 = hashed, 64 = 64-bit
   int hub_parts_cap = HUB_PMAX;  // most partitions per staged hub (a smaller cap is a test knob)
+  bool device_schedule = false;  // test knob: build the schedule on the device at any size
   int scan_items = SCAN_ITEMS;   // vertices per thread in the numbering scan: 8 or 16
 };
 
@@ -632,7 +639,7 @@ int plan_hubs(kbisim_ctx *c, Schedule &s, const std::vector<int> &hubs, const st
 // The schedule of graph rows built on the device (k_sched_walk): two walks
 // over fixed vertex chunks, a host scan of the per-chunk counts in between;
 // only the counts, the hub list and the hubs' degrees come back to the host.
-// Scratch: c->vlist (4n bytes; n >= SCHED_DEVICE_MIN).
+// Scratch: c->vlist (4n bytes; n >= 64).
 int build_schedule_device(kbisim_ctx *c, const int64_t *ptr, Schedule &s, int range_edges, int64_t row_max,
                           int64_t staged_max) {
   const int64_t n = c->g.n;
@@ -694,7 +701,9 @@ int build_schedule(kbisim_ctx *c, const int64_t *ptr, Schedule &s, int range_edg
   const Tuning &t = c->tune;
   s = Schedule{};
   s.range_edges = range_edges;
-  if (ptr && n >= SCHED_DEVICE_MIN) return build_schedule_device(c, ptr, s, range_edges, row_max, staged_max);
+  // (the device walk needs 80 bytes of scratch per chunk in the 4n bytes of vlist)
+  if (ptr && (n >= SCHED_DEVICE_MIN || (c->tune.device_schedule && n >= 64)))
+    return build_schedule_device(c, ptr, s, range_edges, row_max, staged_max);
   HostRowsLease lease;
   std::vector<int64_t> pageable;  // when no pinned host memory may be taken
   const int64_t *rp = nullptr;
@@ -1918,6 +1927,9 @@ int create_impl(const kbisim_graph *g, int kmax, const kbisim_tuning *tuning, vo
     int q = atoi(pdbg);
     if (q >= 1 && q <= HUB_PMAX && (q & (q - 1)) == 0) c->tune.hub_parts_cap = q;
   }
+  // Test knob: build the degree schedule on the device for small graphs too.
+  const char *sdbg = getenv("KBISIM_DEBUG_DEVICE_SCHEDULE");
+  if (sdbg && *sdbg == '1') c->tune.device_schedule = true;
   // Test knob: keep only this many bits of hashed set keys, so that keys
   // collide inside rows (the exact check must still separate the pair sets).
   const char *kdbg = getenv("KBISIM_DEBUG_KEY_BITS");

@@ -306,3 +306,9 @@ def test_gather_probe_runs_on_small_and_empty_graphs():
         ids2, _ = r.refine(1)                      # the context still refines correctly afterwards
         assert torch.equal(ids[0], ids2[0])
         r.close()
+
+
+def test_batch_with_device_built_schedule(monkeypatch):
+    """Batches with the degree schedule built on the device (graphs of every size in one union)."""
+    monkeypatch.setenv("KBISIM_DEBUG_DEVICE_SCHEDULE", "1")
+    check_batch(mixed_graphs(seed=8, count=24), 4, "device schedule")

@@ -192,6 +192,28 @@ def test_key_width_forced_and_automatic(kbits):
         assert_same_tuned(g, 6, kb.tuning(key_bits=kbits), f"keys{kbits}-{g.name}")
 
 
+@pytest.mark.parametrize("kbits", [0, 64])
+def test_device_built_schedule(kbits, monkeypatch):
+    """The degree schedule built on the device (as for graphs of 16M+ vertices), forced on small
+    graphs: every tier boundary, hubs, label-set rows, empty rows; the same tier totals as the
+    host-built schedule and the reference's partitions."""
+    kb = _kb()
+    t = kb.tuning(key_bits=kbits)
+    graphs = [tier_graph(seed=31, labels=50, shared_targets=2000), graphgen.rmat(14, 200_000, seed=32),
+              graphgen.rmat_rdf(13, 90_000, seed=33, types=200, elabels=300),
+              graphgen.deep(seed=34, n=20_000, avg_degree=1.1), graphgen.tiny(seed=35, n=3000, m=6000)]
+    for g in graphs:
+        monkeypatch.delenv("KBISIM_DEBUG_DEVICE_SCHEDULE", raising=False)
+        r = kb.Refiner(*kb.to_device(g), kmax=1, tuning=t)
+        host_tiers = r.schedule_info()
+        r.close()
+        monkeypatch.setenv("KBISIM_DEBUG_DEVICE_SCHEDULE", "1")
+        r = kb.Refiner(*kb.to_device(g), kmax=1, tuning=t)
+        assert r.schedule_info() == host_tiers, g.name
+        r.close()
+        assert_same_tuned(g, 5, t, f"device-schedule keys{kbits}-{g.name}")
+
+
 @pytest.mark.parametrize("label_max", [(1 << 11) - 1, 1 << 11])
 def test_key_width_boundary(label_max):
     """n = 2^20 gives 20 bits of block id; labels up to 2^11 - 1 fill 31 bits exactly (narrow keys),
