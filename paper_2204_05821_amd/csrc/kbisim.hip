@@ -282,6 +282,13 @@ int hip_fail(hipError_t e) {
 
 inline unsigned blocks_for(int64_t items, int per) { return (unsigned)((items + per - 1) / per); }
 
+// Range check of cnt int32 values on stream s (see k_validate_vals).
+void validate_vals(hipStream_t s, int64_t cnt, const int32_t *vals, int64_t upper, u32 *err, u32 bit) {
+  if (cnt <= 0) return;
+  const unsigned g = (unsigned)std::min<int64_t>(VALIDATE_GRID, blocks_for(cnt / 4 + 1, 256));
+  k_validate_vals<<<g, 256, 0, s>>>(cnt, vals, upper, err, bit);
+}
+
 // ---- per-kernel profiling: events around each launch, resolved after syncs.
 hipEvent_t prof_event(kbisim_ctx *c) {
   if (c->ev_used == c->ev_pool.size()) {
@@ -1541,7 +1548,7 @@ int update_steps_t(kbisim_ctx *c, const kbisim_graph *gn, int k, int32_t *const 
   auto &S = c->is;
   const int32_t *lab = separate_labels(c) ? sep_labels(c) : nullptr;
   int rc = 0;
-  bool gpid_ok = true;  // gpid[i & 1] holds names_prev in rank order (P0 for the first step)
+  bool gpid_ok = false;  // gpid[i & 1] holds names_prev in rank order (written when a step needs it)
   for (int i = 0; i < k; ++i) {
     if (i >= 2) {
       // P'_{i-1} refines P'_{i-2}: with as many blocks it is the same
@@ -1551,12 +1558,16 @@ int update_steps_t(kbisim_ctx *c, const kbisim_graph *gn, int k, int32_t *const 
       HIP_TRY(hipMemcpyAsync(pc, &c->dcounts[i - 2], sizeof pc, hipMemcpyDeviceToHost, c->stream));
       HIP_TRY(hipStreamSynchronize(c->stream));
       if (pc[0] == pc[1]) {
-        for (int j = i; j < k; ++j) {
-          k_copy_i32<<<std::min<unsigned>(blocks_for(n, 256), 65536), 256, 0, c->stream>>>(out[j], out[i - 1], n);
+        for (int j0 = i; j0 < k; j0 += CopyDsts::MAX) {
+          CopyDsts d{};
+          d.nd = std::min(k - j0, (int)CopyDsts::MAX);
+          for (int q = 0; q < d.nd; ++q) d.d[q] = out[j0 + q];
+          k_copy_multi<<<std::min<unsigned>(blocks_for(n, 256), 65536), 256, 0, c->stream>>>(d, out[i - 1], n);
           LAUNCH_CHECK();
+        }
+        for (int j = i; j < k; ++j)
           HIP_TRY(hipMemcpyAsync(&c->dcounts[j], &c->dcounts[i - 1], sizeof(int64_t), hipMemcpyDeviceToDevice,
                                  c->stream));
-        }
         return 0;
       }
     }
@@ -1564,9 +1575,9 @@ int update_steps_t(kbisim_ctx *c, const kbisim_graph *gn, int k, int32_t *const 
     int *cnt = c->counters + CNT_STRIDE * i;
     if ((rc = fill_i32(c, cnt, CNT_STRIDE, 0))) return rc;
     if ((rc = fill_i32(c, reinterpret_cast<int *>(S.touch), (n + 3) / 4, 0))) return rc;
-    k_update_flags<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, S.edited, S.flag, S.dirty, S.skip, gn->row_ptr,
-                                                              cnt + 8, S.psmall, S.plarge, S.MVc + (size_t)i * n,
-                                                              S.touch, S.lk);
+    k_update_flags<<<blocks_for((n + FLAGS_GROUP - 1) / FLAGS_GROUP, 256), 256, 0, c->stream>>>(
+        n, S.edited, S.flag, S.dirty, S.skip, gn->row_ptr, cnt + 8, S.psmall, S.plarge, S.MVc + (size_t)i * n, S.touch,
+        S.lk);
     LAUNCH_CHECK();
     if ((rc = fill_i32(c, reinterpret_cast<int *>(S.flag), (n + 3) / 4, 0))) return rc;
     // few vertices flagged by the previous step: sign them from lists
@@ -1619,12 +1630,11 @@ int update_impl(kbisim_ctx *c, const kbisim_graph *gn, const int32_t *rows, int6
   if ((rc = fill_i32(c, (int *)c->err, 1, 0))) return rc;
   k_validate_rows<<<blocks_for(n + 1, 256), 256, 0, c->stream>>>(n, gn->m, gn->row_ptr, c->err, ERR_GRAPH_ROWPTR);
   if (gn->m > 0) {
-    k_validate_vals<<<blocks_for(gn->m, 256), 256, 0, c->stream>>>(gn->m, gn->col, n, c->err, ERR_GRAPH_COL);
+    validate_vals(c->stream, gn->m, gn->col, n, c->err, ERR_GRAPH_COL);
     if (gn->elabel)
-      k_validate_vals<<<blocks_for(gn->m, 256), 256, 0, c->stream>>>(gn->m, gn->elabel, (int64_t)c->max_label + 1,
-                                                                      c->err, ERR_GRAPH_ELABEL);
+      validate_vals(c->stream, gn->m, gn->elabel, (int64_t)c->max_label + 1, c->err, ERR_GRAPH_ELABEL);
   }
-  if (nrows) k_validate_vals<<<blocks_for(nrows, 256), 256, 0, c->stream>>>(nrows, rows, n, c->err, ERR_BAD_PID);
+  if (nrows) validate_vals(c->stream, nrows, rows, n, c->err, ERR_BAD_PID);
   LAUNCH_CHECK();
   u32 err = 0;
   if ((rc = read_err(c, &err))) return rc;
@@ -1701,8 +1711,6 @@ int update_impl(kbisim_ctx *c, const kbisim_graph *gn, const int32_t *rows, int6
       }
     }
   }
-  k_scatter_rank<<<blocks_for(n, 256), 256, 0, c->stream>>>((int)n, c->p0, c->rank, c->gpid[0]);
-  LAUNCH_CHECK();
   // every vertex may carry a key in an update (edited rows can gain entries),
   // and empty signatures are grouped by block names below 2n
   const u64 tmask_saved = c->tmask_steps;
@@ -1951,14 +1959,14 @@ int create_impl(const kbisim_graph *g, int kmax, const kbisim_tuning *tuning, vo
     if (hipGetLastError() != hipSuccess) return fail(KBISIM_EHIP);
   }
   if (m > 0) {
-    k_validate_vals<<<blocks_for(m, 256), 256, 0, c->stream>>>(m, g->col, n, c->err, ERR_GRAPH_COL);
-    if (g->elabel) k_validate_vals<<<blocks_for(m, 256), 256, 0, c->stream>>>(m, g->elabel, -1, c->err, ERR_GRAPH_ELABEL);
+    validate_vals(c->stream, m, g->col, n, c->err, ERR_GRAPH_COL);
+    if (g->elabel) validate_vals(c->stream, m, g->elabel, -1, c->err, ERR_GRAPH_ELABEL);
   }
   if (g->vlabel_ptr) {
     k_validate_rows<<<blocks_for(n + 1, 256), 256, 0, c->stream>>>(n, nl, g->vlabel_ptr, c->err, ERR_GRAPH_VPTR);
-    if (nl > 0) k_validate_vals<<<blocks_for(nl, 256), 256, 0, c->stream>>>(nl, g->vlabel, -1, c->err, ERR_GRAPH_VLABEL);
+    if (nl > 0) validate_vals(c->stream, nl, g->vlabel, -1, c->err, ERR_GRAPH_VLABEL);
   } else if (g->vlabel && n > 0) {
-    k_validate_vals<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, g->vlabel, -1, c->err, ERR_GRAPH_VLABEL);
+    validate_vals(c->stream, n, g->vlabel, -1, c->err, ERR_GRAPH_VLABEL);
   }
   if (hipGetLastError() != hipSuccess) return fail(KBISIM_EHIP);
   u32 err = 0;
@@ -2108,7 +2116,7 @@ int kbisim_refine_from(kbisim_ctx *c, const int32_t *pid_i, int k, int32_t *cons
   if (c->g.n > 0) {
     int rc0 = fill_i32(c, (int *)c->err, 1, 0);
     if (rc0) return rc0;
-    k_validate_vals<<<blocks_for(c->g.n, 256), 256, 0, c->stream>>>(c->g.n, pid_i, c->g.n, c->err, ERR_BAD_PID);
+    validate_vals(c->stream, c->g.n, pid_i, c->g.n, c->err, ERR_BAD_PID);
     LAUNCH_CHECK();
     u32 err = 0;
     int rc = read_err(c, &err);
@@ -2443,8 +2451,8 @@ int kbisim_transpose(int64_t n, int64_t m, const int64_t *row_ptr, const int32_t
   k_fill_i32<<<1, 64, 0, s>>>((int *)err, 1, 0);
   k_validate_rows<<<blocks_for(n + 1, 256), 256, 0, s>>>(n, m, row_ptr, err, ERR_GRAPH_ROWPTR);
   if (m > 0) {
-    k_validate_vals<<<blocks_for(m, 256), 256, 0, s>>>(m, col, n, err, ERR_GRAPH_COL);
-    if (elabel) k_validate_vals<<<blocks_for(m, 256), 256, 0, s>>>(m, elabel, -1, err, ERR_GRAPH_ELABEL);
+    validate_vals(s, m, col, n, err, ERR_GRAPH_COL);
+    if (elabel) validate_vals(s, m, elabel, -1, err, ERR_GRAPH_ELABEL);
   }
   HIP_TRY(hipGetLastError());
   u32 bad = 0;
@@ -2555,8 +2563,8 @@ int kbisim_quotient(kbisim_ctx *c, const int32_t *src_pid, const int32_t *dst_pi
   int rc = 0;
   // both partitions must hold ids in [0, n)
   k_fill_i32<<<1, 64, 0, s>>>((int *)word, 4, 0);
-  k_validate_vals<<<blocks_for(n, 256), 256, 0, s>>>(n, src_pid, n, word, ERR_BAD_PID);
-  k_validate_vals<<<blocks_for(n, 256), 256, 0, s>>>(n, dst_pid, n, word, ERR_BAD_PID);
+  validate_vals(s, n, src_pid, n, word, ERR_BAD_PID);
+  validate_vals(s, n, dst_pid, n, word, ERR_BAD_PID);
   k_max_i32<<<(unsigned)std::min<int64_t>(blocks_for(n, 256), 4096), 256, 0, s>>>(n, src_pid, word + 1);
   k_max_i32<<<(unsigned)std::min<int64_t>(blocks_for(n, 256), 4096), 256, 0, s>>>(n, dst_pid, word + 2);
   HIP_TRY(hipGetLastError());

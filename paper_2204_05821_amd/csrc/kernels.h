@@ -427,11 +427,38 @@ __global__ void k_max_i32(int64_t cnt, const int32_t *__restrict__ vals, u32 *ou
   if ((threadIdx.x & (WAVE - 1)) == 0 && mx) atomicMax(out, mx);
 }
 
-__global__ void k_validate_vals(int64_t cnt, const int32_t *__restrict__ vals, int64_t upper, u32 *err, u32 bit) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= cnt) return;
-  int64_t x = vals[i];
-  if (x < 0 || (upper >= 0 && x >= upper)) atomicOr(err, bit);
+// Range check of cnt values: any value < 0, or >= upper when upper >= 0, sets
+// `bit` in *err.  Grid-stride over the 16-byte-aligned body of the array (the
+// few values before and after it one by one), 4 groups of 4 values in flight
+// per thread, one atomic per wave that found a bad value.
+constexpr int VALIDATE_GRID = 4096;
+typedef u32 u32x4 __attribute__((ext_vector_type(4)));
+__global__ void __launch_bounds__(256) k_validate_vals(int64_t cnt, const int32_t *__restrict__ vals, int64_t upper,
+                                                       u32 *err, u32 bit) {
+  // negative values become >= 2^31 as unsigned: one compare covers both ends
+  const u32 lim = (upper >= 0 && upper < 0x80000000ll) ? (u32)upper : 0x80000000u;
+  const uintptr_t a = reinterpret_cast<uintptr_t>(vals);
+  const int64_t head = (a & 3) ? cnt : std::min<int64_t>(cnt, (int64_t)(((16 - (a & 15)) & 15) >> 2));
+  const int64_t ng = (cnt - head) >> 2;
+  const u32x4 *__restrict__ g4 = reinterpret_cast<const u32x4 *>(vals + head);
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  const int64_t gt = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  bool bad = false;
+  int64_t i = gt;
+  for (; i + 3 * stride < ng; i += 4 * stride) {
+    u32x4 q[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) q[j] = __builtin_nontemporal_load(&g4[i + j * stride]);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) bad |= (q[j].x >= lim) | (q[j].y >= lim) | (q[j].z >= lim) | (q[j].w >= lim);
+  }
+  for (; i < ng; i += stride) {
+    const u32x4 q = __builtin_nontemporal_load(&g4[i]);
+    bad |= (q.x >= lim) | (q.y >= lim) | (q.z >= lim) | (q.w >= lim);
+  }
+  for (int64_t t = gt; t < head; t += stride) bad |= (u32)vals[t] >= lim;
+  for (int64_t t = head + (ng << 2) + gt; t < cnt; t += stride) bad |= (u32)vals[t] >= lim;
+  if (__ballot(bad) && (threadIdx.x & (WAVE - 1)) == 0) atomicOr(err, bit);
 }
 
 // ---------------------------------------------------------------- signature tiers
@@ -2438,41 +2465,62 @@ __global__ void __launch_bounds__(256) k_classify(int n, const int32_t *__restri
   __syncthreads();
   const u32 epoch = dep[EP_TABLE], zep = dep[EP_ZERO];
   const int64_t stride = (int64_t)gridDim.x * 256;
-  for (int64_t base = (int64_t)blockIdx.x * 256; base < n; base += stride) {
-    const int v = (int)(base + threadIdx.x);
-    const bool act = v < n;
-    bool listed = false;
-    if (act) {
-      if (dirty[v]) {
-        listed = true;
-      } else {
-        const int h = mvc[v];
-        const u32 dc = DCc[v];
-        const u64 hv = Hc[v];
-        bool hit = touch[h] != 0;
-        if (!hit) {
-          if (dc == 0) {
-            const u32 nm = (u32)names[v];
-            const u32 b = filter_name_bit(nm);
-            hit = (fl[b >> 5] >> (b & 31)) & 1u;
-            if (hit) hit = (u32)(zrep[nm] >> 32) == ~zep;
-          } else {
-            const u32 b = filter_key_bit(hv);
-            hit = (fl[b >> 5] >> (b & 31)) & 1u;
-            if (hit) hit = table_lookup(table, tmask, hv, epoch) >= 0;
-          }
-        }
-        if (hit) {
-          H[v] = hv;
-          DC[v] = dc;
+  // two vertices per thread per round, every independent load requested
+  // before any is used (the kernel waits on memory, not on arithmetic)
+  constexpr int B = 2;
+  for (int64_t base = (int64_t)blockIdx.x * 256; base < n; base += B * stride) {
+    int v[B];
+    bool act[B];
+    unsigned char dv[B];
+    int hd[B];
+    u32 dc[B];
+    u64 hv[B];
+    int32_t nm[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      const int64_t x = base + b * stride + threadIdx.x;
+      act[b] = x < n;
+      v[b] = act[b] ? (int)x : 0;
+      dv[b] = act[b] ? dirty[v[b]] : 1;
+      hd[b] = act[b] ? mvc[v[b]] : 0;
+      dc[b] = act[b] ? DCc[v[b]] : 0;
+      hv[b] = act[b] ? Hc[v[b]] : 0;
+      nm[b] = act[b] ? names[v[b]] : 0;
+    }
+    unsigned char tb[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) tb[b] = (act[b] && !dv[b]) ? touch[hd[b]] : 1;
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      bool listed = false;
+      if (act[b]) {
+        if (dv[b]) {
           listed = true;
         } else {
-          rep[v] = h;
-          names_out[v] = h;
+          bool hit = tb[b] != 0;
+          if (!hit) {
+            if (dc[b] == 0) {
+              const u32 fb = filter_name_bit((u32)nm[b]);
+              hit = (fl[fb >> 5] >> (fb & 31)) & 1u;
+              if (hit) hit = (u32)(zrep[(u32)nm[b]] >> 32) == ~zep;
+            } else {
+              const u32 fb = filter_key_bit(hv[b]);
+              hit = (fl[fb >> 5] >> (fb & 31)) & 1u;
+              if (hit) hit = table_lookup(table, tmask, hv[b], epoch) >= 0;
+            }
+          }
+          if (hit) {
+            H[v[b]] = hv[b];
+            DC[v[b]] = dc[b];
+            listed = true;
+          } else {
+            rep[v[b]] = hd[b];
+            names_out[v[b]] = hd[b];
+          }
         }
       }
+      wave_append(count, list, listed, v[b]);
     }
-    wave_append(count, list, listed, v);
   }
 }
 
@@ -2620,27 +2668,55 @@ __global__ void __launch_bounds__(256) k_mark_heavy(const int *__restrict__ nhea
 // the row and hub tiers (skip[v] = 0 for exactly them).
 // touch[mvc[v]] is set for every dirty v: its cached block may lose members;
 // the dirty vertices are listed in dlist (count at cnt[4]).
-__global__ void k_update_flags(int n, const unsigned char *__restrict__ edited, const unsigned char *__restrict__ flag,
-                               unsigned char *__restrict__ dirty, unsigned char *__restrict__ skip,
-                               const int64_t *__restrict__ row_ptr, int *cnt, int *small, int *large,
-                               const int32_t *__restrict__ mvc, unsigned char *__restrict__ touch, int *dlist) {
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool act = v < n;
-  bool prop = false;
-  int64_t d = 0;
-  if (act) {
-    const bool ed = edited[v] != 0, fl = flag[v] != 0;
-    dirty[v] = (ed || fl) ? 1 : 0;
-    if (ed || fl) touch[mvc[v]] = 1;
-    prop = fl && !ed;
-    if (prop) d = row_ptr[v + 1] - row_ptr[v];
-    skip[v] = (prop && d > LIST_BIG) ? 0 : 1;
+constexpr int FLAGS_GROUP = 16;  // vertices per thread in k_update_flags
+__global__ void __launch_bounds__(256) k_update_flags(int n, const unsigned char *__restrict__ edited,
+                                                      const unsigned char *__restrict__ flag,
+                                                      unsigned char *__restrict__ dirty,
+                                                      unsigned char *__restrict__ skip,
+                                                      const int64_t *__restrict__ row_ptr, int *cnt, int *small,
+                                                      int *large, const int32_t *__restrict__ mvc,
+                                                      unsigned char *__restrict__ touch, int *dlist) {
+  // FLAGS_GROUP vertices per thread.  Most groups are clean (no byte set in
+  // either input): one 16-byte load of each and one 16-byte store of each
+  // output.  A wave with a vertex to list takes them one by one (the lists are
+  // appended to wave-wide, so every lane of such a wave walks its group).
+  const int64_t v0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * FLAGS_GROUP;
+  const bool vec = ((reinterpret_cast<uintptr_t>(edited) | reinterpret_cast<uintptr_t>(flag) |
+                     reinterpret_cast<uintptr_t>(dirty) | reinterpret_cast<uintptr_t>(skip)) & 15) == 0;
+  bool slow = false;
+  if (vec && v0 + FLAGS_GROUP <= n) {
+    const u32x4 e = *reinterpret_cast<const u32x4 *>(edited + v0);
+    const u32x4 f = *reinterpret_cast<const u32x4 *>(flag + v0);
+    const u32x4 o = e | f;
+    slow = (o.x | o.y | o.z | o.w) != 0;
+    if (!slow) {
+      *reinterpret_cast<u32x4 *>(dirty + v0) = u32x4{0u, 0u, 0u, 0u};
+      *reinterpret_cast<u32x4 *>(skip + v0) = u32x4{0x01010101u, 0x01010101u, 0x01010101u, 0x01010101u};
+    }
+  } else {
+    slow = v0 < n;
   }
-  wave_append(&cnt[0], small, prop && d <= LIST_SMALL, v);
-  wave_append(&cnt[1], large, prop && d > LIST_SMALL && d <= LIST_BIG, v);
-  wave_append(&cnt[4], dlist, act && dirty[v], v);
-  const u64 big = __ballot(prop && d > LIST_BIG);
-  if ((threadIdx.x & (WAVE - 1)) == 0 && big) atomicAdd(&cnt[2], (int)__popcll(big));
+  if (!__ballot(slow)) return;
+  for (int j = 0; j < FLAGS_GROUP; ++j) {
+    const int v = (int)(v0 + j);
+    const bool act = slow && v0 + j < n;
+    bool prop = false, dv = false;
+    int64_t d = 0;
+    if (act) {
+      const bool ed = edited[v] != 0, fl = flag[v] != 0;
+      dv = ed || fl;
+      dirty[v] = dv ? 1 : 0;
+      if (dv) touch[mvc[v]] = 1;
+      prop = fl && !ed;
+      if (prop) d = row_ptr[v + 1] - row_ptr[v];
+      skip[v] = (prop && d > LIST_BIG) ? 0 : 1;
+    }
+    wave_append(&cnt[0], small, prop && d <= LIST_SMALL, v);
+    wave_append(&cnt[1], large, prop && d > LIST_SMALL && d <= LIST_BIG, v);
+    wave_append(&cnt[4], dlist, dv, v);
+    const u64 big = __ballot(prop && d > LIST_BIG);
+    if ((threadIdx.x & (WAVE - 1)) == 0 && big) atomicAdd(&cnt[2], (int)__popcll(big));
+  }
 }
 
 // Skip flags when every flagged unedited vertex goes to the tier kernels.
@@ -2708,6 +2784,19 @@ __global__ void k_copy_i32(int *dst, const int *src, int64_t cnt) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x)
     dst[i] = src[i];
 }
+// One source copied to up to MAX destinations (read once).
+struct CopyDsts {
+  static constexpr int MAX = 16;
+  int32_t *d[MAX];
+  int nd;
+};
+__global__ void k_copy_multi(CopyDsts dst, const int32_t *__restrict__ src, int64_t cnt) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t v = src[i];
+    for (int q = 0; q < dst.nd; ++q) dst.d[q][i] = v;
+  }
+}
+
 // Streaming copy, 16 bytes per thread per step (bandwidth probe).
 __global__ void k_copy16(uint4 *__restrict__ dst, const uint4 *__restrict__ src, int64_t n16) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (int64_t)gridDim.x * blockDim.x)

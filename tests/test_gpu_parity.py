@@ -389,6 +389,31 @@ def test_invalid_graphs_rejected():
     r.close()
 
 
+def test_range_checks_at_every_alignment():
+    """Targets and labels are range-checked 16 bytes at a time over the aligned body of the
+    array and one by one before and after it: a bad value is found in the head, the body and
+    the tail, for arrays starting at each 4-byte offset and for arrays shorter than one group."""
+    kb = _kb()
+    for n, m in [(50, 1), (50, 3), (60, 7), (300, 4099)]:
+        g = graphgen.tiny(seed=11, n=n, m=m)
+        rp, col, el, vl, _ = kb.to_device(g)
+        for off in range(4):
+            cbuf = torch.zeros(g.m + off + 3, dtype=torch.int32, device=rp.device)
+            ebuf = torch.zeros_like(cbuf)
+            c, e = cbuf[off:off + g.m], ebuf[off:off + g.m]
+            c.copy_(col)
+            e.copy_(el)
+            kb.Refiner(rp, c, e, vl, kmax=1).close()     # clean arrays pass
+            for pos in sorted({0, 1, 2, 3, g.m // 2, g.m - 2, g.m - 1} & set(range(g.m))):
+                for arr, bad in [(c, g.n), (c, -1), (e, -1)]:
+                    old = arr[pos].item()
+                    arr[pos] = bad
+                    with pytest.raises(kb.KbisimError) as ei:
+                        kb.Refiner(rp, c, e, vl, kmax=1)
+                    assert ei.value.code == kb.EGRAPH, (n, m, off, pos, bad)
+                    arr[pos] = old
+
+
 def test_large_sparse_label_values():
     """Labels need not be dense: values up to 2^31 - 1 (no packing, 64-bit keys) and a mix of
     small graphs where labels pack above the target ranks."""
