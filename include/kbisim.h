@@ -27,7 +27,9 @@
  *  - Graph arrays, outputs and the workspace are DEVICE pointers on the
  *    current HIP device.  Counts returned to the caller are HOST memory.
  *  - The library allocates no device memory: every buffer it uses is carved
- *    from the caller's workspace (size from kbisim_workspace_bytes).
+ *    from the caller's workspace (size from kbisim_workspace_bytes), which
+ *    must start at a 256-byte boundary (hipMalloc's and torch's allocations
+ *    do; EINVAL otherwise).
  *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
  *    work is enqueued on it.  A context is bound to one stream and is not
  *    thread-safe; separate contexts are independent.

@@ -62,7 +62,7 @@ struct Plan {
   size_t off_H, off_DC, off_rep, off_p0, off_vlist, off_clA, off_clB, off_ranges, off_lists, off_gcol, off_rank,
       off_gpid, off_zrep;
   size_t off_table, off_ctable, off_hacc, off_hcnt, off_chunks, off_parts, off_gchunks, off_poff;
-  size_t off_status, off_counters, off_dcounts, off_err, off_dep, off_hubsets, off_single, off_multi, off_nzv;
+  size_t off_status, off_hw, off_counters, off_dcounts, off_err, off_dep, off_hubsets, off_single, off_multi, off_nzv;
   size_t off_gid, off_ibuf, off_first, off_next, off_bcounts;  // batches only
   uint64_t tslots;
   int64_t max_ranges, max_lists, nhub_max, nchunk_max, npart_max, ngchunk_max, npoff_max, ntiles, hubset_slots;
@@ -118,6 +118,7 @@ Plan make_plan(int64_t n, int64_t m, int64_t nl, int kmax, int64_t num_graphs) {
   p.off_gchunks = take(sizeof(HubGChunk) * (size_t)p.ngchunk_max);
   p.off_poff = take(4 * (size_t)p.npoff_max);
   p.off_status = take(4 * (size_t)p.ntiles);
+  p.off_hw = take(sizeof(HeadWord) * (N / 64 + 1));
   p.off_counters = take(4 * (size_t)CNT_STRIDE * (size_t)p.ncounter_steps);
   p.off_dcounts = take(8 * (size_t)p.ncounter_steps);
   p.off_err = take(16);
@@ -185,6 +186,7 @@ struct kbisim_ctx {
   char *ws;
   u64 *H, *table, *ctable, *hacc, *hubsets, *zrep;
   u32 *DC, *hcnt, *err, *tiles, *dep;
+  HeadWord *hw;
   int *rep, *p0, *vlist, *clA, *clB, *lists, *counters, *poff, *gcol, *rank, *gpid[2], *nzv;
   int64_t *dcounts;
   Range *ranges;
@@ -400,6 +402,21 @@ int numbering_scan(kbisim_ctx *c, int n, int *out, int64_t *count_dev) {
   if (items == 8) k_scan_write<8><<<(unsigned)ntiles, 256, 0, c->stream>>>(n, c->rep, c->tiles, out, aligned);
   else k_scan_write<16><<<(unsigned)ntiles, 256, 0, c->stream>>>(n, c->rep, c->tiles, out, aligned);
   LAUNCH_CHECK();
+  return 0;
+}
+
+// A step's numbering: head words and the tile prefixes of the heads in
+// vertex order (k_head_words, k_tile_scan); the block count to count_dev.
+// The assign kernels then read every vertex's dense id through the result.
+int numbering_words(kbisim_ctx *c, int n, int64_t *count_dev, HeadIds *ids) {
+  const int items = c->tune.scan_items;
+  const int ntiles = (int)blocks_for(n, 256 * items);
+  if (items == 8) k_head_words<8><<<(unsigned)ntiles, 256, 0, c->stream>>>(n, c->rep, c->hw, c->tiles);
+  else k_head_words<16><<<(unsigned)ntiles, 256, 0, c->stream>>>(n, c->rep, c->hw, c->tiles);
+  LAUNCH_CHECK();
+  k_tile_scan<<<1, 1024, 0, c->stream>>>(ntiles, c->tiles, count_dev);
+  LAUNCH_CHECK();
+  *ids = HeadIds{c->hw, c->tiles, items == 8 ? 11 : 12};
   return 0;
 }
 
@@ -1123,18 +1140,19 @@ int run_step(kbisim_ctx *c, const Src &src, const Schedule &s, int *out, int64_t
     LAUNCH_CHECK();
   }
   if ((rc = settle_collisions(c, src, s, cnt, careful))) return rc;
+  HeadIds ids{};
   {
     ProfScope ps(c, KBISIM_K_SCAN);
-    if ((rc = numbering_scan(c, n, out, count_dev))) return rc;
+    if ((rc = numbering_words(c, n, count_dev, &ids))) return rc;
   }
   {
     ProfScope ps(c, KBISIM_K_ASSIGN);
     if (names_out) {
-      k_assign_names<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, c->rep, out, names_out,
+      k_assign_names<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, c->rep, ids, out, names_out,
                                                                 gpid_next ? c->rank : nullptr, gpid_next, nullptr,
                                                                 nullptr, nullptr, nullptr, nullptr);
     } else {
-      k_assign<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, c->rep, out, gpid_next ? c->rank : nullptr, gpid_next,
+      k_assign<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, c->rep, ids, out, gpid_next ? c->rank : nullptr, gpid_next,
                                                           single_out ? c->multi : nullptr, c->dep);
     }
     LAUNCH_CHECK();
@@ -1507,10 +1525,11 @@ int update_step(kbisim_ctx *c, const TierSrc &tsrc, const ListSrc &lsrc, int i, 
     LAUNCH_CHECK();
   }
   if ((rc = settle_collisions(c, lsrc, s, cnt, true))) return rc;
-  if ((rc = numbering_scan(c, n, out, count_dev))) return rc;
+  HeadIds ids{};
+  if ((rc = numbering_words(c, n, count_dev, &ids))) return rc;
   if ((rc = fill_i32(c, reinterpret_cast<int *>(S.claimed), (n + 3) / 4, 0))) return rc;
   if (prop_lists) {
-    k_assign_out<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, c->rep, out);
+    k_assign_out<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, c->rep, ids, out);
     LAUNCH_CHECK();
     if (nlk) {
       const unsigned g = blocks_for(nlk, 256);
@@ -1518,8 +1537,8 @@ int update_step(kbisim_ctx *c, const TierSrc &tsrc, const ListSrc &lsrc, int i, 
       k_block_names_clean<<<g, 256, 0, c->stream>>>(n, c->rep, S.dirty, S.MVc + at, S.bname, S.claimed, nlk, S.lk);
       k_block_names_keep<<<g, 256, 0, c->stream>>>(n, c->rep, S.dirty, S.MVc + at, S.bname, S.claimed, S.keep, nlk,
                                                    S.lk);
-      k_assign_names<<<g, 256, 0, c->stream>>>(n, c->rep, nullptr, S.names[i & 1], nullptr, nullptr, S.bname, S.keep,
-                                               S.MVc + at, &cnt[6], S.changed, nlk, S.lk);
+      k_assign_names<<<g, 256, 0, c->stream>>>(n, c->rep, ids, nullptr, S.names[i & 1], nullptr, nullptr, S.bname,
+                                               S.keep, S.MVc + at, &cnt[6], S.changed, nlk, S.lk);
       LAUNCH_CHECK();
     }
     *gpid_written = false;
@@ -1529,7 +1548,7 @@ int update_step(kbisim_ctx *c, const TierSrc &tsrc, const ListSrc &lsrc, int i, 
                                                                     S.claimed);
     k_block_names_keep<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, c->rep, S.dirty, S.MVc + at, S.bname,
                                                                    S.claimed, S.keep);
-    k_assign_names<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, c->rep, out, S.names[i & 1], c->rank,
+    k_assign_names<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, c->rep, ids, out, S.names[i & 1], c->rank,
                                                               c->gpid[(i + 1) & 1], S.bname, S.keep, S.MVc + at,
                                                               &cnt[6], S.changed);
     LAUNCH_CHECK();
@@ -1869,7 +1888,7 @@ int create_impl(const kbisim_graph *g, int kmax, const kbisim_tuning *tuning, vo
   }
   const int64_t nl = g->vlabel_ptr ? g->nlabels : 0;
   Plan plan = make_plan(n, m, nl, kmax, num_graphs);
-  if (!workspace) return KBISIM_EINVAL;
+  if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & (ALIGN - 1))) return KBISIM_EINVAL;
   if (ws_bytes < plan.total) return KBISIM_ENOSPACE;
 
   kbisim_ctx *c = new (std::nothrow) kbisim_ctx();
@@ -1900,6 +1919,7 @@ int create_impl(const kbisim_graph *g, int kmax, const kbisim_tuning *tuning, vo
   c->gchunks = (HubGChunk *)(w + plan.off_gchunks);
   c->poff = (int *)(w + plan.off_poff);
   c->tiles = (u32 *)(w + plan.off_status);
+  c->hw = (HeadWord *)(w + plan.off_hw);
   c->gcol = (int *)(w + plan.off_gcol);
   c->rank = (int *)(w + plan.off_rank);
   c->gpid[0] = (int *)(w + plan.off_gpid);

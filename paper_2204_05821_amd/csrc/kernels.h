@@ -1364,7 +1364,7 @@ __global__ void __launch_bounds__(256) k_res_verify(Src src, const int *__restri
 // 256 * ITEMS vertices, ITEMS = 8 or 16 per thread): per-tile head counts, one workgroup scans the tile
 // counts, then every tile numbers its heads.  A head's exclusive prefix is its
 // dense id, so blocks are numbered by their first vertex.  Non-heads get -1
-// here and their representative's id in k_assign.
+// (k_scan_write lists the heads; the steps number through head words).
 template <int ITEMS>
 __device__ inline u32 tile_flags(int n, const int *__restrict__ rep, int64_t base) {
   int r[ITEMS];
@@ -1466,6 +1466,49 @@ __global__ void __launch_bounds__(256) k_scan_write(int n, const int *__restrict
   }
 }
 
+// Head words: the numbering of a step without the scattered write of every
+// head's id.  Word w holds one bit per vertex 64w..64w+63 (set for a head,
+// rep[v] == v) and the number of heads before the word in its tile (tiles of
+// 256 * ITEMS vertices, as k_tile_count; the tile counts go to tile_sum for
+// k_tile_scan).  A vertex then reads its dense id from its representative's
+// word: tile prefix + word prefix + heads below it in the word.  The words
+// (n / 4 bytes) and tile prefixes stay in the caches, unlike a gather of
+// every representative's id from the output (n * 4 bytes).
+struct HeadWord {
+  u64 bits;
+  u32 pre;
+  u32 pad;
+};
+struct HeadIds {
+  const HeadWord *hw;
+  const u32 *tile_pre;  // exclusive prefix of head counts per tile
+  int tile_shift;       // log2 of the tile's vertex count
+};
+__device__ inline int head_id(const HeadIds &h, int r) {
+  const u32x4 q = *reinterpret_cast<const u32x4 *>(&h.hw[r >> 6]);
+  const u64 bits = (u64)q.x | ((u64)q.y << 32);
+  const u64 below = bits & ((1ull << (r & 63)) - 1ull);
+  return (int)(h.tile_pre[r >> h.tile_shift] + q.z + (u32)__popcll(below));
+}
+
+template <int ITEMS>
+__global__ void __launch_bounds__(256) k_head_words(int n, const int *__restrict__ rep, HeadWord *__restrict__ hw,
+                                                    u32 *__restrict__ tile_sum) {
+  static_assert(64 % ITEMS == 0, "a word spans whole threads");
+  constexpr int TPW = 64 / ITEMS;  // threads per word (consecutive lanes of one wave)
+  __shared__ u32 sh_w[4];
+  const int64_t base = (int64_t)blockIdx.x * (256 * ITEMS) + (int64_t)threadIdx.x * ITEMS;
+  const u32 bits = tile_flags<ITEMS>(n, rep, base);
+  u32 total;
+  const u32 pre = block_exclusive_scan(__popc(bits), sh_w, &total);
+  u64 word = 0;
+#pragma unroll
+  for (int q = 0; q < TPW; ++q) word |= (u64)__shfl_down(bits, q, WAVE) << (q * ITEMS);
+  if ((threadIdx.x % TPW) == 0 && base < n)
+    *reinterpret_cast<u32x4 *>(&hw[base >> 6]) = u32x4{(u32)word, (u32)(word >> 32), pre, 0u};
+  if (threadIdx.x == 0) tile_sum[blockIdx.x] = total;
+}
+
 // rep[v] = v for vertices with at least one entry, else -1 (heads of the
 // numbering scan, which then lists them in order).
 __global__ void k_mark_rows(int n, const int64_t *__restrict__ row_ptr, int *__restrict__ rep) {
@@ -1479,22 +1522,20 @@ __global__ void k_list_from_ids(int n, const int *__restrict__ pos, int *__restr
   if (v < n && pos[v] >= 0) list[pos[v]] = v;
 }
 
-// Every non-head copies its representative's id (written by k_scan_write),
-// and the new partition is also written in rank order for the next gather
-// (vertices no entry names have rank -1 and are left out).
+// Every vertex takes its representative's dense id (head words), and the
+// new partition is also written in rank order for the next gather (vertices
+// no entry names have rank -1 and are left out).
 // Work-efficient mode (multi != NULL): every non-head marks its head with the
 // step's stamp, so a head left unmarked is a singleton block (k_singletons).
-__global__ void k_assign(int n, const int *__restrict__ rep, int *out, const int *__restrict__ rank,
-                         int *__restrict__ gpid_next, u32 *multi, const u32 *__restrict__ dep) {
+__global__ void k_assign(int n, const int *__restrict__ rep, HeadIds ids, int *__restrict__ out,
+                         const int *__restrict__ rank, int *__restrict__ gpid_next, u32 *multi,
+                         const u32 *__restrict__ dep) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
   const int r = rep[v];
-  int val = out[v];
-  if (r != v) {
-    val = r >= 0 ? out[r] : -1;
-    out[v] = val;
-    if (multi && r >= 0) multi[r] = dep[EP_ZERO];
-  }
+  const int val = r >= 0 ? head_id(ids, r) : -1;
+  out[v] = val;
+  if (multi && r >= 0 && r != v) multi[r] = dep[EP_ZERO];
   if (rank) {
     const int rk = rank[v];
     if (rk >= 0) gpid_next[rk] = val;
@@ -2385,14 +2426,14 @@ __global__ void __launch_bounds__(256) k_insert_cached(int n, const unsigned cha
   zero_insert_wave(zrep, zero, own, (u32)v, zep);
 }
 
-// Every vertex: dense id from its representative (k_scan_write left the
-// heads' ids), its new block name in vertex order and, for the next gather,
-// in rank order.  The name is the representative (the block's minimum
+// Every vertex: dense id from its representative (head words), its new
+// block name in vertex order and, for the next gather, in rank order.  The name is the representative (the block's minimum
 // vertex), or with bname (an update) the name bname[] gives the
 // representative's block; vertices whose name differs from the cached
 // chain's (old_names) are then listed in changed[].
 // list != NULL: only the `count` listed vertices (out may then be NULL).
-__global__ void k_assign_names(int n, const int *__restrict__ rep, int *out, int32_t *__restrict__ names_out,
+__global__ void k_assign_names(int n, const int *__restrict__ rep, HeadIds ids, int *__restrict__ out,
+                               int32_t *__restrict__ names_out,
                                const int *__restrict__ rank, int *__restrict__ gpid_next,
                                const int32_t *__restrict__ bname, const int32_t *__restrict__ keep,
                                const int32_t *__restrict__ old_names, int *nchanged, int *changed,
@@ -2403,7 +2444,7 @@ __global__ void k_assign_names(int n, const int *__restrict__ rep, int *out, int
   bool moved = false;
   if (act) {
     const int r = rep[v];
-    if (out && r != v) out[v] = r >= 0 ? out[r] : -1;
+    if (out) out[v] = r >= 0 ? head_id(ids, r) : -1;
     int nm = r;
     if (bname) {
       nm = r >= 0 ? bname[r] : -1;
@@ -2557,12 +2598,12 @@ __global__ void k_row_degrees(int count, const int *__restrict__ list, const int
   deg[i] = row_ptr[v + 1] - row_ptr[v];
 }
 
-// Dense ids of the vertices that are not heads: the id of their representative.
-__global__ void k_assign_out(int n, const int *__restrict__ rep, int *out) {
+// Dense id of every vertex: its representative's (head words).
+__global__ void k_assign_out(int n, const int *__restrict__ rep, HeadIds ids, int *__restrict__ out) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
   const int r = rep[v];
-  if (r != v) out[v] = r >= 0 ? out[r] : -1;
+  out[v] = r >= 0 ? head_id(ids, r) : -1;
 }
 
 // Block names of an update step.  A new block that keeps an unchanged

@@ -389,6 +389,27 @@ def test_invalid_graphs_rejected():
     r.close()
 
 
+def test_workspace_alignment():
+    """The workspace must start at a 256-byte boundary: an offset one is refused with EINVAL,
+    a caller-given aligned one gives the same partitions as the library-sized default."""
+    kb = _kb()
+    g = graphgen.tiny(seed=4, n=500, m=3000)
+    d = kb.to_device(g)
+    ref = kb.Refiner(*d, kmax=3)
+    ids, counts = ref.refine(3)
+    nbytes = ref.workspace_bytes
+    ref.close()
+    buf = torch.empty(nbytes + 512, dtype=torch.uint8, device=d[0].device)
+    for off in (1, 8, 128):
+        with pytest.raises(kb.KbisimError) as ei:
+            kb.Refiner(*d, kmax=3, workspace=buf[off:])
+        assert ei.value.code == kb.EINVAL
+    r = kb.Refiner(*d, kmax=3, workspace=buf[256:])
+    ids2, counts2 = r.refine(3)
+    assert counts2 == counts and all(bool((a == b).all()) for a, b in zip(ids, ids2))
+    r.close()
+
+
 def test_range_checks_at_every_alignment():
     """Targets and labels are range-checked 16 bytes at a time over the aligned body of the
     array and one by one before and after it: a bad value is found in the head, the body and
