@@ -681,7 +681,7 @@ def main():
                          "calibration) and print its rate")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU; a multi-GPU figure is not produced "
+        print("bench.py: the refinement of one graph runs on one GPU; no multi-GPU figure is produced "
               "(the sharding design is described in the design notes).", file=sys.stderr)
         sys.exit(2)
 
