@@ -345,8 +345,9 @@ int kbisim_destroy(kbisim_ctx *c);
  *
  * Bytes of the caller buffer that holds the cached chain of a graph of
  * g->n vertices and g->m edges for up to kmax steps: per step a key hash, a
- * distinct count and a block name per vertex (16 bytes), the graph's in-rows
- * (8 (n+1) + 4 m) and scratch; about 16 kmax n + 4 m + 75 n bytes.  Host
+ * distinct count, a block name and a filter bit index per vertex (18
+ * bytes), the graph's in-rows (8 (n+1) + 4 m) and scratch; about
+ * 18 kmax n + 4 m + 75 n bytes.  Host
  * only.  Errors: EINVAL (null, kmax < 1), ERANGE.                           */
 int kbisim_incr_state_bytes(const kbisim_graph *g, int kmax, size_t *bytes);
 

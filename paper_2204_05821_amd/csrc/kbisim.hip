@@ -238,6 +238,7 @@ struct kbisim_ctx {
     u64 *Hc;
     u32 *DCc;
     int32_t *MVc;
+    uint16_t *FKc;  // filter bit of each vertex's cached key, per step
     int64_t *tptr;
     int32_t *tcol;
     int32_t *names[2];
@@ -247,7 +248,7 @@ struct kbisim_ctx {
     int32_t *keep;    // cached names kept by blocks of changed vertices, by representative
     unsigned char *claimed;  // cached names taken by blocks with an unchanged member
     int *heavy;       // changed vertices with long in-rows
-    unsigned char *touch;  // cached blocks (by minimum vertex) that can change in this step
+    u32 *touch;  // bitmap of the cached blocks (by minimum vertex) that can change in this step
     int *lk;               // the dirty vertices, then these and the clean members of touched blocks
     u32 *filter;           // bit filter of the dirty keys
     // edited rows longer than LIST_BIG: one global set each (chunks of HUB_GCHUNK)
@@ -1152,8 +1153,8 @@ int run_step(kbisim_ctx *c, const Src &src, const Schedule &s, int *out, int64_t
                                                                 gpid_next ? c->rank : nullptr, gpid_next, nullptr,
                                                                 nullptr, nullptr, nullptr, nullptr);
     } else {
-      k_assign<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, c->rep, ids, out, gpid_next ? c->rank : nullptr, gpid_next,
-                                                          single_out ? c->multi : nullptr, c->dep);
+      k_assign<<<blocks_for((n + ASSIGN_V - 1) / ASSIGN_V, 256), 256, 0, c->stream>>>(
+          n, c->rep, ids, out, gpid_next ? c->rank : nullptr, gpid_next, single_out ? c->multi : nullptr, c->dep);
     }
     LAUNCH_CHECK();
     if (single_out) {
@@ -1218,6 +1219,8 @@ int enqueue_steps(kbisim_ctx *c, const int32_t *prev, int i0, int k, int32_t *co
                                            reinterpret_cast<const int *>(c->H), 2 * (int64_t)n);
       k_copy_i32<<<g, 256, 0, c->stream>>>(reinterpret_cast<int *>(c->is.DCc + (size_t)i * (size_t)n),
                                            reinterpret_cast<const int *>(c->DC), (int64_t)n);
+      k_filter_keys<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, c->H, c->DC, prev,
+                                                                c->is.FKc + (size_t)i * (size_t)n);
       LAUNCH_CHECK();
       prev = names_out;
     } else {
@@ -1372,7 +1375,7 @@ int refine_impl(kbisim_ctx *c, const int32_t *start, int k, int32_t *const *out,
 // the cached graph (to find the vertices whose targets' names changed) and
 // per-update scratch.
 struct IncrPlan {
-  size_t off_hc, off_dcc, off_mvc, off_tptr, off_tcol, off_names, off_edited, off_flag, off_dirty, off_skip,
+  size_t off_hc, off_dcc, off_mvc, off_fk, off_tptr, off_tcol, off_names, off_edited, off_flag, off_dirty, off_skip,
       off_small, off_large, off_psmall, off_plarge, off_changed, off_bname, off_keep, off_claimed, off_heavy, off_touch,
       off_lk, off_filter, off_zrep, off_huge, off_hchunks, off_hacc, off_hcnt, off_cnt, total;
   int64_t huge_cap, huge_chunk_cap;
@@ -1389,6 +1392,7 @@ IncrPlan incr_plan(int64_t n, int64_t m, int kmax) {
   p.off_hc = take(8 * N * K);
   p.off_dcc = take(4 * N * K);
   p.off_mvc = take(4 * N * K);
+  p.off_fk = take(2 * N * K);
   p.off_tptr = take(8 * (N + 1));
   p.off_tcol = take(4 * (size_t)std::max<int64_t>(m, 1));
   p.off_names = take(8 * N);
@@ -1405,7 +1409,7 @@ IncrPlan incr_plan(int64_t n, int64_t m, int kmax) {
   p.off_keep = take(4 * N);
   p.off_claimed = take(N);
   p.off_heavy = take(4 * N);
-  p.off_touch = take(N);
+  p.off_touch = take(4 * (N / 32 + 1));
   p.off_lk = take(4 * N);
   p.off_filter = take(4 * FILTER_WORDS);
   p.off_zrep = take(16 * N);
@@ -1492,12 +1496,12 @@ int update_step(kbisim_ctx *c, const TierSrc &tsrc, const ListSrc &lsrc, int i, 
     if (ndirty > 0) {
       // the dirty vertices were listed by k_update_flags (count at cnt[12])
       k_build_filter<<<blocks_for(ndirty, 256), 256, 0, c->stream>>>(&cnt[12], S.lk, c->H, c->DC, names_prev,
-                                                                      S.filter);
+                                                                      S.MVc + at, S.filter);
       LAUNCH_CHECK();
     }
     k_classify<<<(unsigned)std::min<int64_t>(CLASSIFY_GRID, blocks_for(n, 256)), 256, 0, c->stream>>>(
-        n, S.MVc + at, S.dirty, S.touch, S.Hc + at, S.DCc + at, names_prev, S.filter, c->table, tmask, c->dep, c->zrep,
-        c->H, c->DC, c->rep, S.names[i & 1], &cnt[11], S.lk);
+        n, S.MVc + at, S.dirty, S.touch, S.FKc + at, S.Hc + at, S.DCc + at, names_prev, S.filter, c->table, tmask,
+        c->dep, c->zrep, c->H, c->DC, c->rep, S.names[i & 1], &cnt[11], S.lk);
     LAUNCH_CHECK();
     HIP_TRY(hipMemcpyAsync(&nlk, &cnt[11], sizeof nlk, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
@@ -1529,7 +1533,7 @@ int update_step(kbisim_ctx *c, const TierSrc &tsrc, const ListSrc &lsrc, int i, 
   if ((rc = numbering_words(c, n, count_dev, &ids))) return rc;
   if ((rc = fill_i32(c, reinterpret_cast<int *>(S.claimed), (n + 3) / 4, 0))) return rc;
   if (prop_lists) {
-    k_assign_out<<<blocks_for(n, 256), 256, 0, c->stream>>>(n, c->rep, ids, out);
+    k_assign_out<<<blocks_for((n + ASSIGN_V - 1) / ASSIGN_V, 256), 256, 0, c->stream>>>(n, c->rep, ids, out);
     LAUNCH_CHECK();
     if (nlk) {
       const unsigned g = blocks_for(nlk, 256);
@@ -1593,7 +1597,7 @@ int update_steps_t(kbisim_ctx *c, const kbisim_graph *gn, int k, int32_t *const 
     const int32_t *names_prev = i == 0 ? c->p0 : S.names[(i - 1) & 1];
     int *cnt = c->counters + CNT_STRIDE * i;
     if ((rc = fill_i32(c, cnt, CNT_STRIDE, 0))) return rc;
-    if ((rc = fill_i32(c, reinterpret_cast<int *>(S.touch), (n + 3) / 4, 0))) return rc;
+    if ((rc = fill_i32(c, reinterpret_cast<int *>(S.touch), (n + 31) / 32, 0))) return rc;
     k_update_flags<<<blocks_for((n + FLAGS_GROUP - 1) / FLAGS_GROUP, 256), 256, 0, c->stream>>>(
         n, S.edited, S.flag, S.dirty, S.skip, gn->row_ptr, cnt + 8, S.psmall, S.plarge, S.MVc + (size_t)i * n, S.touch,
         S.lk);
@@ -1761,6 +1765,7 @@ int incr_enable_impl(kbisim_ctx *c, void *state, size_t bytes) {
   S.Hc = (u64 *)(w + p.off_hc);
   S.DCc = (u32 *)(w + p.off_dcc);
   S.MVc = (int32_t *)(w + p.off_mvc);
+  S.FKc = (uint16_t *)(w + p.off_fk);
   S.tptr = (int64_t *)(w + p.off_tptr);
   S.tcol = (int32_t *)(w + p.off_tcol);
   S.names[0] = (int32_t *)(w + p.off_names);
@@ -1778,7 +1783,7 @@ int incr_enable_impl(kbisim_ctx *c, void *state, size_t bytes) {
   S.keep = (int32_t *)(w + p.off_keep);
   S.claimed = (unsigned char *)(w + p.off_claimed);
   S.heavy = (int *)(w + p.off_heavy);
-  S.touch = (unsigned char *)(w + p.off_touch);
+  S.touch = (u32 *)(w + p.off_touch);
   S.lk = (int *)(w + p.off_lk);
   S.filter = (u32 *)(w + p.off_filter);
   S.huge = (int *)(w + p.off_huge);

@@ -1527,18 +1527,46 @@ __global__ void k_list_from_ids(int n, const int *__restrict__ pos, int *__restr
 // no entry names have rank -1 and are left out).
 // Work-efficient mode (multi != NULL): every non-head marks its head with the
 // step's stamp, so a head left unmarked is a singleton block (k_singletons).
-__global__ void k_assign(int n, const int *__restrict__ rep, HeadIds ids, int *__restrict__ out,
-                         const int *__restrict__ rank, int *__restrict__ gpid_next, u32 *multi,
-                         const u32 *__restrict__ dep) {
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= n) return;
-  const int r = rep[v];
-  const int val = r >= 0 ? head_id(ids, r) : -1;
-  out[v] = val;
-  if (multi && r >= 0 && r != v) multi[r] = dep[EP_ZERO];
-  if (rank) {
-    const int rk = rank[v];
-    if (rk >= 0) gpid_next[rk] = val;
+// ASSIGN_V consecutive vertices per thread: representatives, ranks and ids
+// move 16 bytes at a time where the arrays' starts allow.
+constexpr int ASSIGN_V = 4;
+__global__ void __launch_bounds__(256) k_assign(int n, const int *__restrict__ rep, HeadIds ids,
+                                                int *__restrict__ out, const int *__restrict__ rank,
+                                                int *__restrict__ gpid_next, u32 *multi,
+                                                const u32 *__restrict__ dep) {
+  const int64_t v0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * ASSIGN_V;
+  if (v0 >= n) return;
+  const bool vec = v0 + ASSIGN_V <= n && ((reinterpret_cast<uintptr_t>(rep) | reinterpret_cast<uintptr_t>(out) |
+                                           reinterpret_cast<uintptr_t>(rank)) & 15) == 0;
+  int r[ASSIGN_V], rk[ASSIGN_V], val[ASSIGN_V];
+  if (vec) {
+    const int4 r4 = *reinterpret_cast<const int4 *>(rep + v0);
+    r[0] = r4.x; r[1] = r4.y; r[2] = r4.z; r[3] = r4.w;
+    if (rank) {
+      const int4 k4 = *reinterpret_cast<const int4 *>(rank + v0);
+      rk[0] = k4.x; rk[1] = k4.y; rk[2] = k4.z; rk[3] = k4.w;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < ASSIGN_V; ++j) {
+      r[j] = v0 + j < n ? rep[v0 + j] : -1;
+      if (rank) rk[j] = v0 + j < n ? rank[v0 + j] : -1;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < ASSIGN_V; ++j) val[j] = r[j] >= 0 ? head_id(ids, r[j]) : -1;
+  if (vec) {
+    *reinterpret_cast<int4 *>(out + v0) = make_int4(val[0], val[1], val[2], val[3]);
+  } else {
+#pragma unroll
+    for (int j = 0; j < ASSIGN_V; ++j)
+      if (v0 + j < n) out[v0 + j] = val[j];
+  }
+#pragma unroll
+  for (int j = 0; j < ASSIGN_V; ++j) {
+    if (v0 + j >= n) break;
+    if (multi && r[j] >= 0 && r[j] != (int)(v0 + j)) multi[r[j]] = dep[EP_ZERO];
+    if (rank && rk[j] >= 0) gpid_next[rk[j]] = val[j];
   }
 }
 
@@ -2463,7 +2491,8 @@ __global__ void k_assign_names(int n, const int *__restrict__ rep, HeadIds ids, 
 // Update steps with few dirty vertices group only the blocks that can have
 // changed.  Clean members of a cached block keep equal keys, so a cached
 // block B keeps exactly its members (and its minimum vertex and name) unless
-// it holds a dirty vertex (touch[minimum vertex], set by k_update_flags) or a
+// it holds a dirty vertex (bit "minimum vertex" of touch, set by
+// k_update_flags; a bitmap of n bits, so that its reads stay in the caches) or a
 // dirty vertex now has B's key.  The second is found by each clean vertex
 // looking its own cached key up among the dirty keys already inserted (the
 // table, or zrep for an empty signature, whose key is the own name alone):
@@ -2474,28 +2503,46 @@ __global__ void k_assign_names(int n, const int *__restrict__ rep, HeadIds ids, 
 // vertex keeps its cached block: representative and name = the cached
 // minimum vertex.
 // A bit filter of the dirty keys lets most clean vertices skip the table
-// probe: FILTER_BITS bits for key hashes (bits 36.. of the hash, as the
-// table's slot tags), as many for the names of empty signatures.  Copied to
-// LDS by every workgroup of k_classify, so the grid strides over vertices.
+// probe: one of FILTER_BITS bits per key, from bits 36.. of its hash (as the
+// table's slot tags), or for an empty signature from a multiplicative hash of
+// the own name.  The same filter holds a bit per touched block (another
+// multiplicative hash of its minimum vertex), so that most clean vertices
+// skip the touch bitmap too.  Copied to LDS by every workgroup of
+// k_classify, so the grid strides over vertices.  A clean vertex's bit is fixed by the cached chain
+// (its key hash, distinct count and previous name do not change), so it is
+// kept per step in the chain (k_filter_keys) and k_classify reads 2 bytes
+// per vertex for the test instead of the hash, count and name.
 constexpr int FILTER_BITS = 1 << 16;
-constexpr int FILTER_WORDS = 2 * FILTER_BITS / 32;
+constexpr int FILTER_WORDS = FILTER_BITS / 32;
 constexpr int CLASSIFY_GRID = 2048;
 __device__ inline u32 filter_key_bit(u64 h) { return (u32)(h >> 36) & (FILTER_BITS - 1); }
-__device__ inline u32 filter_name_bit(u32 name) { return FILTER_BITS + ((name * 0x9E3779B1u) >> 16); }
+__device__ inline u32 filter_name_bit(u32 name) { return (name * 0x9E3779B1u) >> 16; }
+__device__ inline u32 filter_touch_bit(u32 head) { return (head * 0x85EBCA6Bu) >> 16; }
+
+// Filter bit of every vertex's key at one step of a cached chain.
+__global__ void k_filter_keys(int n, const u64 *__restrict__ H, const u32 *__restrict__ DC,
+                              const int32_t *__restrict__ names_prev, uint16_t *__restrict__ fk) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  fk[v] = (uint16_t)(DC[v] ? filter_key_bit(H[v]) : filter_name_bit((u32)names_prev[v]));
+}
 
 __global__ void k_build_filter(const int *__restrict__ count, const int *__restrict__ dlist,
                                const u64 *__restrict__ H, const u32 *__restrict__ DC,
-                               const int32_t *__restrict__ names, u32 *filter) {
+                               const int32_t *__restrict__ names, const int32_t *__restrict__ mvc, u32 *filter) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= *count) return;
   const int d = dlist[i];
   const u32 b = DC[d] ? filter_key_bit(H[d]) : filter_name_bit((u32)names[d]);
   atomicOr(&filter[b >> 5], 1u << (b & 31));
+  const u32 t = filter_touch_bit((u32)mvc[d]);
+  atomicOr(&filter[t >> 5], 1u << (t & 31));
 }
 
 __global__ void __launch_bounds__(256) k_classify(int n, const int32_t *__restrict__ mvc,
                                                   const unsigned char *__restrict__ dirty,
-                                                  const unsigned char *__restrict__ touch, const u64 *__restrict__ Hc,
+                                                  const u32 *__restrict__ touch,
+                                                  const uint16_t *__restrict__ fkc, const u64 *__restrict__ Hc,
                                                   const u32 *__restrict__ DCc, const int32_t *__restrict__ names,
                                                   const u32 *__restrict__ filter, const u64 *table, u64 tmask,
                                                   const u32 *__restrict__ dep, const u64 *__restrict__ zrep,
@@ -2505,62 +2552,89 @@ __global__ void __launch_bounds__(256) k_classify(int n, const int32_t *__restri
   for (int i = threadIdx.x; i < FILTER_WORDS; i += 256) fl[i] = filter[i];
   __syncthreads();
   const u32 epoch = dep[EP_TABLE], zep = dep[EP_ZERO];
-  const int64_t stride = (int64_t)gridDim.x * 256;
-  // two vertices per thread per round, every independent load requested
-  // before any is used (the kernel waits on memory, not on arithmetic)
-  constexpr int B = 2;
-  for (int64_t base = (int64_t)blockIdx.x * 256; base < n; base += B * stride) {
-    int v[B];
-    bool act[B];
-    unsigned char dv[B];
-    int hd[B];
-    u32 dc[B];
-    u64 hv[B];
-    int32_t nm[B];
+  // CV consecutive vertices per thread and round, read and written 4 at a
+  // time when every array's start allows (a step's slice of the chain starts
+  // at step * n, so with n not a multiple of 4 they are read one by one).
+  // Every vertex first gets its
+  // cached block as representative and name; a listed vertex's are
+  // overwritten by the lookup and naming kernels of the step.  The cached key
+  // itself is read only by vertices that pass the touch or filter test.
+  constexpr int CV = 4;
+  const bool vec = ((reinterpret_cast<uintptr_t>(mvc) | reinterpret_cast<uintptr_t>(rep) |
+                     reinterpret_cast<uintptr_t>(names_out)) & 15) == 0 &&
+                   (reinterpret_cast<uintptr_t>(fkc) & 7) == 0 && (reinterpret_cast<uintptr_t>(dirty) & 3) == 0;
+  const int64_t stride = (int64_t)gridDim.x * 256 * CV;
+  for (int64_t v0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * CV; v0 < n; v0 += stride) {
+    int hd[CV];
+    u32 fk[CV], dv[CV];
+    const bool full = vec && v0 + CV <= n;
+    if (full) {
+      const u32 d4 = *reinterpret_cast<const u32 *>(dirty + v0);
+      const int4 m4 = *reinterpret_cast<const int4 *>(mvc + v0);
+      const uint2 f2 = *reinterpret_cast<const uint2 *>(fkc + v0);
+      hd[0] = m4.x; hd[1] = m4.y; hd[2] = m4.z; hd[3] = m4.w;
+      fk[0] = f2.x & 0xffffu; fk[1] = f2.x >> 16; fk[2] = f2.y & 0xffffu; fk[3] = f2.y >> 16;
 #pragma unroll
-    for (int b = 0; b < B; ++b) {
-      const int64_t x = base + b * stride + threadIdx.x;
-      act[b] = x < n;
-      v[b] = act[b] ? (int)x : 0;
-      dv[b] = act[b] ? dirty[v[b]] : 1;
-      hd[b] = act[b] ? mvc[v[b]] : 0;
-      dc[b] = act[b] ? DCc[v[b]] : 0;
-      hv[b] = act[b] ? Hc[v[b]] : 0;
-      nm[b] = act[b] ? names[v[b]] : 0;
-    }
-    unsigned char tb[B];
+      for (int j = 0; j < CV; ++j) dv[j] = (d4 >> (8 * j)) & 0xffu;
+      *reinterpret_cast<int4 *>(rep + v0) = m4;
+      *reinterpret_cast<int4 *>(names_out + v0) = m4;
+    } else {
 #pragma unroll
-    for (int b = 0; b < B; ++b) tb[b] = (act[b] && !dv[b]) ? touch[hd[b]] : 1;
-#pragma unroll
-    for (int b = 0; b < B; ++b) {
-      bool listed = false;
-      if (act[b]) {
-        if (dv[b]) {
-          listed = true;
-        } else {
-          bool hit = tb[b] != 0;
-          if (!hit) {
-            if (dc[b] == 0) {
-              const u32 fb = filter_name_bit((u32)nm[b]);
-              hit = (fl[fb >> 5] >> (fb & 31)) & 1u;
-              if (hit) hit = (u32)(zrep[(u32)nm[b]] >> 32) == ~zep;
-            } else {
-              const u32 fb = filter_key_bit(hv[b]);
-              hit = (fl[fb >> 5] >> (fb & 31)) & 1u;
-              if (hit) hit = table_lookup(table, tmask, hv[b], epoch) >= 0;
-            }
-          }
-          if (hit) {
-            H[v[b]] = hv[b];
-            DC[v[b]] = dc[b];
-            listed = true;
-          } else {
-            rep[v[b]] = hd[b];
-            names_out[v[b]] = hd[b];
-          }
+      for (int j = 0; j < CV; ++j) {
+        const bool in = v0 + j < n;
+        dv[j] = in ? dirty[v0 + j] : 1u;
+        hd[j] = in ? mvc[v0 + j] : 0;
+        fk[j] = in ? fkc[v0 + j] : 0u;
+        if (in) {
+          rep[v0 + j] = hd[j];
+          names_out[v0 + j] = hd[j];
         }
       }
-      wave_append(count, list, listed, v[b]);
+    }
+    u32 tb[CV];
+#pragma unroll
+    for (int j = 0; j < CV; ++j) {
+      // the touch bitmap is read only where the filter says "maybe touched"
+      const u32 t = filter_touch_bit((u32)hd[j]);
+      if (dv[j]) tb[j] = 1u;
+      else if ((fl[t >> 5] >> (t & 31)) & 1u) tb[j] = (touch[hd[j] >> 5] >> (hd[j] & 31)) & 1u;
+      else tb[j] = 0u;
+    }
+    // clean vertices that may share a key with a dirty one (filter hit) or
+    // belong to a touched block read their cached key; all such loads are
+    // requested before the first is used (with many dirty keys most vertices
+    // take this path)
+    bool probe[CV], need[CV];
+#pragma unroll
+    for (int j = 0; j < CV; ++j) {
+      const bool clean = v0 + j < n && !dv[j];
+      probe[j] = clean && !tb[j] && ((fl[fk[j] >> 5] >> (fk[j] & 31)) & 1u);
+      need[j] = clean && (tb[j] || probe[j]);
+    }
+    u32 dc[CV];
+    u64 hv[CV];
+#pragma unroll
+    for (int j = 0; j < CV; ++j) {
+      dc[j] = need[j] ? DCc[v0 + j] : 0u;
+      hv[j] = need[j] ? Hc[v0 + j] : 0ull;
+    }
+#pragma unroll
+    for (int j = 0; j < CV; ++j) {
+      const int v = (int)(v0 + j);
+      bool listed = v0 + j < n && dv[j];
+      if (need[j]) {
+        bool hit = !probe[j];  // touched
+        if (probe[j]) {
+          if (dc[j] == 0) hit = (u32)(zrep[(u32)names[v]] >> 32) == ~zep;
+          else hit = table_lookup(table, tmask, hv[j], epoch) >= 0;
+        }
+        if (hit) {
+          H[v] = hv[j];
+          DC[v] = dc[j];
+          listed = true;
+        }
+      }
+      wave_append(count, list, listed, v);
     }
   }
 }
@@ -2599,11 +2673,21 @@ __global__ void k_row_degrees(int count, const int *__restrict__ list, const int
 }
 
 // Dense id of every vertex: its representative's (head words).
-__global__ void k_assign_out(int n, const int *__restrict__ rep, HeadIds ids, int *__restrict__ out) {
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= n) return;
-  const int r = rep[v];
-  out[v] = r >= 0 ? head_id(ids, r) : -1;
+__global__ void __launch_bounds__(256) k_assign_out(int n, const int *__restrict__ rep, HeadIds ids,
+                                                    int *__restrict__ out) {
+  const int64_t v0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * ASSIGN_V;
+  if (v0 >= n) return;
+  if (v0 + ASSIGN_V <= n && ((reinterpret_cast<uintptr_t>(rep) | reinterpret_cast<uintptr_t>(out)) & 15) == 0) {
+    const int4 r4 = *reinterpret_cast<const int4 *>(rep + v0);
+    *reinterpret_cast<int4 *>(out + v0) =
+        make_int4(r4.x >= 0 ? head_id(ids, r4.x) : -1, r4.y >= 0 ? head_id(ids, r4.y) : -1,
+                  r4.z >= 0 ? head_id(ids, r4.z) : -1, r4.w >= 0 ? head_id(ids, r4.w) : -1);
+  } else {
+    for (int64_t v = v0; v < v0 + ASSIGN_V && v < n; ++v) {
+      const int r = rep[v];
+      out[v] = r >= 0 ? head_id(ids, r) : -1;
+    }
+  }
 }
 
 // Block names of an update step.  A new block that keeps an unchanged
@@ -2707,7 +2791,7 @@ __global__ void __launch_bounds__(256) k_mark_heavy(const int *__restrict__ nhea
 // kernels instead of the tier kernels: counts at cnt[0] (short) and cnt[1]
 // (up to LIST_BIG entries); longer rows are counted at cnt[2] and left to
 // the row and hub tiers (skip[v] = 0 for exactly them).
-// touch[mvc[v]] is set for every dirty v: its cached block may lose members;
+// Bit mvc[v] of touch is set for every dirty v: its cached block may lose members;
 // the dirty vertices are listed in dlist (count at cnt[4]).
 constexpr int FLAGS_GROUP = 16;  // vertices per thread in k_update_flags
 __global__ void __launch_bounds__(256) k_update_flags(int n, const unsigned char *__restrict__ edited,
@@ -2716,7 +2800,7 @@ __global__ void __launch_bounds__(256) k_update_flags(int n, const unsigned char
                                                       unsigned char *__restrict__ skip,
                                                       const int64_t *__restrict__ row_ptr, int *cnt, int *small,
                                                       int *large, const int32_t *__restrict__ mvc,
-                                                      unsigned char *__restrict__ touch, int *dlist) {
+                                                      u32 *__restrict__ touch, int *dlist) {
   // FLAGS_GROUP vertices per thread.  Most groups are clean (no byte set in
   // either input): one 16-byte load of each and one 16-byte store of each
   // output.  A wave with a vertex to list takes them one by one (the lists are
@@ -2747,7 +2831,10 @@ __global__ void __launch_bounds__(256) k_update_flags(int n, const unsigned char
       const bool ed = edited[v] != 0, fl = flag[v] != 0;
       dv = ed || fl;
       dirty[v] = dv ? 1 : 0;
-      if (dv) touch[mvc[v]] = 1;
+      if (dv) {
+        const int h = mvc[v];
+        atomicOr(&touch[h >> 5], 1u << (h & 31));
+      }
       prop = fl && !ed;
       if (prop) d = row_ptr[v + 1] - row_ptr[v];
       skip[v] = (prop && d > LIST_BIG) ? 0 : 1;

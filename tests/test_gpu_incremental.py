@@ -114,6 +114,10 @@ GRAPHS = {
     "rmat": lambda: graphgen.rmat(14, 200_000, seed=6),
     "rdf": lambda: graphgen.rmat_rdf(13, 90_000, seed=7, types=200, elabels=300),
     "deep": lambda: graphgen.deep(seed=8, n=20_000, avg_degree=1.3),
+    # vertex counts that are not multiples of 4: a step's slice of the cached
+    # chain starts unaligned, and the per-vertex passes take one vertex at a time
+    "odd1": lambda: graphgen.tiny(seed=15, n=4_001, m=20_000),
+    "odd2": lambda: graphgen.tiny(seed=16, n=4_094, m=30_000, elabels=60),
 }
 
 
