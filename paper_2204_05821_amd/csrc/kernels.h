@@ -2919,7 +2919,21 @@ struct CopyDsts {
   int nd;
 };
 __global__ void k_copy_multi(CopyDsts dst, const int32_t *__restrict__ src, int64_t cnt) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uintptr_t a = reinterpret_cast<uintptr_t>(src);
+  for (int q = 0; q < dst.nd; ++q) a |= reinterpret_cast<uintptr_t>(dst.d[q]);
+  int64_t done = 0;
+  if ((a & 15) == 0) {
+    // 16 bytes per thread and step where every start is 16-byte aligned
+    const int64_t n4 = cnt >> 2;
+    for (int64_t i = t; i < n4; i += stride) {
+      const int4 v = reinterpret_cast<const int4 *>(src)[i];
+      for (int q = 0; q < dst.nd; ++q) reinterpret_cast<int4 *>(dst.d[q])[i] = v;
+    }
+    done = n4 << 2;
+  }
+  for (int64_t i = done + t; i < cnt; i += stride) {
     const int32_t v = src[i];
     for (int q = 0; q < dst.nd; ++q) dst.d[q][i] = v;
   }

@@ -192,6 +192,18 @@ def test_key_width_forced_and_automatic(kbits):
         assert_same_tuned(g, 6, kb.tuning(key_bits=kbits), f"keys{kbits}-{g.name}")
 
 
+@pytest.mark.parametrize("items", [8, 16])
+def test_numbering_tiles(items):
+    """Numbering through head words with tiles of 2,048 and 4,096 vertices: vertex counts below
+    one word, below one tile, several tiles with a ragged tail, and counts that are not a
+    multiple of 4 (the assign kernels then take the tail one vertex at a time)."""
+    kb = _kb()
+    for g in [graphgen.tiny(seed=21, n=37, m=120), graphgen.tiny(seed=22, n=1_999, m=9_000),
+              graphgen.tiny(seed=23, n=12_289, m=60_000), graphgen.rmat(14, 150_000, seed=24),
+              graphgen.deep(seed=25, n=20_003, avg_degree=1.2)]:
+        assert_same_tuned(g, 5, kb.tuning(scan_items=items), f"scan{items}-{g.name}")
+
+
 @pytest.mark.parametrize("kbits", [0, 64])
 def test_device_built_schedule(kbits, monkeypatch):
     """The degree schedule built on the device (as for graphs of 16M+ vertices), forced on small
