@@ -257,6 +257,10 @@ struct kbisim_ctx {
     u64 *huge_acc;
     u32 *huge_cnt;
     int nhuge = 0, nhuge_chunks = 0;
+    // edited rows of LIST_BIG < length <= ROW_MAX (and, with 32-bit keys,
+    // <= ROW_MAX_NARROW after them): one row-kernel workgroup each
+    Range *erows;
+    int nerows8 = 0, nerows20 = 0;
     int64_t huge_set_begin = 0, huge_set_slots = 0;
     int64_t huge_cap = 0, huge_chunk_cap = 0;
     int64_t nrows = 0;  // edited rows listed by the caller
@@ -1377,7 +1381,7 @@ int refine_impl(kbisim_ctx *c, const int32_t *start, int k, int32_t *const *out,
 struct IncrPlan {
   size_t off_hc, off_dcc, off_mvc, off_fk, off_tptr, off_tcol, off_names, off_edited, off_flag, off_dirty, off_skip,
       off_small, off_large, off_psmall, off_plarge, off_changed, off_bname, off_keep, off_claimed, off_heavy, off_touch,
-      off_lk, off_filter, off_zrep, off_huge, off_hchunks, off_hacc, off_hcnt, off_cnt, total;
+      off_lk, off_filter, off_zrep, off_huge, off_hchunks, off_hacc, off_hcnt, off_erows, off_cnt, total;
   int64_t huge_cap, huge_chunk_cap;
 };
 IncrPlan incr_plan(int64_t n, int64_t m, int kmax) {
@@ -1419,6 +1423,7 @@ IncrPlan incr_plan(int64_t n, int64_t m, int kmax) {
   p.off_hchunks = take(sizeof(HubGChunk) * (size_t)p.huge_chunk_cap);
   p.off_hacc = take(8 * (size_t)p.huge_cap);
   p.off_hcnt = take(4 * (size_t)p.huge_cap);
+  p.off_erows = take(sizeof(Range) * (size_t)p.huge_cap);
   p.off_cnt = take(64);
   p.total = at;
   return p;
@@ -1477,6 +1482,18 @@ int update_step(kbisim_ctx *c, const TierSrc &tsrc, const ListSrc &lsrc, int i, 
     if ((rc = launch_signatures(c, tsrc, s, true, S.skip))) return rc;
   }
   if ((rc = lists(&S.cnt[0], S.small, S.large))) return rc;
+  if (S.nerows8) {
+    k_sig_row<ListSrc, ROW_MAX, 1024, K><<<(unsigned)S.nerows8, 1024, 0, c->stream>>>(
+        lsrc, S.erows, c->H, c->DC, c->table, tmask, c->dep, c->hmask, c->zrep, nullptr);
+    LAUNCH_CHECK();
+  }
+  if constexpr (std::is_same<K, u32>::value) {
+    if (S.nerows20) {
+      k_sig_row<ListSrc, ROW_MAX_NARROW, 1024, u32><<<(unsigned)S.nerows20, 1024, 0, c->stream>>>(
+          lsrc, S.erows + S.nerows8, c->H, c->DC, c->table, tmask, c->dep, c->hmask, c->zrep, nullptr);
+      LAUNCH_CHECK();
+    }
+  }
   if (S.nhuge) {
     // edited rows too long for one workgroup: global hash sets in the spare hub-set space
     if ((rc = fill_u64(c, c->hubsets + S.huge_set_begin, S.huge_set_slots, 0))) return rc;
@@ -1670,21 +1687,22 @@ int update_impl(kbisim_ctx *c, const kbisim_graph *gn, const int32_t *rows, int6
   if ((rc = fill_i32(c, S.cnt + 2, 1, (int)nrows))) return rc;
   S.nhuge = 0;
   S.nhuge_chunks = 0;
+  S.nerows8 = S.nerows20 = 0;
   S.nrows = nrows;
   if (nrows) {
     k_set_flags<<<std::min<unsigned>(blocks_for(nrows, 256), 65536), 256, 0, c->stream>>>(S.cnt + 2, rows, S.edited);
-    // edited rows longer than LIST_BIG take global sets when the spare hub-set
-    // space holds them (else they stay with the multi-pass list kernel)
+    // edited rows longer than LIST_BIG: a row-kernel workgroup each up to
+    // what one workgroup's LDS holds, longer ones global sets when the spare
+    // hub-set space holds them (else they stay with the multi-pass list kernel)
     const int64_t free_begin = c->sched.gset_end;
     const int64_t free_end = c->glab ? (int64_t)(reinterpret_cast<const u64 *>(c->glab) - c->hubsets)
                                      : c->plan.hubset_slots;
-    const bool room = free_end - free_begin > 2 * LIST_BIG;
+    const int64_t row_cap = c->narrow ? ROW_MAX_NARROW : ROW_MAX;
     k_split_list<<<blocks_for(nrows, 256), 256, 0, c->stream>>>((int)nrows, rows, gn->row_ptr, &S.cnt[0], S.small,
-                                                                  &S.cnt[1], S.large,
-                                                                  room ? (int64_t)LIST_BIG : (int64_t)1 << 62,
-                                                                  &S.cnt[3], S.huge);
+                                                                  &S.cnt[1], S.large, (int64_t)LIST_BIG, &S.cnt[3],
+                                                                  S.huge);
     LAUNCH_CHECK();
-    if (room) {
+    {
       int nh = 0;
       HIP_TRY(hipMemcpyAsync(&nh, &S.cnt[3], sizeof nh, hipMemcpyDeviceToHost, c->stream));
       HIP_TRY(hipStreamSynchronize(c->stream));
@@ -1700,20 +1718,31 @@ int update_impl(kbisim_ctx *c, const kbisim_graph *gn, const int32_t *rows, int6
         HIP_TRY(hipStreamSynchronize(c->stream));
         std::vector<HubGChunk> ch;
         std::vector<int> keep_list;
+        std::vector<Range> r8, r20;
         int64_t at = free_begin;
+        int nglob = 0;
         for (int i = 0; i < nh; ++i) {
-          const int64_t d = be[2 * (size_t)i + 1] - be[2 * (size_t)i];
-          if (at + 2 * d > free_end || (int64_t)ch.size() + d / HUB_GCHUNK + 1 > S.huge_chunk_cap) {
-            keep_list.push_back(hv[(size_t)i]);  // no room: back to the list kernel
+          const int v = hv[(size_t)i];
+          const int64_t b = be[2 * (size_t)i], d = be[2 * (size_t)i + 1] - b;
+          if (d <= row_cap) {
+            (d <= ROW_MAX ? r8 : r20).push_back(Range{v, v + 1, (int)d, 0, b});
             continue;
           }
-          const int idx = (int)(i - (int)keep_list.size());
+          if (at + 2 * d > free_end || (int64_t)ch.size() + d / HUB_GCHUNK + 1 > S.huge_chunk_cap) {
+            keep_list.push_back(v);  // no room: back to the list kernel
+            continue;
+          }
           for (int64_t x = 0; x < d; x += HUB_GCHUNK)
-            ch.push_back(HubGChunk{idx, 0, x, std::min<int64_t>(d, x + HUB_GCHUNK), at - free_begin, 2 * d});
-          hv[(size_t)idx] = hv[(size_t)i];
+            ch.push_back(HubGChunk{nglob, 0, x, std::min<int64_t>(d, x + HUB_GCHUNK), at - free_begin, 2 * d});
+          hv[(size_t)nglob++] = v;
           at += 2 * d;
         }
-        S.nhuge = nh - (int)keep_list.size();
+        S.nerows8 = (int)r8.size();
+        S.nerows20 = (int)r20.size();
+        r8.insert(r8.end(), r20.begin(), r20.end());
+        if (!r8.empty())
+          HIP_TRY(hipMemcpyAsync(S.erows, r8.data(), sizeof(Range) * r8.size(), hipMemcpyHostToDevice, c->stream));
+        S.nhuge = nglob;
         S.nhuge_chunks = (int)ch.size();
         S.huge_set_begin = free_begin;
         S.huge_set_slots = at - free_begin;
@@ -1790,6 +1819,7 @@ int incr_enable_impl(kbisim_ctx *c, void *state, size_t bytes) {
   S.huge_chunks = (HubGChunk *)(w + p.off_hchunks);
   S.huge_acc = (u64 *)(w + p.off_hacc);
   S.huge_cnt = (u32 *)(w + p.off_hcnt);
+  S.erows = (Range *)(w + p.off_erows);
   S.huge_cap = p.huge_cap;
   S.huge_chunk_cap = p.huge_chunk_cap;
   S.zrep = (u64 *)(w + p.off_zrep);

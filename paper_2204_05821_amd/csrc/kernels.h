@@ -2260,6 +2260,22 @@ struct PlainSrcT {
     if constexpr (HK) return hkey(pair(e));
     else return (label(e) << pb) | ((u32)names[col[e]] & pmask());
   }
+  // the row kernels' interface (as GraphSrcT, with targets in vertex order):
+  // (label, target) of entries first + min(t + u*STRIDE, count - 1)
+  template <int U, int STRIDE>
+  __device__ inline void entries(int64_t first, int t, int count, u32 (&l)[U], u32 (&r)[U]) const {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t e = first + min(t + u * STRIDE, count - 1);
+      r[u] = (u32)__builtin_nontemporal_load(&col[e]);
+      l[u] = elabel ? (u32)__builtin_nontemporal_load(&elabel[e]) : 0u;
+    }
+  }
+  __device__ inline u64 pair_of(u32 l, u32 r) const { return ((u64)l << 31) | (u64)((u32)names[r] & pmask()); }
+  __device__ inline u32 key32_of(u32 l, u32 r) const {
+    if constexpr (HK) return hkey(pair_of(l, r));
+    else return (l << pb) | ((u32)names[r] & pmask());
+  }
   __device__ inline u64 mixin(u32 q) const {
     if constexpr (HK) return (u64)q;
     else return ((u64)(q >> pb) << 31) | (u64)(q & pmask());
