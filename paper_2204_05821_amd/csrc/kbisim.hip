@@ -162,6 +162,7 @@ struct Tuning {
   int hub_parts_cap = HUB_PMAX;  // most partitions per staged hub (a smaller cap is a test knob)
   bool device_schedule = false;  // test knob: build the schedule on the device at any size
   int scan_items = SCAN_ITEMS;   // vertices per thread in the numbering scan: 8 or 16
+  int gfilter_min = GFILTER_MIN_DIRTY;  // dirty vertices from which update steps use the global filter
 };
 
 struct GraphKey {
@@ -251,6 +252,7 @@ struct kbisim_ctx {
     u32 *touch;  // bitmap of the cached blocks (by minimum vertex) that can change in this step
     int *lk;               // the dirty vertices, then these and the clean members of touched blocks
     u32 *filter;           // bit filter of the dirty keys
+    u32 *gfilter;          // the larger global filter (GFILTER_BITS) used with many dirty keys
     // edited rows longer than LIST_BIG: one global set each (chunks of HUB_GCHUNK)
     int *huge;
     HubGChunk *huge_chunks;
@@ -1381,7 +1383,7 @@ int refine_impl(kbisim_ctx *c, const int32_t *start, int k, int32_t *const *out,
 struct IncrPlan {
   size_t off_hc, off_dcc, off_mvc, off_fk, off_tptr, off_tcol, off_names, off_edited, off_flag, off_dirty, off_skip,
       off_small, off_large, off_psmall, off_plarge, off_changed, off_bname, off_keep, off_claimed, off_heavy, off_touch,
-      off_lk, off_filter, off_zrep, off_huge, off_hchunks, off_hacc, off_hcnt, off_erows, off_cnt, total;
+      off_lk, off_filter, off_gfilter, off_zrep, off_huge, off_hchunks, off_hacc, off_hcnt, off_erows, off_cnt, total;
   int64_t huge_cap, huge_chunk_cap;
 };
 IncrPlan incr_plan(int64_t n, int64_t m, int kmax) {
@@ -1416,6 +1418,7 @@ IncrPlan incr_plan(int64_t n, int64_t m, int kmax) {
   p.off_touch = take(4 * (N / 32 + 1));
   p.off_lk = take(4 * N);
   p.off_filter = take(4 * FILTER_WORDS);
+  p.off_gfilter = take(4 * (size_t)GFILTER_WORDS);
   p.off_zrep = take(16 * N);
   p.huge_cap = std::max<int64_t>(m, 0) / LIST_BIG + 1;
   p.huge_chunk_cap = std::max<int64_t>(m, 0) / HUB_GCHUNK + p.huge_cap + 1;
@@ -1510,15 +1513,17 @@ int update_step(kbisim_ctx *c, const TierSrc &tsrc, const ListSrc &lsrc, int i, 
     // touched blocks: the cached blocks of dirty vertices (k_update_flags) and
     // those whose key a dirty vertex now has (k_classify)
     if ((rc = fill_i32(c, (int *)S.filter, FILTER_WORDS, 0))) return rc;
+    u32 *gfilter = ndirty >= c->tune.gfilter_min ? S.gfilter : nullptr;
+    if (gfilter && (rc = fill_i32(c, (int *)gfilter, GFILTER_WORDS, 0))) return rc;
     if (ndirty > 0) {
       // the dirty vertices were listed by k_update_flags (count at cnt[12])
       k_build_filter<<<blocks_for(ndirty, 256), 256, 0, c->stream>>>(&cnt[12], S.lk, c->H, c->DC, names_prev,
-                                                                      S.MVc + at, S.filter);
+                                                                      S.MVc + at, S.filter, gfilter);
       LAUNCH_CHECK();
     }
     k_classify<<<(unsigned)std::min<int64_t>(CLASSIFY_GRID, blocks_for(n, 256)), 256, 0, c->stream>>>(
-        n, S.MVc + at, S.dirty, S.touch, S.FKc + at, S.Hc + at, S.DCc + at, names_prev, S.filter, c->table, tmask,
-        c->dep, c->zrep, c->H, c->DC, c->rep, S.names[i & 1], &cnt[11], S.lk);
+        n, S.MVc + at, S.dirty, S.touch, S.FKc + at, S.Hc + at, S.DCc + at, names_prev, S.filter, gfilter, c->table,
+        tmask, c->dep, c->zrep, c->H, c->DC, c->rep, S.names[i & 1], &cnt[11], S.lk);
     LAUNCH_CHECK();
     HIP_TRY(hipMemcpyAsync(&nlk, &cnt[11], sizeof nlk, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
@@ -1815,6 +1820,7 @@ int incr_enable_impl(kbisim_ctx *c, void *state, size_t bytes) {
   S.touch = (u32 *)(w + p.off_touch);
   S.lk = (int *)(w + p.off_lk);
   S.filter = (u32 *)(w + p.off_filter);
+  S.gfilter = (u32 *)(w + p.off_gfilter);
   S.huge = (int *)(w + p.off_huge);
   S.huge_chunks = (HubGChunk *)(w + p.off_hchunks);
   S.huge_acc = (u64 *)(w + p.off_hacc);
@@ -1999,6 +2005,13 @@ int create_impl(const kbisim_graph *g, int kmax, const kbisim_tuning *tuning, vo
   if (kdbg && *kdbg) {
     int b = atoi(kdbg);
     if (b >= 1 && b < 32) c->kmask = (1u << b) - 1u;
+  }
+  // Test knob: update steps use the global dirty-key filter from this many
+  // dirty vertices on (at least 1), so that small graphs take that path.
+  const char *gdbg = getenv("KBISIM_DEBUG_GFILTER_MIN");
+  if (gdbg && *gdbg) {
+    int q = atoi(gdbg);
+    if (q >= 1) c->tune.gfilter_min = q;
   }
 
   auto fail = [&](int code) {

@@ -325,6 +325,30 @@ __device__ inline void wave_append(int *counter, int *list, bool pred, int item)
   }
 }
 
+// Append v0 + j for every bit j of each lane's mask to list[*counter], one
+// atomic per wave.  Must be called by the whole wave.
+__device__ inline void wave_append_mask(int *counter, int *list, u32 mask, int64_t v0) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const u32 c = (u32)__popc(mask);
+  u32 x = c;
+#pragma unroll
+  for (int o = 1; o < WAVE; o <<= 1) {
+    const u32 y = __shfl_up(x, o, WAVE);
+    if (lane >= o) x += y;
+  }
+  const u32 total = __shfl(x, WAVE - 1, WAVE);
+  if (total == 0) return;
+  int base = 0;
+  if (lane == WAVE - 1) base = atomicAdd(counter, (int)total);
+  base = __shfl(base, WAVE - 1, WAVE);
+  int at = base + (int)(x - c);
+  while (mask) {
+    const int j = __ffs(mask) - 1;
+    list[at++] = (int)(v0 + j);
+    mask &= mask - 1u;
+  }
+}
+
 // ---------------------------------------------------------------- grouping table
 // Open addressing with linear probing.  Slot = (tag << 32) | vertex, tag =
 // 28 hash bits above bit 36 plus a 4-bit epoch (1..15).  A slot whose epoch is
@@ -2534,6 +2558,17 @@ constexpr int CLASSIFY_GRID = 2048;
 __device__ inline u32 filter_key_bit(u64 h) { return (u32)(h >> 36) & (FILTER_BITS - 1); }
 __device__ inline u32 filter_name_bit(u32 name) { return (name * 0x9E3779B1u) >> 16; }
 __device__ inline u32 filter_touch_bit(u32 head) { return (head * 0x85EBCA6Bu) >> 16; }
+// With many dirty keys the LDS filter fills up; a second, global filter of
+// GFILTER_BITS bits (16 MB, held in the L2 and MALL) then keeps most clean
+// vertices from a table probe in HBM.  Its key bits come from other hash bits
+// than the LDS filter's.
+constexpr int64_t GFILTER_BITS = int64_t(1) << 27;
+constexpr int64_t GFILTER_WORDS = GFILTER_BITS / 32;
+constexpr int GFILTER_MIN_DIRTY = FILTER_BITS / 16;  // fewer dirty keys: the LDS filter suffices
+__device__ inline u32 gfilter_key_bit(u64 h) { return (u32)h & (u32)(GFILTER_BITS - 1); }
+__device__ inline u32 gfilter_name_bit(u32 name) {
+  return (u32)(((u64)name * 0x9E3779B97F4A7C15ull) >> 37) & (u32)(GFILTER_BITS - 1);
+}
 
 // Filter bit of every vertex's key at one step of a cached chain.
 __global__ void k_filter_keys(int n, const u64 *__restrict__ H, const u32 *__restrict__ DC,
@@ -2543,16 +2578,25 @@ __global__ void k_filter_keys(int n, const u64 *__restrict__ H, const u32 *__res
   fk[v] = (uint16_t)(DC[v] ? filter_key_bit(H[v]) : filter_name_bit((u32)names_prev[v]));
 }
 
+// gfilter: the global filter (cleared), or null.
 __global__ void k_build_filter(const int *__restrict__ count, const int *__restrict__ dlist,
                                const u64 *__restrict__ H, const u32 *__restrict__ DC,
-                               const int32_t *__restrict__ names, const int32_t *__restrict__ mvc, u32 *filter) {
+                               const int32_t *__restrict__ names, const int32_t *__restrict__ mvc, u32 *filter,
+                               u32 *gfilter) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= *count) return;
   const int d = dlist[i];
-  const u32 b = DC[d] ? filter_key_bit(H[d]) : filter_name_bit((u32)names[d]);
+  const u32 dc = DC[d];
+  const u64 h = dc ? H[d] : 0ull;
+  const u32 nm = (u32)names[d];
+  const u32 b = dc ? filter_key_bit(h) : filter_name_bit(nm);
   atomicOr(&filter[b >> 5], 1u << (b & 31));
   const u32 t = filter_touch_bit((u32)mvc[d]);
   atomicOr(&filter[t >> 5], 1u << (t & 31));
+  if (gfilter) {
+    const u32 g = dc ? gfilter_key_bit(h) : gfilter_name_bit(nm);
+    atomicOr(&gfilter[g >> 5], 1u << (g & 31));
+  }
 }
 
 __global__ void __launch_bounds__(256) k_classify(int n, const int32_t *__restrict__ mvc,
@@ -2560,7 +2604,8 @@ __global__ void __launch_bounds__(256) k_classify(int n, const int32_t *__restri
                                                   const u32 *__restrict__ touch,
                                                   const uint16_t *__restrict__ fkc, const u64 *__restrict__ Hc,
                                                   const u32 *__restrict__ DCc, const int32_t *__restrict__ names,
-                                                  const u32 *__restrict__ filter, const u64 *table, u64 tmask,
+                                                  const u32 *__restrict__ filter,
+                                                  const u32 *__restrict__ gfilter, const u64 *table, u64 tmask,
                                                   const u32 *__restrict__ dep, const u64 *__restrict__ zrep,
                                                   u64 *__restrict__ H, u32 *__restrict__ DC, int *__restrict__ rep,
                                                   int32_t *__restrict__ names_out, int *count, int *list) {
@@ -2579,8 +2624,14 @@ __global__ void __launch_bounds__(256) k_classify(int n, const int32_t *__restri
   const bool vec = ((reinterpret_cast<uintptr_t>(mvc) | reinterpret_cast<uintptr_t>(rep) |
                      reinterpret_cast<uintptr_t>(names_out)) & 15) == 0 &&
                    (reinterpret_cast<uintptr_t>(fkc) & 7) == 0 && (reinterpret_cast<uintptr_t>(dirty) & 3) == 0;
+  // the list is appended with one atomic per workgroup and round (with many
+  // dirty keys most vertices are listed, and per-wave atomics on the one
+  // counter would serialise)
+  __shared__ u32 sh_w[4];
+  __shared__ int sh_base;
   const int64_t stride = (int64_t)gridDim.x * 256 * CV;
-  for (int64_t v0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * CV; v0 < n; v0 += stride) {
+  for (int64_t b0 = (int64_t)blockIdx.x * 256 * CV; b0 < n; b0 += stride) {  // uniform in the workgroup
+    const int64_t v0 = b0 + (int64_t)threadIdx.x * CV;
     int hd[CV];
     u32 fk[CV], dv[CV];
     const bool full = vec && v0 + CV <= n;
@@ -2634,24 +2685,45 @@ __global__ void __launch_bounds__(256) k_classify(int n, const int32_t *__restri
       dc[j] = need[j] ? DCc[v0 + j] : 0u;
       hv[j] = need[j] ? Hc[v0 + j] : 0ull;
     }
+    bool listed[CV];
 #pragma unroll
     for (int j = 0; j < CV; ++j) {
       const int v = (int)(v0 + j);
-      bool listed = v0 + j < n && dv[j];
+      listed[j] = v0 + j < n && dv[j];
       if (need[j]) {
         bool hit = !probe[j];  // touched
         if (probe[j]) {
-          if (dc[j] == 0) hit = (u32)(zrep[(u32)names[v]] >> 32) == ~zep;
-          else hit = table_lookup(table, tmask, hv[j], epoch) >= 0;
+          const u32 nm = dc[j] == 0 ? (u32)names[v] : 0u;
+          bool maybe = true;
+          if (gfilter) {
+            const u32 g = dc[j] ? gfilter_key_bit(hv[j]) : gfilter_name_bit(nm);
+            maybe = (gfilter[g >> 5] >> (g & 31)) & 1u;
+          }
+          if (maybe) {
+            if (dc[j] == 0) hit = (u32)(zrep[nm] >> 32) == ~zep;
+            else hit = table_lookup(table, tmask, hv[j], epoch) >= 0;
+          }
         }
         if (hit) {
           H[v] = hv[j];
           DC[v] = dc[j];
-          listed = true;
+          listed[j] = true;
         }
       }
-      wave_append(count, list, listed, v);
     }
+    u32 mine = 0;
+#pragma unroll
+    for (int j = 0; j < CV; ++j) mine += listed[j] ? 1u : 0u;
+    if (!__syncthreads_or(mine != 0)) continue;  // most rounds with few dirty keys
+    u32 total;
+    u32 at = block_exclusive_scan(mine, sh_w, &total);
+    if (threadIdx.x == 0) sh_base = atomicAdd(count, (int)total);
+    __syncthreads();
+    const int base = sh_base;
+#pragma unroll
+    for (int j = 0; j < CV; ++j)
+      if (listed[j]) list[base + (int)at++] = (int)(v0 + j);
+    __syncthreads();  // sh_base is rewritten in the next round
   }
 }
 
@@ -2838,29 +2910,33 @@ __global__ void __launch_bounds__(256) k_update_flags(int n, const unsigned char
     slow = v0 < n;
   }
   if (!__ballot(slow)) return;
-  for (int j = 0; j < FLAGS_GROUP; ++j) {
-    const int v = (int)(v0 + j);
-    const bool act = slow && v0 + j < n;
-    bool prop = false, dv = false;
-    int64_t d = 0;
-    if (act) {
+  // the group's members of each list as bit masks, appended once per wave
+  u32 msmall = 0, mlarge = 0, mdirty = 0, nbig = 0;
+  if (slow) {
+    for (int j = 0; j < FLAGS_GROUP; ++j) {
+      const int64_t v = v0 + j;
+      if (v >= n) break;
       const bool ed = edited[v] != 0, fl = flag[v] != 0;
-      dv = ed || fl;
+      const bool dv = ed || fl;
       dirty[v] = dv ? 1 : 0;
       if (dv) {
         const int h = mvc[v];
         atomicOr(&touch[h >> 5], 1u << (h & 31));
+        mdirty |= 1u << j;
       }
-      prop = fl && !ed;
-      if (prop) d = row_ptr[v + 1] - row_ptr[v];
+      const bool prop = fl && !ed;
+      const int64_t d = prop ? row_ptr[v + 1] - row_ptr[v] : 0;
       skip[v] = (prop && d > LIST_BIG) ? 0 : 1;
+      if (prop && d <= LIST_SMALL) msmall |= 1u << j;
+      else if (prop && d <= LIST_BIG) mlarge |= 1u << j;
+      else if (prop) ++nbig;
     }
-    wave_append(&cnt[0], small, prop && d <= LIST_SMALL, v);
-    wave_append(&cnt[1], large, prop && d > LIST_SMALL && d <= LIST_BIG, v);
-    wave_append(&cnt[4], dlist, dv, v);
-    const u64 big = __ballot(prop && d > LIST_BIG);
-    if ((threadIdx.x & (WAVE - 1)) == 0 && big) atomicAdd(&cnt[2], (int)__popcll(big));
   }
+  wave_append_mask(&cnt[0], small, msmall, v0);
+  wave_append_mask(&cnt[1], large, mlarge, v0);
+  wave_append_mask(&cnt[4], dlist, mdirty, v0);
+  nbig = wave_sum_u32(nbig);
+  if ((threadIdx.x & (WAVE - 1)) == 0 && nbig) atomicAdd(&cnt[2], (int)nbig);
 }
 
 // Skip flags when every flagged unedited vertex goes to the tier kernels.

@@ -140,6 +140,22 @@ def test_update_equals_refine_from_scratch(name):
         c.close()
 
 
+@pytest.mark.parametrize("name", ["tiny", "rmat", "rdf"])
+def test_update_with_global_dirty_filter(name, monkeypatch):
+    """The global filter of dirty keys (taken with many dirty vertices) forced on every list
+    step: clean vertices whose key or name bit is set there probe the table, the others not."""
+    monkeypatch.setenv("KBISIM_DEBUG_GFILTER_MIN", "1")
+    g = GRAPHS[name]()
+    c = Cached(g, 6)
+    rng = np.random.default_rng(51)
+    try:
+        for n_del, n_ins in [(1, 0), (0, 1), (50, 50), (400, 400)]:
+            g2, rows = edited(g, rng, n_del, n_ins)
+            check_update(c, g2, rows, f"{name} gfilter -{n_del}+{n_ins}")
+    finally:
+        c.close()
+
+
 def test_rows_emptied_filled_and_a_hub_row():
     g = graphgen.rmat(13, 150_000, seed=9)
     deg = np.diff(g.row_ptr)
