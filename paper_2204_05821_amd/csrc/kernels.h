@@ -2889,53 +2889,73 @@ __global__ void __launch_bounds__(256) k_update_flags(int n, const unsigned char
                                                       const int64_t *__restrict__ row_ptr, int *cnt, int *small,
                                                       int *large, const int32_t *__restrict__ mvc,
                                                       u32 *__restrict__ touch, int *dlist) {
-  // FLAGS_GROUP vertices per thread.  Most groups are clean (no byte set in
-  // either input): one 16-byte load of each and one 16-byte store of each
-  // output.  A wave with a vertex to list takes them one by one (the lists are
-  // appended to wave-wide, so every lane of such a wave walks its group).
+  // FLAGS_GROUP vertices per thread, their bytes moved 16 at a time where the
+  // arrays allow.  Most groups are clean (no byte set in either input): one
+  // load and one store of each array.  A group with a set byte decides per
+  // vertex; its list members are appended once per wave (bit masks).
   const int64_t v0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * FLAGS_GROUP;
-  const bool vec = ((reinterpret_cast<uintptr_t>(edited) | reinterpret_cast<uintptr_t>(flag) |
+  const bool vec = v0 + FLAGS_GROUP <= n &&
+                   ((reinterpret_cast<uintptr_t>(edited) | reinterpret_cast<uintptr_t>(flag) |
                      reinterpret_cast<uintptr_t>(dirty) | reinterpret_cast<uintptr_t>(skip)) & 15) == 0;
-  bool slow = false;
-  if (vec && v0 + FLAGS_GROUP <= n) {
+  u32 eb = 0, fb = 0;  // bit j: vertex v0 + j edited / flagged
+  if (vec) {
     const u32x4 e = *reinterpret_cast<const u32x4 *>(edited + v0);
     const u32x4 f = *reinterpret_cast<const u32x4 *>(flag + v0);
-    const u32x4 o = e | f;
-    slow = (o.x | o.y | o.z | o.w) != 0;
-    if (!slow) {
-      *reinterpret_cast<u32x4 *>(dirty + v0) = u32x4{0u, 0u, 0u, 0u};
-      *reinterpret_cast<u32x4 *>(skip + v0) = u32x4{0x01010101u, 0x01010101u, 0x01010101u, 0x01010101u};
+#pragma unroll
+    for (int j = 0; j < FLAGS_GROUP; ++j) {
+      const u32 sh = 8 * (j & 3);
+      const u32 ew = j < 4 ? e.x : j < 8 ? e.y : j < 12 ? e.z : e.w;
+      const u32 fw = j < 4 ? f.x : j < 8 ? f.y : j < 12 ? f.z : f.w;
+      eb |= (((ew >> sh) & 0xffu) != 0u ? 1u : 0u) << j;
+      fb |= (((fw >> sh) & 0xffu) != 0u ? 1u : 0u) << j;
     }
   } else {
-    slow = v0 < n;
-  }
-  if (!__ballot(slow)) return;
-  // the group's members of each list as bit masks, appended once per wave
-  u32 msmall = 0, mlarge = 0, mdirty = 0, nbig = 0;
-  if (slow) {
-    for (int j = 0; j < FLAGS_GROUP; ++j) {
-      const int64_t v = v0 + j;
-      if (v >= n) break;
-      const bool ed = edited[v] != 0, fl = flag[v] != 0;
-      const bool dv = ed || fl;
-      dirty[v] = dv ? 1 : 0;
-      if (dv) {
-        const int h = mvc[v];
-        atomicOr(&touch[h >> 5], 1u << (h & 31));
-        mdirty |= 1u << j;
-      }
-      const bool prop = fl && !ed;
-      const int64_t d = prop ? row_ptr[v + 1] - row_ptr[v] : 0;
-      skip[v] = (prop && d > LIST_BIG) ? 0 : 1;
-      if (prop && d <= LIST_SMALL) msmall |= 1u << j;
-      else if (prop && d <= LIST_BIG) mlarge |= 1u << j;
-      else if (prop) ++nbig;
+    for (int j = 0; j < FLAGS_GROUP && v0 + j < n; ++j) {
+      eb |= (edited[v0 + j] != 0 ? 1u : 0u) << j;
+      fb |= (flag[v0 + j] != 0 ? 1u : 0u) << j;
     }
   }
+  const u32 mdirty = eb | fb, mprop = fb & ~eb;
+  // row lengths of the flagged unedited vertices, all requested together
+  int64_t d[FLAGS_GROUP];
+#pragma unroll
+  for (int j = 0; j < FLAGS_GROUP; ++j) d[j] = (mprop >> j) & 1u ? row_ptr[v0 + j + 1] - row_ptr[v0 + j] : 0;
+  u32 msmall = 0, mlarge = 0, mbig = 0;
+#pragma unroll
+  for (int j = 0; j < FLAGS_GROUP; ++j) {
+    if (!((mprop >> j) & 1u)) continue;
+    if (d[j] <= LIST_SMALL) msmall |= 1u << j;
+    else if (d[j] <= LIST_BIG) mlarge |= 1u << j;
+    else mbig |= 1u << j;
+  }
+  // dirty = edited or flagged; skip = all but the flagged unedited rows past LIST_BIG
+  if (vec) {
+    u32 dw[4] = {0u, 0u, 0u, 0u}, sw[4] = {0x01010101u, 0x01010101u, 0x01010101u, 0x01010101u};
+#pragma unroll
+    for (int j = 0; j < FLAGS_GROUP; ++j) {
+      dw[j >> 2] |= ((mdirty >> j) & 1u) << (8 * (j & 3));
+      sw[j >> 2] &= ~(((mbig >> j) & 1u) << (8 * (j & 3)));
+    }
+    *reinterpret_cast<u32x4 *>(dirty + v0) = u32x4{dw[0], dw[1], dw[2], dw[3]};
+    *reinterpret_cast<u32x4 *>(skip + v0) = u32x4{sw[0], sw[1], sw[2], sw[3]};
+  } else {
+    for (int j = 0; j < FLAGS_GROUP && v0 + j < n; ++j) {
+      dirty[v0 + j] = (mdirty >> j) & 1u;
+      skip[v0 + j] = ((mbig >> j) & 1u) ? 0 : 1;
+    }
+  }
+  // touch: the cached block of every dirty vertex (many share one: set its bit once)
+  for (u32 m = mdirty; m; m &= m - 1u) {
+    const int h = mvc[v0 + __ffs(m) - 1];
+    const u32 bit = 1u << (h & 31);
+    if (!(__hip_atomic_load(&touch[h >> 5], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & bit))
+      atomicOr(&touch[h >> 5], bit);
+  }
+  if (!__ballot(mdirty != 0)) return;
   wave_append_mask(&cnt[0], small, msmall, v0);
   wave_append_mask(&cnt[1], large, mlarge, v0);
   wave_append_mask(&cnt[4], dlist, mdirty, v0);
-  nbig = wave_sum_u32(nbig);
+  const u32 nbig = wave_sum_u32((u32)__popc(mbig));
   if ((threadIdx.x & (WAVE - 1)) == 0 && nbig) atomicAdd(&cnt[2], (int)nbig);
 }
 
