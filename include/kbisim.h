@@ -97,7 +97,7 @@ typedef struct kbisim_ctx kbisim_ctx;
  *                    keys always; 64 = exact 64-bit keys always.  With hashed
  *                    keys the signature is deduplicated by key and every
  *                    grouping is still confirmed on the pairs themselves.
- *   scan_items       vertices per thread in the numbering scan: 8 or 16
+ *   scan_items       vertices per thread in the numbering (head words): 8 or 16
  *                    (default)                                                */
 typedef struct {
   int range_edges;
