@@ -2616,10 +2616,10 @@ __global__ void __launch_bounds__(256) k_classify(int n, const int32_t *__restri
   // CV consecutive vertices per thread and round, read and written 4 at a
   // time when every array's start allows (a step's slice of the chain starts
   // at step * n, so with n not a multiple of 4 they are read one by one).
-  // Every vertex first gets its
-  // cached block as representative and name; a listed vertex's are
-  // overwritten by the lookup and naming kernels of the step.  The cached key
-  // itself is read only by vertices that pass the touch or filter test.
+  // Every vertex first gets its cached block as representative and name; a
+  // listed vertex's are overwritten by the lookup and naming kernels of the
+  // step.  The cached key itself is read only by vertices that pass the touch
+  // or filter test.
   constexpr int CV = 4;
   const bool vec = ((reinterpret_cast<uintptr_t>(mvc) | reinterpret_cast<uintptr_t>(rep) |
                      reinterpret_cast<uintptr_t>(names_out)) & 15) == 0 &&
