@@ -156,6 +156,36 @@ def test_update_with_global_dirty_filter(name, monkeypatch):
         c.close()
 
 
+def test_outputs_off_16_byte_boundaries():
+    """Output tensors that start 4, 8 or 12 bytes past a 16-byte boundary (views into one
+    buffer): the per-vertex passes and the fixpoint copies then write them one id at a time;
+    refine and update results equal those into fresh tensors."""
+    g = GRAPHS["rmat"]()
+    k = 6
+    c = Cached(g, k)
+    rng = np.random.default_rng(61)
+    try:
+        g2, rows = edited(g, rng, 20, 20)
+        exp, ec = c.update(g2, rows)
+        buf = torch.empty(k * g.n + 16, dtype=torch.int32, device="cuda")
+        for off in (1, 2, 3):
+            outs = [buf[off + i * g.n: off + (i + 1) * g.n] for i in range(k)]
+            ids, counts = c.r.refine(k, out=outs)
+            assert counts == c.base_counts
+            for a, b in zip(ids, c.base_ids):
+                assert bool((a == b).all())
+            rp = torch.from_numpy(g2.row_ptr).cuda()
+            col = torch.from_numpy(g2.col).cuda()
+            el = torch.from_numpy(g2.elabel).cuda()
+            rw = torch.from_numpy(np.asarray(rows, dtype=np.int32)).cuda()
+            ids2, counts2 = c.r.update(rp, col, el, rw, k, out=outs)
+            assert counts2 == ec
+            for a, b in zip(ids2, exp):
+                assert np.array_equal(a.cpu().numpy(), b), off
+    finally:
+        c.close()
+
+
 def test_rows_emptied_filled_and_a_hub_row():
     g = graphgen.rmat(13, 150_000, seed=9)
     deg = np.diff(g.row_ptr)
